@@ -1,0 +1,258 @@
+"""Seeded synthetic inputs shared by the oracle-side tests and the HIP path.
+
+This module draws random numbers and lays out initial density fields; it holds
+none of the model's arithmetic.  Everything thermodynamic (critical constants,
+bubble/dew points, flashes, volatility coefficients) is delegated to a `backend`
+object passed in by the caller, so each side supplies its own implementation:
+
+    backend.critical_temperature(mix)           -> Tc[nc]
+    backend.bubble_pressure(mix, T, z)          -> p
+    backend.dew_pressure(mix, T, z)             -> p
+    backend.flash(mix, T, p, z)                 -> object with .rbar_l, .rbar_v,
+                                                   .gamma, .x, .y (raises on one phase)
+
+`mix` is a plain dict {"a", "b", "omega", "M", "k", "R"} of float64 arrays.
+
+Initial-condition recipes (Sec. 4 of the paper):
+  * drop:  rbar_i = (l_i + v_i)/2 - (l_i - v_i)/2 tanh(2 (r - R0)/W), the sign of
+           Eq. (initialden); the printed drop formulas of Sec. 4.3 carry a '+' that
+           would put vapor inside the drop, contrary to their text, so the sign of
+           Eq. (initialden) is used for all drops.
+  * slab:  a liquid slab centred in y with two tanh interfaces of width D
+           (the two-interface layout of Eq. (initialdensity), along y).
+  * noise: multiplicative, rbar <- rbar (1 + amp U[-1, 1]), per cell and component.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+SEED = 1909_12390
+LB_A = 2.0 / 49.0      # lattice-unit attraction parameter of Sec. 4.1 / 4.2 scaling
+LB_B = 2.0 / 21.0      # lattice-unit co-volume parameter
+
+
+def rng_for(config_id: int, *extra: int) -> np.random.Generator:
+    return np.random.default_rng([SEED, int(config_id), *[int(e) for e in extra]])
+
+
+# ---------------------------------------------------------------------------
+# raw random draws
+# ---------------------------------------------------------------------------
+
+def draw_components(rng, nc, a_range=(0.8, 1.5), b_range=(0.9, 1.2),
+                    omega_range=(0.01, 0.3), k_max=0.05, R=1.0):
+    """Component parameters in lattice units: a = (2/49) U[a_range], b = (2/21) U[b_range],
+    omega ~ U[omega_range], symmetric k_ij ~ U[0, k_max] (zero diagonal), molar mass
+    proportional to the co-volume, M_i = b_i / (2/21)."""
+    a = LB_A * rng.uniform(*a_range, size=nc)
+    b = LB_B * rng.uniform(*b_range, size=nc)
+    omega = rng.uniform(*omega_range, size=nc)
+    k = np.zeros((nc, nc))
+    for i in range(nc):
+        for j in range(i + 1, nc):
+            k[i, j] = k[j, i] = rng.uniform(0.0, k_max)
+    M = b / LB_B
+    return {"a": a, "b": b, "omega": omega, "M": M, "k": k, "R": float(R)}
+
+
+def draw_composition(rng, nc, zmin=0.05):
+    """Overall mole fractions uniform on the simplex (Dirichlet(1,...,1)), redrawn
+    until every z_i >= zmin."""
+    while True:
+        z = rng.dirichlet(np.ones(nc))
+        if z.min() >= zmin:
+            return z
+
+
+def multiplicative_noise(rng, shape, amp):
+    return 1.0 + amp * rng.uniform(-1.0, 1.0, size=shape)
+
+
+# ---------------------------------------------------------------------------
+# geometry
+# ---------------------------------------------------------------------------
+
+def coords(shape):
+    """Cell-centre coordinates (x, y[, z]) for an array of shape (ny, nx) or (nz, ny, nx)."""
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    return grids[::-1]
+
+
+def drop_profile(shape, R0, W, inner, outer, center=None, h=1.0):
+    """tanh drop of radius R0 (interface width W) centred in the box; `inner` and
+    `outer` are per-component values inside and outside; h squeezes y (ellipse)."""
+    xs = coords(shape)
+    if center is None:
+        center = [n / 2.0 for n in shape[::-1]]
+    r2 = np.zeros(shape)
+    for d, xd in enumerate(xs):
+        dd = xd - center[d]
+        if d == 1:
+            dd = dd / h
+        r2 = r2 + dd * dd
+    r = np.sqrt(r2)
+    inner = np.asarray(inner, dtype=np.float64)
+    outer = np.asarray(outer, dtype=np.float64)
+    t = np.tanh(2.0 * (r - R0) / W)
+    return (0.5 * (inner + outer)[:, None] - 0.5 * (inner - outer)[:, None] * t.reshape(1, -1)).reshape(
+        (inner.shape[0],) + tuple(shape))
+
+
+def slab_profile(shape, half_thickness, D, inner, outer):
+    """Liquid slab centred in y: |y - yc| < half_thickness is liquid, tanh interfaces
+    of width D (Eq. (initialdensity) laid along y, both interfaces)."""
+    xs = coords(shape)
+    y = xs[1]
+    yc = shape[-2] / 2.0
+    dist = np.abs(y - yc) - half_thickness
+    t = np.tanh(2.0 * dist / D)
+    inner = np.asarray(inner, dtype=np.float64)
+    outer = np.asarray(outer, dtype=np.float64)
+    return (0.5 * (inner + outer)[:, None] - 0.5 * (inner - outer)[:, None] * t.reshape(1, -1)).reshape(
+        (inner.shape[0],) + tuple(shape))
+
+
+# ---------------------------------------------------------------------------
+# configurations
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Config:
+    name: str
+    lattice: str                 # "D2Q9" | "D3Q19"
+    shape: tuple                 # (ny, nx) or (nz, ny, nx)
+    mix: dict
+    T: float
+    p_star: float
+    z: np.ndarray
+    gamma: np.ndarray
+    rbar_l: np.ndarray
+    rbar_v: np.ndarray
+    rho0: np.ndarray             # (nc, *shape) initial cell-volume densities
+    collision: str
+    forcing: str
+    tau: float = 0.8
+    beta: float = 1.945
+    G: float = -1.0
+    steps: int = 1000
+    mrt_s: Optional[np.ndarray] = None
+    geometry: dict = field(default_factory=dict)
+
+    @property
+    def nc(self):
+        return int(self.mix["a"].shape[0])
+
+    @property
+    def cells(self):
+        return int(np.prod(self.shape))
+
+
+def default_mrt_rates(lattice: str, tau: float):
+    """Relaxation rates per moment row: shear (nu) and component momentum (j) relax
+    at 1/tau, the rest at 1.0 (rate of the conserved density row is irrelevant)."""
+    if lattice == "D2Q9":
+        kinds = ["rho", "e", "eps", "j", "q", "j", "q", "nu", "nu"]
+    else:
+        kinds = ["rho", "e", "eps", "j", "q", "j", "q", "j", "q",
+                 "nu", "pi", "nu", "pi", "nu", "nu", "nu", "m", "m", "m"]
+    return np.array([1.0 / tau if k in ("nu", "j") else 1.0 for k in kinds])
+
+
+def _pick_state(rng, backend, nc, t_lo, t_hi, k_max, comp_kwargs, z=None,
+                exactly_one_supercritical=False, max_draws=200):
+    """Draw components, T and z until the mixture splits into two phases at
+    p* = (p_bub + p_dew)/2 with every gamma in (0, 1]."""
+    for _ in range(max_draws):
+        mix = draw_components(rng, nc, k_max=k_max, **comp_kwargs)
+        zz = draw_composition(rng, nc) if z is None else np.asarray(z, dtype=np.float64)
+        u = rng.uniform()
+        Tc = np.asarray(backend.critical_temperature(mix))
+        lo, hi = t_lo * Tc.max(), t_hi * Tc.min()
+        if not lo < hi:
+            continue
+        T = lo + u * (hi - lo)
+        if exactly_one_supercritical and int(np.sum(T > Tc)) != 1:
+            continue
+        try:
+            pb = backend.bubble_pressure(mix, T, zz)
+            pd = backend.dew_pressure(mix, T, zz)
+            if not (np.isfinite(pb) and np.isfinite(pd)) or pb <= pd * (1 + 1e-6):
+                continue
+            p = 0.5 * (pb + pd)
+            fl = backend.flash(mix, T, p, zz)
+        except Exception:
+            continue
+        g = np.asarray(fl.gamma)
+        if np.all(g > 0.0) and np.all(g <= 1.0 + 1e-12) and np.all(np.isfinite(g)):
+            return mix, T, zz, p, fl
+    raise RuntimeError("no two-phase state found")
+
+
+def config_c1(backend, shape=(64, 64), R0=16.0, noise=1e-3) -> Config:
+    """Binary D2Q9 drop (radius 16 in 64x64), BGK + exact-difference forcing, FP64."""
+    rng = rng_for(1)
+    mix, T, z, p, fl = _pick_state(rng, backend, 2, 0.7, 0.95, 0.05, {}, z=[0.5, 0.5])
+    rho0 = drop_profile(shape, R0, 4.0, fl.rbar_l, fl.rbar_v)
+    rho0 = rho0 * multiplicative_noise(rng_for(1, 1), rho0.shape, noise)
+    return Config("C1", "D2Q9", tuple(shape), mix, T, p, z, np.asarray(fl.gamma), np.asarray(fl.rbar_l),
+                  np.asarray(fl.rbar_v), rho0, "bgk", "edm", steps=1000,
+                  geometry={"kind": "drop", "R0": R0})
+
+
+def config_c2(backend, shape=(256, 256)) -> Config:
+    """Ternary D2Q9 slab of half the height, MRT + exact-difference forcing."""
+    rng = rng_for(2)
+    mix, T, z, p, fl = _pick_state(rng, backend, 3, 0.65, 0.95, 0.05, {})
+    H = shape[0] / 4.0
+    rho0 = slab_profile(shape, H, 8.0, fl.rbar_l, fl.rbar_v)
+    return Config("C2", "D2Q9", tuple(shape), mix, T, p, z, np.asarray(fl.gamma), np.asarray(fl.rbar_l),
+                  np.asarray(fl.rbar_v), rho0, "mrt", "edm", steps=20000,
+                  mrt_s=default_mrt_rates("D2Q9", 0.8), geometry={"kind": "slab", "half": H})
+
+
+def config_c3(backend, shape=(128, 128, 128), R0=32.0) -> Config:
+    """Four-component D3Q19 drop (radius 32 in 128^3), one supercritical component,
+    MRT + exact-difference forcing."""
+    rng = rng_for(3)
+    mix, T, z, p, fl = _pick_state(rng, backend, 4, 0.6, 1.05, 0.08, {},
+                                   exactly_one_supercritical=True)
+    rho0 = drop_profile(shape, R0, 4.0, fl.rbar_l, fl.rbar_v)
+    return Config("C3", "D3Q19", tuple(shape), mix, T, p, z, np.asarray(fl.gamma), np.asarray(fl.rbar_l),
+                  np.asarray(fl.rbar_v), rho0, "mrt", "edm", steps=5000,
+                  mrt_s=default_mrt_rates("D3Q19", 0.8), geometry={"kind": "drop", "R0": R0})
+
+
+def config_c5(backend, shape=(128, 128), R0=32.0) -> Config:
+    """Ternary D2Q9 drop for the adjoint case (BGK + exact-difference forcing)."""
+    rng = rng_for(5)
+    mix, T, z, p, fl = _pick_state(rng, backend, 3, 0.7, 0.95, 0.05, {})
+    rho0 = drop_profile(shape, R0, 4.0, fl.rbar_l, fl.rbar_v)
+    return Config("C5", "D2Q9", tuple(shape), mix, T, p, z, np.asarray(fl.gamma), np.asarray(fl.rbar_l),
+                  np.asarray(fl.rbar_v), rho0, "bgk", "edm", steps=2000,
+                  geometry={"kind": "drop", "R0": R0})
+
+
+BOX_SIDES = (32, 48, 64, 96, 128)
+
+
+def config_c4_boxes(backend, nboxes=512) -> List[Config]:
+    """Batched sweep: independent binary or ternary D2Q9 boxes, sides drawn from
+    {32, 48, 64, 96, 128}, each with its own T (T/Tc in [0.6, 0.98]) and composition;
+    a centred drop of radius min(nx, ny)/4."""
+    rng = rng_for(4)
+    out = []
+    for i in range(nboxes):
+        nx = int(rng.choice(BOX_SIDES))
+        ny = int(rng.choice(BOX_SIDES))
+        nc = int(rng.choice([2, 3]))
+        sub = rng_for(4, i + 1)
+        mix, T, z, p, fl = _pick_state(sub, backend, nc, 0.6, 0.98, 0.05, {})
+        R0 = min(nx, ny) / 4.0
+        rho0 = drop_profile((ny, nx), R0, 4.0, fl.rbar_l, fl.rbar_v)
+        out.append(Config(f"C4[{i}]", "D2Q9", (ny, nx), mix, T, p, z, np.asarray(fl.gamma),
+                          np.asarray(fl.rbar_l), np.asarray(fl.rbar_v), rho0, "bgk", "edm",
+                          steps=10000, geometry={"kind": "drop", "R0": R0}))
+    return out
