@@ -1,0 +1,200 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) multi-component pseudo-potential lattice
+ * Boltzmann step.
+ *
+ * Model: Peng, Ayala & Ayala, "A thermodynamically consistent pseudo-potential
+ * lattice Boltzmann model for multi-component, multiphase, partially miscible
+ * mixtures" (arXiv 1909.12390).  One step, in the order of Sec. 3.4:
+ *   mixture Peng-Robinson pressure  (Sec. 3.2, Eq. MCPengRobinson + randommixingrule)
+ *   pseudo-potential psi            (Sec. 3.1, Eq. psicorrected)
+ *   total interaction force         (Sec. 3.3, Eq. coupledMCforce)
+ *   split into components           (Sec. 3.1, Eqs. forcedistribution, distributionforce)
+ *   collision with forcing          (Sec. 2.1, Eq. LBE with Eq. equilibrium; or the
+ *                                    exact-difference method; BGK or MRT)
+ *   streaming                       (Sec. 2.1, left side of Eq. LBE)
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an lbm_status; nothing throws or aborts across the ABI.
+ *     lbm_last_error() returns a thread-local message for the last failure.
+ *   - Units are lattice units (dx = dt = 1, c_s^2 = 1/3) for the step; the thermo
+ *     calls (lbm_critical, lbm_fugacity, lbm_flash, lbm_bubble_pressure,
+ *     lbm_dew_pressure) accept any consistent unit system through lbm_mixture.R.
+ *   - All thermodynamics and psi are float64.
+ *   - Field layout on the device: structure of arrays, x fastest:
+ *       cell = (z * ny + y) * nx + x,   cells = nx * ny * nz   (nz = 1 in 2-D)
+ *       scalar field [cells]; per-component field [nc][cells];
+ *       vector field [D][cells]; populations [nc][Q][cells].
+ *   - "dev" pointers are device (HBM) pointers owned by the caller; "host" pointers
+ *     are host memory, borrowed for the duration of the call.
+ *   - Boundaries are periodic in every direction (Sec. 4 uses periodic domains).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,          /* invalid argument (checked on the host before any launch)   */
+  LBM_ERR_DOMAIN = -2,       /* EOS / psi left its domain on the device: b_m*rho~ >= 1,
+                                negative argument of the square root in Eq. psicorrected,
+                                sum_i gamma_i rbar_i <= 0, or a non-finite value           */
+  LBM_ERR_HIP = -3,          /* a HIP runtime call failed                                    */
+  LBM_ERR_NOCONVERGE = -4,   /* an iterative thermo solve did not converge                   */
+  LBM_ERR_SINGLEPHASE = -5,  /* flash found one phase (trivial K or vapor fraction outside (0,1)) */
+  LBM_ERR_UNSUPPORTED = -6   /* combination not built into this library                      */
+} lbm_status;
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+enum { LBM_BGK = 0, LBM_MRT = 1 };
+enum { LBM_GUO = 0, LBM_EDM = 1 };
+/* Population storage.  F64: plain float64 populations, float64 collision.
+ * F32_OFS / F16_OFS: per cell and component a float32 base b = rbar_sigma and Q
+ * offsets r_a = f_a / b - w_a stored in float32 / float16 (round to nearest even);
+ * collision in float32; EOS, psi and the force stencil stay float64. */
+enum { LBM_F64 = 0, LBM_F32_OFS = 1, LBM_F16_OFS = 2 };
+/* Kernel schedule of one step. TWO_PASS: density/psi pass then collide pass;
+ * FUSED: one launch that recomputes densities on a halo and marches along the
+ * slowest axis (same results). */
+enum { LBM_SCHED_TWO_PASS = 0, LBM_SCHED_FUSED = 1 };
+
+#define LBM_MAX_NC 4
+#define LBM_MAX_Q 19
+
+/* Component data (Sec. 3.2).  a_i, b_i per mole with gas constant R; molar mass
+ * M_i converts the cell-volume (mass) densities of the populations to molar
+ * densities; k = binary interaction coefficients zeta_ij (symmetric, zero diagonal). */
+typedef struct {
+  int nc;                    /* 1..4                                            */
+  double R;
+  double a[LBM_MAX_NC], b[LBM_MAX_NC], omega[LBM_MAX_NC], M[LBM_MAX_NC];
+  double k[LBM_MAX_NC][LBM_MAX_NC];
+} lbm_mixture;
+
+typedef struct {
+  int lattice;               /* LBM_D2Q9 | LBM_D3Q19                            */
+  int nx, ny, nz;            /* nz must be 1 for D2Q9                           */
+  int collision;             /* LBM_BGK | LBM_MRT                               */
+  int forcing;               /* LBM_GUO | LBM_EDM                               */
+  int storage;               /* LBM_F64 | LBM_F32_OFS | LBM_F16_OFS             */
+  int schedule;              /* LBM_SCHED_TWO_PASS | LBM_SCHED_FUSED            */
+  double T;                  /* temperature                                     */
+  double tau;                /* relaxation time, > 0.5 (Sec. 2.1)               */
+  double G;                  /* interaction strength, < 0 (Sec. 4.1: only its sign matters) */
+  double beta;               /* blending parameter of Eq. coupledMCforce        */
+  double gamma[LBM_MAX_NC];  /* volatility coefficients, Eq. distributionforce, each in (0, 1] */
+  double mrt_s[LBM_MAX_Q];   /* MRT: relaxation rate of each moment row (rows of the orthogonal
+                                Lallemand-Luo D2Q9 / d'Humieres D3Q19 bases, in their order) */
+  double accel[3];           /* uniform body acceleration g; adds rbar_sigma g to F_sigma */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Result of a two-phase flash at (T, p, z) (Sec. 3.2 iso-fugacity; Sec. 2.2 relations). */
+typedef struct {
+  double V;                          /* vapor mole fraction                       */
+  double x[LBM_MAX_NC], y[LBM_MAX_NC], K[LBM_MAX_NC];
+  double Zl, Zv;                     /* compressibility factors                   */
+  double rho_l, rho_v;               /* molar densities of the phases             */
+  double rbar_l[LBM_MAX_NC];         /* cell-volume (mass) densities, liquid: rho_l x_i M_i */
+  double rbar_v[LBM_MAX_NC];         /* ... vapor: rho_v y_i M_i                  */
+  double gamma[LBM_MAX_NC];          /* Eq. gamma against the least volatile component */
+  double fug_l[LBM_MAX_NC], fug_v[LBM_MAX_NC];
+  double residual;                   /* Eq. error                                  */
+  int iterations;
+} lbm_flash_result;
+
+/* ---------------------------------------------------------------------------
+ * Time stepping (device)
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace lbm_init needs for (mix, prm): two population copies
+ * (ping-pong) in the chosen storage, the psi field (two-pass schedule), reduction
+ * partials and an error flag.  Pure host computation. */
+lbm_status lbm_workspace_bytes(const lbm_mixture* mix, const lbm_params* prm, size_t* bytes);
+
+/* Validate (mix, prm) on the host, bind the caller-owned device workspace
+ * (dev, >= lbm_workspace_bytes, 256-byte aligned, must outlive the context) and
+ * set the populations to equilibrium f_a = f^eq_a(rbar_sigma, u) (Eq. equilibrium a)
+ * of the initial cell-volume densities rho_bar0 (dev, float64 [nc][cells]) and the
+ * velocity u0 (dev, float64 [D][cells], or NULL for rest).  All work is enqueued
+ * on `stream` (a hipStream_t; NULL = default stream).  Host-side rejections:
+ * nc outside 1..4, tau <= 0.5, G >= 0, gamma outside (0, 1], non-positive a, b, M,
+ * box sides < 1, nz != 1 for D2Q9, unknown enums -> LBM_ERR_ARG. */
+lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, void* workspace_dev,
+                    size_t workspace_bytes, const double* rho_bar0_dev, const double* u0_dev,
+                    void* stream, lbm_ctx** out);
+
+/* Enqueue nsteps time steps (Sec. 3.4 order) on the context's stream.
+ * Asynchronous: device domain errors are recorded in a device flag and reported by
+ * the next lbm_moments or lbm_check. */
+lbm_status lbm_step(lbm_ctx* ctx, int nsteps);
+
+/* Macroscopic fields of the current state, each output optional (NULL = skip):
+ *   rho_bar_dev [nc][cells]  cell-volume densities rbar_sigma (Sec. 2.1)
+ *   u_dev       [D][cells]   physical velocity (sum_sigma j_sigma + F_total/2)/rho
+ *   p_dev       [cells]      p_EOS (= hydrodynamic pressure of Eq. hydropressure)
+ *   psi_dev     [cells]      pseudo-potential, Eq. psicorrected
+ *   totals_host [nc + 2*D]   mass of each component, total momentum sum(j + F_total/2),
+ *                            net interaction force sum(F), as float64 sums in a fixed
+ *                            (deterministic) order.
+ * Synchronises the stream when totals_host != NULL; returns LBM_ERR_DOMAIN if the
+ * device error flag is set. */
+lbm_status lbm_moments(lbm_ctx* ctx, double* rho_bar_dev, double* u_dev, double* p_dev,
+                       double* psi_dev, double* totals_host);
+
+/* Export / import the populations of the current state as float64 [nc][Q][cells]
+ * (dev), post-streaming (the f of Eq. LBE at time t), velocity order:
+ *   D2Q9 : (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+ *   D3Q19: (0,0,0) (+-1,0,0) (0,+-1,0) (0,0,+-1) (+-1,+-1,0) (+-1,0,+-1) (0,+-1,+-1)
+ *          each group with the sign pattern (+,+) (-,+) (+,-) (-,-) for pairs.
+ * Import encodes into the context's storage (rounding for reduced precision). */
+lbm_status lbm_get_populations(lbm_ctx* ctx, double* f_dev);
+lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f_dev);
+
+/* Synchronise the stream and report the device error flag (LBM_OK / LBM_ERR_DOMAIN). */
+lbm_status lbm_check(lbm_ctx* ctx);
+
+/* Clear the device error flag. */
+lbm_status lbm_clear_error(lbm_ctx* ctx);
+
+/* Release the context (not the caller's workspace). NULL is accepted. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Thread-local text of the last error (never NULL). */
+const char* lbm_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Thermodynamics (host, float64)
+ * ------------------------------------------------------------------------- */
+
+/* Critical constants implied by a_i, b_i (inverting the Sec. 3.2 definitions):
+ * Tc_i = (Omega_b/Omega_a) a_i / (b_i R), pc_i = Omega_b R Tc_i / b_i. Outputs [nc]. */
+lbm_status lbm_critical(const lbm_mixture* mix, double* Tc_host, double* pc_host);
+
+/* State of nstates homogeneous cells given molar densities n (host, [nstates][nc]):
+ * p from Eq. MCPengRobinson, Z = p / (rho~ R T) (no root choice), ln(phi_i) from
+ * Eq. fugacitycoeff2 at the local composition, fugacity f_i = phi_i c_i p
+ * (Eq. fugacity).  Outputs (host, any may be NULL): p [nstates], Z [nstates],
+ * lnphi [nstates][nc], fug [nstates][nc]. */
+lbm_status lbm_fugacity(const lbm_mixture* mix, double T, int nstates, const double* n_host,
+                        double* p_host, double* Z_host, double* lnphi_host, double* fug_host);
+
+/* Two-phase flash at (T, p, z) (z host [nc]): Wilson start, successive substitution
+ * on K with the Gibbs-energy root choice of Eq. solutionselection, Rachford-Rice for
+ * the vapor fraction.  LBM_ERR_SINGLEPHASE if no two-phase split exists. */
+lbm_status lbm_flash(const lbm_mixture* mix, double T, double p, const double* z_host,
+                     lbm_flash_result* out);
+
+/* Bubble- and dew-point pressures of composition z at T (successive substitution). */
+lbm_status lbm_bubble_pressure(const lbm_mixture* mix, double T, const double* z_host, double* p_out);
+lbm_status lbm_dew_pressure(const lbm_mixture* mix, double T, const double* z_host, double* p_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

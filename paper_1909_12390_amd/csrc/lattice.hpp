@@ -1,0 +1,104 @@
+// Velocity sets and orthogonal MRT moment rows for the device kernels.
+//
+// D2Q9 / D3Q19 with c_s^2 = 1/3 (the paper does not name its set; Sec. 2.1 only
+// speaks of weighting factors).  Velocity order (also the order of the population
+// planes in memory and of lbm_get_populations):
+//   D2Q9 : 0 rest, 1 +x, 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-)
+//   D3Q19: 0 rest, 1..6 faces +x -x +y -y +z -z, 7..10 xy-edges, 11..14 xz-edges,
+//          15..18 yz-edges, each edge group (+,+) (-,+) (+,-) (-,-).
+// MRT rows: the orthogonal polynomial sets of Lallemand & Luo (D2Q9) and
+// d'Humieres et al. (D3Q19), evaluated from their polynomials in (cx, cy, cz).
+#pragma once
+#include "lbm.h"
+
+namespace lbmk {
+
+template <int LAT>
+struct VS;
+
+template <>
+struct VS<LBM_D2Q9> {
+  static constexpr int D = 2;
+  static constexpr int Q = 9;
+  __host__ __device__ static constexpr int cx(int a) {
+    return (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cy(int a) {
+    return (a == 2 || a == 5 || a == 6) ? 1 : ((a == 4 || a == 7 || a == 8) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cz(int) { return 0; }
+  __host__ __device__ static constexpr double w(int a) {
+    return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+  // moment row k evaluated at velocity a
+  __host__ __device__ static constexpr double mrow(int k, int a) {
+    const double x = cx(a), y = cy(a);
+    const double e2 = x * x + y * y;
+    switch (k) {
+      case 0: return 1.0;
+      case 1: return -4.0 + 3.0 * e2;
+      case 2: return 4.0 - 10.5 * e2 + 4.5 * e2 * e2;
+      case 3: return x;
+      case 4: return (-5.0 + 3.0 * e2) * x;
+      case 5: return y;
+      case 6: return (-5.0 + 3.0 * e2) * y;
+      case 7: return x * x - y * y;
+      default: return x * y;
+    }
+  }
+};
+
+template <>
+struct VS<LBM_D3Q19> {
+  static constexpr int D = 3;
+  static constexpr int Q = 19;
+  __host__ __device__ static constexpr int cx(int a) {
+    return (a == 1 || a == 7 || a == 9 || a == 11 || a == 13) ? 1
+           : ((a == 2 || a == 8 || a == 10 || a == 12 || a == 14) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cy(int a) {
+    return (a == 3 || a == 7 || a == 8 || a == 15 || a == 17) ? 1
+           : ((a == 4 || a == 9 || a == 10 || a == 16 || a == 18) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cz(int a) {
+    return (a == 5 || a == 11 || a == 12 || a == 15 || a == 16) ? 1
+           : ((a == 6 || a == 13 || a == 14 || a == 17 || a == 18) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr double w(int a) {
+    return a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+  __host__ __device__ static constexpr double mrow(int k, int a) {
+    const double x = cx(a), y = cy(a), z = cz(a);
+    const double e2 = x * x + y * y + z * z;
+    switch (k) {
+      case 0: return 1.0;
+      case 1: return 19.0 * e2 - 30.0;
+      case 2: return (21.0 * e2 * e2 - 53.0 * e2 + 24.0) / 2.0;
+      case 3: return x;
+      case 4: return (5.0 * e2 - 9.0) * x;
+      case 5: return y;
+      case 6: return (5.0 * e2 - 9.0) * y;
+      case 7: return z;
+      case 8: return (5.0 * e2 - 9.0) * z;
+      case 9: return 3.0 * x * x - e2;
+      case 10: return (3.0 * e2 - 5.0) * (3.0 * x * x - e2);
+      case 11: return y * y - z * z;
+      case 12: return (3.0 * e2 - 5.0) * (y * y - z * z);
+      case 13: return x * y;
+      case 14: return y * z;
+      case 15: return x * z;
+      case 16: return (y * y - z * z) * x;
+      case 17: return (z * z - x * x) * y;
+      default: return (x * x - y * y) * z;
+    }
+  }
+};
+
+template <int LAT>
+__host__ __device__ constexpr double mrow_norm2(int k) {
+  double s = 0.0;
+  for (int a = 0; a < VS<LAT>::Q; ++a) s += VS<LAT>::mrow(k, a) * VS<LAT>::mrow(k, a);
+  return s;
+}
+
+}  // namespace lbmk

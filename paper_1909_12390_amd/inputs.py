@@ -161,7 +161,7 @@ def default_mrt_rates(lattice: str, tau: float):
     return np.array([1.0 / tau if k in ("nu", "j") else 1.0 for k in kinds])
 
 
-def _pick_state(rng, backend, nc, t_lo, t_hi, k_max, comp_kwargs, z=None,
+def pick_state(rng, backend, nc, t_lo, t_hi, k_max, comp_kwargs, z=None,
                 exactly_one_supercritical=False, max_draws=200):
     """Draw components, T and z until the mixture splits into two phases at
     p* = (p_bub + p_dew)/2 with every gamma in (0, 1]."""
@@ -194,7 +194,7 @@ def _pick_state(rng, backend, nc, t_lo, t_hi, k_max, comp_kwargs, z=None,
 def config_c1(backend, shape=(64, 64), R0=16.0, noise=1e-3) -> Config:
     """Binary D2Q9 drop (radius 16 in 64x64), BGK + exact-difference forcing, FP64."""
     rng = rng_for(1)
-    mix, T, z, p, fl = _pick_state(rng, backend, 2, 0.7, 0.95, 0.05, {}, z=[0.5, 0.5])
+    mix, T, z, p, fl = pick_state(rng, backend, 2, 0.7, 0.95, 0.05, {}, z=[0.5, 0.5])
     rho0 = drop_profile(shape, R0, 4.0, fl.rbar_l, fl.rbar_v)
     rho0 = rho0 * multiplicative_noise(rng_for(1, 1), rho0.shape, noise)
     return Config("C1", "D2Q9", tuple(shape), mix, T, p, z, np.asarray(fl.gamma), np.asarray(fl.rbar_l),
@@ -205,7 +205,7 @@ def config_c1(backend, shape=(64, 64), R0=16.0, noise=1e-3) -> Config:
 def config_c2(backend, shape=(256, 256)) -> Config:
     """Ternary D2Q9 slab of half the height, MRT + exact-difference forcing."""
     rng = rng_for(2)
-    mix, T, z, p, fl = _pick_state(rng, backend, 3, 0.65, 0.95, 0.05, {})
+    mix, T, z, p, fl = pick_state(rng, backend, 3, 0.65, 0.95, 0.05, {})
     H = shape[0] / 4.0
     rho0 = slab_profile(shape, H, 8.0, fl.rbar_l, fl.rbar_v)
     return Config("C2", "D2Q9", tuple(shape), mix, T, p, z, np.asarray(fl.gamma), np.asarray(fl.rbar_l),
@@ -217,7 +217,7 @@ def config_c3(backend, shape=(128, 128, 128), R0=32.0) -> Config:
     """Four-component D3Q19 drop (radius 32 in 128^3), one supercritical component,
     MRT + exact-difference forcing."""
     rng = rng_for(3)
-    mix, T, z, p, fl = _pick_state(rng, backend, 4, 0.6, 1.05, 0.08, {},
+    mix, T, z, p, fl = pick_state(rng, backend, 4, 0.6, 1.05, 0.08, {},
                                    exactly_one_supercritical=True)
     rho0 = drop_profile(shape, R0, 4.0, fl.rbar_l, fl.rbar_v)
     return Config("C3", "D3Q19", tuple(shape), mix, T, p, z, np.asarray(fl.gamma), np.asarray(fl.rbar_l),
@@ -228,7 +228,7 @@ def config_c3(backend, shape=(128, 128, 128), R0=32.0) -> Config:
 def config_c5(backend, shape=(128, 128), R0=32.0) -> Config:
     """Ternary D2Q9 drop for the adjoint case (BGK + exact-difference forcing)."""
     rng = rng_for(5)
-    mix, T, z, p, fl = _pick_state(rng, backend, 3, 0.7, 0.95, 0.05, {})
+    mix, T, z, p, fl = pick_state(rng, backend, 3, 0.7, 0.95, 0.05, {})
     rho0 = drop_profile(shape, R0, 4.0, fl.rbar_l, fl.rbar_v)
     return Config("C5", "D2Q9", tuple(shape), mix, T, p, z, np.asarray(fl.gamma), np.asarray(fl.rbar_l),
                   np.asarray(fl.rbar_v), rho0, "bgk", "edm", steps=2000,
@@ -249,7 +249,7 @@ def config_c4_boxes(backend, nboxes=512) -> List[Config]:
         ny = int(rng.choice(BOX_SIDES))
         nc = int(rng.choice([2, 3]))
         sub = rng_for(4, i + 1)
-        mix, T, z, p, fl = _pick_state(sub, backend, nc, 0.6, 0.98, 0.05, {})
+        mix, T, z, p, fl = pick_state(sub, backend, nc, 0.6, 0.98, 0.05, {})
         R0 = min(nx, ny) / 4.0
         rho0 = drop_profile((ny, nx), R0, 4.0, fl.rbar_l, fl.rbar_v)
         out.append(Config(f"C4[{i}]", "D2Q9", (ny, nx), mix, T, p, z, np.asarray(fl.gamma),

@@ -1,0 +1,326 @@
+"""ctypes binding of include/lbm.h (argument marshalling only).
+
+Every step of the model runs in the HIP library libpaper_lbm.so; this module only
+converts Python/NumPy/torch arguments into the C structures and device pointers
+the ABI takes.  If the library is not built, every call raises: there is no
+fallback implementation.
+
+torch is used for device memory (the caller-owned workspace and field tensors)
+and for the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_size_t, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpaper_lbm.so")
+
+# enum values of include/lbm.h
+LBM_OK, LBM_ERR_ARG, LBM_ERR_DOMAIN, LBM_ERR_HIP, LBM_ERR_NOCONVERGE, LBM_ERR_SINGLEPHASE, LBM_ERR_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+LATTICES = {"D2Q9": 0, "D3Q19": 1}
+COLLISIONS = {"bgk": 0, "mrt": 1}
+FORCINGS = {"guo": 0, "edm": 1}
+STORAGES = {"f64": 0, "f32": 1, "f16": 2}
+SCHEDULES = {"two_pass": 0, "fused": 1}
+MAX_NC = 4
+MAX_Q = 19
+Q_OF = {"D2Q9": 9, "D3Q19": 19}
+D_OF = {"D2Q9": 2, "D3Q19": 3}
+
+# every function declared in include/lbm.h
+EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_get_populations",
+            "lbm_set_populations", "lbm_check", "lbm_clear_error", "lbm_destroy", "lbm_last_error",
+            "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure"]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbm status {code}: {msg}")
+        self.code = code
+
+
+class LbmMixture(ctypes.Structure):
+    _fields_ = [("nc", c_int), ("R", c_double), ("a", c_double * MAX_NC), ("b", c_double * MAX_NC),
+                ("omega", c_double * MAX_NC), ("M", c_double * MAX_NC), ("k", (c_double * MAX_NC) * MAX_NC)]
+
+
+class LbmParams(ctypes.Structure):
+    _fields_ = [("lattice", c_int), ("nx", c_int), ("ny", c_int), ("nz", c_int), ("collision", c_int),
+                ("forcing", c_int), ("storage", c_int), ("schedule", c_int), ("T", c_double),
+                ("tau", c_double), ("G", c_double), ("beta", c_double), ("gamma", c_double * MAX_NC),
+                ("mrt_s", c_double * MAX_Q), ("accel", c_double * 3)]
+
+
+class LbmFlashResult(ctypes.Structure):
+    _fields_ = [("V", c_double), ("x", c_double * MAX_NC), ("y", c_double * MAX_NC), ("K", c_double * MAX_NC),
+                ("Zl", c_double), ("Zv", c_double), ("rho_l", c_double), ("rho_v", c_double),
+                ("rbar_l", c_double * MAX_NC), ("rbar_v", c_double * MAX_NC), ("gamma", c_double * MAX_NC),
+                ("fug_l", c_double * MAX_NC), ("fug_v", c_double * MAX_NC), ("residual", c_double),
+                ("iterations", c_int)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpaper_lbm.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LbmError(LBM_ERR_UNSUPPORTED,
+                           f"{LIB_PATH} is not built (python -m paper_1909_12390_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        dp = POINTER(c_double)
+        L.lbm_workspace_bytes.argtypes = [POINTER(LbmMixture), POINTER(LbmParams), POINTER(c_size_t)]
+        L.lbm_init.argtypes = [POINTER(LbmMixture), POINTER(LbmParams), c_void_p, c_size_t, c_void_p, c_void_p,
+                               c_void_p, POINTER(c_void_p)]
+        L.lbm_step.argtypes = [c_void_p, c_int]
+        L.lbm_moments.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, dp]
+        L.lbm_get_populations.argtypes = [c_void_p, c_void_p]
+        L.lbm_set_populations.argtypes = [c_void_p, c_void_p]
+        L.lbm_check.argtypes = [c_void_p]
+        L.lbm_clear_error.argtypes = [c_void_p]
+        L.lbm_destroy.argtypes = [c_void_p]
+        L.lbm_destroy.restype = None
+        L.lbm_last_error.restype = ctypes.c_char_p
+        L.lbm_critical.argtypes = [POINTER(LbmMixture), dp, dp]
+        L.lbm_fugacity.argtypes = [POINTER(LbmMixture), c_double, c_int, dp, dp, dp, dp, dp]
+        L.lbm_flash.argtypes = [POINTER(LbmMixture), c_double, c_double, dp, POINTER(LbmFlashResult)]
+        L.lbm_bubble_pressure.argtypes = [POINTER(LbmMixture), c_double, dp, dp]
+        L.lbm_dew_pressure.argtypes = [POINTER(LbmMixture), c_double, dp, dp]
+        for name in EXPORTED:
+            f = getattr(L, name)
+            if name not in ("lbm_destroy", "lbm_last_error"):
+                f.restype = c_int
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != LBM_OK:
+        raise LbmError(code, lib().lbm_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def mixture_struct(mix: dict) -> LbmMixture:
+    m = LbmMixture()
+    nc = len(mix["a"])
+    m.nc = nc
+    m.R = float(mix.get("R", 1.0))
+    for i in range(nc):
+        m.a[i] = float(mix["a"][i])
+        m.b[i] = float(mix["b"][i])
+        m.omega[i] = float(mix["omega"][i])
+        m.M[i] = float(mix["M"][i])
+        for j in range(nc):
+            m.k[i][j] = float(np.asarray(mix["k"])[i, j])
+    return m
+
+
+# ---------------------------------------------------------------------------
+# thermodynamics (host float64 in the library)
+# ---------------------------------------------------------------------------
+
+def lbm_critical(mix: dict):
+    m = mixture_struct(mix)
+    Tc = np.zeros(m.nc)
+    pc = np.zeros(m.nc)
+    _check(lib().lbm_critical(ctypes.byref(m), _dptr(Tc), _dptr(pc)))
+    return Tc, pc
+
+
+def lbm_fugacity(mix: dict, T: float, n: np.ndarray):
+    """n: molar densities [nstates, nc].  Returns dict p, Z, lnphi, fug."""
+    m = mixture_struct(mix)
+    n = np.ascontiguousarray(np.atleast_2d(n), dtype=np.float64)
+    ns = n.shape[0]
+    p = np.zeros(ns)
+    Z = np.zeros(ns)
+    lp = np.zeros((ns, m.nc))
+    fug = np.zeros((ns, m.nc))
+    _check(lib().lbm_fugacity(ctypes.byref(m), float(T), ns, _dptr(n), _dptr(p), _dptr(Z), _dptr(lp), _dptr(fug)))
+    return {"p": p, "Z": Z, "lnphi": lp, "fug": fug}
+
+
+class FlashResult:
+    def __init__(self, r: LbmFlashResult, nc: int):
+        for name in ("V", "Zl", "Zv", "rho_l", "rho_v", "residual", "iterations"):
+            setattr(self, name, getattr(r, name))
+        for name in ("x", "y", "K", "rbar_l", "rbar_v", "gamma", "fug_l", "fug_v"):
+            setattr(self, name, np.array(getattr(r, name)[:nc]))
+
+
+def lbm_flash(mix: dict, T: float, p: float, z) -> FlashResult:
+    m = mixture_struct(mix)
+    zz = np.ascontiguousarray(z, dtype=np.float64)
+    r = LbmFlashResult()
+    _check(lib().lbm_flash(ctypes.byref(m), float(T), float(p), _dptr(zz), ctypes.byref(r)))
+    return FlashResult(r, m.nc)
+
+
+def lbm_bubble_pressure(mix: dict, T: float, z) -> float:
+    m = mixture_struct(mix)
+    zz = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.zeros(1)
+    _check(lib().lbm_bubble_pressure(ctypes.byref(m), float(T), _dptr(zz), _dptr(out)))
+    return float(out[0])
+
+
+def lbm_dew_pressure(mix: dict, T: float, z) -> float:
+    m = mixture_struct(mix)
+    zz = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.zeros(1)
+    _check(lib().lbm_dew_pressure(ctypes.byref(m), float(T), _dptr(zz), _dptr(out)))
+    return float(out[0])
+
+
+class LibThermo:
+    """The library's thermodynamics through the backend interface of inputs.py."""
+
+    def critical_temperature(self, mix):
+        return lbm_critical(mix)[0]
+
+    def bubble_pressure(self, mix, T, z):
+        return lbm_bubble_pressure(mix, T, z)
+
+    def dew_pressure(self, mix, T, z):
+        return lbm_dew_pressure(mix, T, z)
+
+    def flash(self, mix, T, p, z):
+        return lbm_flash(mix, T, p, z)
+
+
+# ---------------------------------------------------------------------------
+# time stepping on the device
+# ---------------------------------------------------------------------------
+
+def params_struct(lattice, shape, T, tau, beta, gamma, collision="bgk", forcing="guo", storage="f64",
+                  schedule="two_pass", mrt_s=None, accel=None, G=-1.0) -> LbmParams:
+    p = LbmParams()
+    p.lattice = LATTICES[lattice]
+    if lattice == "D2Q9":
+        ny, nx = shape
+        nz = 1
+    else:
+        nz, ny, nx = shape
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.collision = COLLISIONS[collision]
+    p.forcing = FORCINGS[forcing]
+    p.storage = STORAGES[storage]
+    p.schedule = SCHEDULES[schedule]
+    p.T = float(T)
+    p.tau = float(tau)
+    p.G = float(G)
+    p.beta = float(beta)
+    for i, g in enumerate(gamma):
+        p.gamma[i] = float(g)
+    if mrt_s is not None:
+        for k, s in enumerate(mrt_s):
+            p.mrt_s[k] = float(s)
+    if accel is not None:
+        for d, g in enumerate(accel):
+            p.accel[d] = float(g)
+    return p
+
+
+class LbmContext:
+    """One simulation box on the current HIP device (one lbm_ctx).
+
+    rho0: initial cell-volume densities (nc, *shape), float64 (NumPy or torch).
+    u0  : optional initial velocity (D, *shape).
+    """
+
+    def __init__(self, mix: dict, lattice: str, shape, T, tau, beta, gamma, rho0, u0=None,
+                 collision="bgk", forcing="guo", storage="f64", schedule="two_pass", mrt_s=None,
+                 accel=None, G=-1.0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lattice = lattice
+        self.shape = tuple(int(s) for s in shape)
+        self.nc = len(mix["a"])
+        self.Q = Q_OF[lattice]
+        self.D = D_OF[lattice]
+        self.cells = int(np.prod(self.shape))
+        self._mix = mixture_struct(mix)
+        self._prm = params_struct(lattice, self.shape, T, tau, beta, gamma, collision, forcing, storage,
+                                  schedule, mrt_s, accel, G)
+        nbytes = c_size_t(0)
+        _check(lib().lbm_workspace_bytes(ctypes.byref(self._mix), ctypes.byref(self._prm), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        rho0_t = self._to_device(rho0, (self.nc,) + self.shape)
+        u0_t = None if u0 is None else self._to_device(u0, (self.D,) + self.shape)
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        ctx = c_void_p()
+        _check(lib().lbm_init(ctypes.byref(self._mix), ctypes.byref(self._prm), c_void_p(self._ws_ptr),
+                              c_size_t(int(nbytes.value)), c_void_p(rho0_t.data_ptr()),
+                              None if u0_t is None else c_void_p(u0_t.data_ptr()),
+                              c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.stream.synchronize()     # the init kernel has read rho0_t / u0_t
+        self._keep = None
+
+    def _to_device(self, a, shape):
+        torch = self.torch
+        t = torch.as_tensor(a, dtype=torch.float64)
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        return t.to(self.workspace.device).contiguous()
+
+    def step(self, n: int = 1):
+        _check(lib().lbm_step(self._ctx, int(n)))
+
+    def check(self):
+        _check(lib().lbm_check(self._ctx))
+
+    def clear_error(self):
+        _check(lib().lbm_clear_error(self._ctx))
+
+    def moments(self, fields=True, totals=True):
+        torch = self.torch
+        dev = self.workspace.device
+        out = {}
+        ptrs = [None, None, None, None]
+        if fields:
+            out["rho_s"] = torch.empty((self.nc,) + self.shape, dtype=torch.float64, device=dev)
+            out["u"] = torch.empty((self.D,) + self.shape, dtype=torch.float64, device=dev)
+            out["p"] = torch.empty(self.shape, dtype=torch.float64, device=dev)
+            out["psi"] = torch.empty(self.shape, dtype=torch.float64, device=dev)
+            ptrs = [c_void_p(out[k].data_ptr()) for k in ("rho_s", "u", "p", "psi")]
+        tot = np.zeros(self.nc + 2 * self.D) if totals else None
+        _check(lib().lbm_moments(self._ctx, *ptrs, None if tot is None else _dptr(tot)))
+        if totals:
+            out["mass"] = tot[: self.nc].copy()
+            out["momentum"] = tot[self.nc: self.nc + self.D].copy()
+            out["force"] = tot[self.nc + self.D:].copy()
+        return out
+
+    def get_populations(self):
+        torch = self.torch
+        f = torch.empty((self.nc, self.Q) + self.shape, dtype=torch.float64, device=self.workspace.device)
+        _check(lib().lbm_get_populations(self._ctx, c_void_p(f.data_ptr())))
+        return f
+
+    def set_populations(self, f):
+        t = self._to_device(f, (self.nc, self.Q) + self.shape)
+        _check(lib().lbm_set_populations(self._ctx, c_void_p(t.data_ptr())))
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None:
+            lib().lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

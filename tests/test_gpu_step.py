@@ -1,0 +1,147 @@
+"""GPU parity of the HIP step (through the C ABI) against the CPU oracle.
+
+Bar: float64 storage must match the oracle to 1e-12 relative per component
+(max |f_gpu - f_oracle| / max |f_oracle|) after 1 and 10 steps from identical
+states.  Boxes are ragged (cells not a multiple of the 256-thread block, sides
+not multiples of the tile) and span several blocks.
+"""
+import numpy as np
+import pytest
+
+from cases import LAT, case, mrt_rates, oracle_params, oracle_run
+from oracle import lbm as olbm
+from oracle_backend import to_mixture
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPES = {"D2Q9": (45, 70), "D3Q19": (13, 14, 15)}
+COMBOS = [("bgk", "guo"), ("bgk", "edm"), ("mrt", "guo"), ("mrt", "edm")]
+
+
+def _lbm():
+    from paper_1909_12390_amd import lbm
+    return lbm
+
+
+def rel_err(g, f):
+    """max over components of max|g - f| / max|f|"""
+    return max(float(np.max(np.abs(g[s] - f[s])) / np.max(np.abs(f[s]))) for s in range(f.shape[0]))
+
+
+def gpu_context(c, lattice, collision, forcing, storage="f64", schedule="two_pass", tau=0.8, beta=1.7,
+                mrt_s=None, accel=None):
+    lbm = _lbm()
+    return lbm.LbmContext(c["mix"], lattice, c["shape"], c["T"], tau, beta, c["gamma"], c["rho0"], c["u0"],
+                          collision=collision, forcing=forcing, storage=storage, schedule=schedule,
+                          mrt_s=mrt_s, accel=accel)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("nc", [1, 2, 3, 4])
+@pytest.mark.parametrize("collision,forcing", COMBOS)
+def test_f64_step_matches_oracle(lattice, nc, collision, forcing):
+    print(f"case f64 {lattice} nc={nc} {collision}+{forcing}", flush=True)
+    c = case(lattice, nc, SHAPES[lattice], seed=nc, u_amp=0.01)
+    rates = mrt_rates(lattice, 0.8) if collision == "mrt" else None
+    prm = oracle_params(c, collision, forcing, mrt_s=rates)
+    ref = oracle_run(c, lattice, prm, 10)
+    ctx = gpu_context(c, lattice, collision, forcing, mrt_s=rates)
+    f0 = ctx.get_populations().cpu().numpy()
+    assert rel_err(f0, ref[0]) < 1e-15
+    ctx.step(1)
+    e1 = rel_err(ctx.get_populations().cpu().numpy(), ref[1])
+    ctx.step(9)
+    e10 = rel_err(ctx.get_populations().cpu().numpy(), ref[10])
+    ctx.check()
+    assert e1 < 1e-12 and e10 < 1e-12, (e1, e10)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_moments_and_totals_match_oracle(lattice):
+    print(f"case moments {lattice}", flush=True)
+    c = case(lattice, 3, SHAPES[lattice], seed=7, u_amp=0.01)
+    accel = [1e-5, -2e-5, 3e-5][: 2 if lattice == "D2Q9" else 3]
+    prm = oracle_params(c, "bgk", "guo", accel=accel)
+    ref = oracle_run(c, lattice, prm, 3)
+    ctx = gpu_context(c, lattice, "bgk", "guo", accel=accel)
+    ctx.step(3)
+    m = ctx.moments()
+    lat = LAT[lattice]
+    om = olbm.macroscopic(ref[3], to_mixture(c["mix"]), prm, lat)
+    ot = olbm.totals(ref[3], to_mixture(c["mix"]), prm, lat)
+    for k in ("rho_s", "u", "p", "psi"):
+        g = m[k].cpu().numpy()
+        assert np.max(np.abs(g - om[k])) <= 1e-12 * np.max(np.abs(om[k])), k
+    assert np.allclose(m["mass"], ot["mass"], rtol=1e-13)
+    assert np.allclose(m["momentum"], ot["momentum"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(m["force"], ot["force"], atol=1e-12)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("forcing", ["guo", "edm"])
+def test_conservation_on_gpu(lattice, forcing):
+    print(f"case conservation {lattice} {forcing}", flush=True)
+    c = case(lattice, 2, SHAPES[lattice], seed=3)
+    g = [2e-6, -1e-6, 1e-6][: 2 if lattice == "D2Q9" else 3]
+    ctx = gpu_context(c, lattice, "bgk", forcing, accel=g)
+    t0 = ctx.moments(fields=False)
+    n = 200
+    ctx.step(n)
+    t1 = ctx.moments(fields=False)
+    assert np.all(np.abs(t1["mass"] / t0["mass"] - 1) < 1e-13 * np.sqrt(n))
+    assert np.all(np.abs(t1["force"]) < 1e-11)
+    M = float(np.sum(t0["mass"]))
+    assert np.allclose(t1["momentum"] - t0["momentum"], n * M * np.asarray(g), rtol=1e-9, atol=1e-11)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("forcing,gamma", [("guo", (0.4, 1.0)), ("edm", (1.0, 1.0))])
+def test_identical_components_equal_single_component_on_gpu(lattice, forcing, gamma):
+    # Sec. 4.1 limiting case on the device: two identical components (segregated
+    # initial fields, Eq. (initialMC)) evolve as the pure fluid.
+    print(f"case limiting {lattice} {forcing}", flush=True)
+    c1 = case(lattice, 1, SHAPES[lattice], seed=0, noise=0.0)
+    mix2 = {k: (np.concatenate([v, v]) if k in ("a", "b", "omega", "M") else v) for k, v in c1["mix"].items()}
+    mix2["k"] = np.zeros((2, 2))
+    rho = c1["rho0"][0]
+    rl, rv = rho.max(), rho.min()
+    # split: component 1 carries the liquid excess, component 2 the vapor part
+    r1 = rho - rv
+    r2 = np.full_like(rho, rv)
+    r1 = np.maximum(r1, 1e-3 * rl)
+    r2 = rho - r1
+    c2 = dict(c1, mix=mix2, rho0=np.stack([r1, r2]), gamma=np.array(gamma))
+    a = gpu_context(c1, lattice, "bgk", forcing, tau=1.0, beta=1.3)
+    b = gpu_context(c2, lattice, "bgk", forcing, tau=1.0, beta=1.3)
+    a.step(20)
+    b.step(20)
+    fa = a.get_populations().cpu().numpy()[0]
+    fb = b.get_populations().cpu().numpy().sum(0)
+    a.check()
+    b.check()
+    assert np.max(np.abs(fa - fb)) < 1e-12 * np.max(np.abs(fa))
+
+
+def test_domain_error_reported():
+    lbm = _lbm()
+    c = case("D2Q9", 2, (16, 20), seed=1)
+    rho0 = c["rho0"].copy()
+    rho0[0, 3, 4] = 50.0 / c["mix"]["b"][0] * c["mix"]["M"][0]      # b_m rho~ >> 1 in one cell
+    c = dict(c, rho0=rho0)
+    ctx = gpu_context(c, "D2Q9", "bgk", "edm")
+    ctx.step(1)
+    with pytest.raises(lbm.LbmError) as e:
+        ctx.check()
+    assert e.value.code == lbm.LBM_ERR_DOMAIN
+    ctx.clear_error()
+
+
+def test_set_get_populations_roundtrip():
+    c = case("D3Q19", 2, (9, 10, 11), seed=5, u_amp=0.02)
+    ctx = gpu_context(c, "D3Q19", "mrt", "edm", mrt_s=mrt_rates("D3Q19", 0.8))
+    f = ctx.get_populations().cpu().numpy()
+    rng = np.random.default_rng(0)
+    g = f * (1 + 1e-3 * rng.uniform(-1, 1, f.shape))
+    ctx.set_populations(g)
+    assert np.array_equal(ctx.get_populations().cpu().numpy(), g)

@@ -1,0 +1,89 @@
+"""Host thermodynamics of the library (C++ float64) against the oracle.
+
+The two are independent implementations (closed-form cubic and Newton-safeguarded
+Rachford-Rice in the library; eigenvalue roots and bisection in the oracle)."""
+import numpy as np
+import pytest
+
+from golden_io import table1
+from oracle import thermo as th
+from oracle_backend import BACKEND, to_mixture
+from paper_1909_12390_amd import inputs, lbm
+
+R_FIELD = 10.7316
+
+
+def c3_nc5_dict():
+    t = table1()
+    m = th.mixture_from_critical([t["C3"]["pc"], t["nC5"]["pc"]], [t["C3"]["Tc"], t["nC5"]["Tc"]],
+                                 [t["C3"]["omega"], t["nC5"]["omega"]], [t["C3"]["M"], t["nC5"]["M"]], R=R_FIELD)
+    return {"a": m.a, "b": m.b, "omega": m.omega, "M": m.M, "k": m.k, "R": m.R}, m
+
+
+def test_critical_constants():
+    d, m = c3_nc5_dict()
+    Tc, pc = lbm.lbm_critical(d)
+    assert np.allclose(Tc, [666.06, 845.8], rtol=1e-13)
+    assert np.allclose(pc, [616.0, 488.6], rtol=1e-13)
+    assert np.allclose(Tc, m.Tc, rtol=1e-15)
+
+
+@pytest.mark.parametrize("p", [240.0, 220.0, 200.0, 180.0, 160.0, 140.0])
+def test_flash_matches_oracle_table2_state(p):
+    d, m = c3_nc5_dict()
+    a = lbm.lbm_flash(d, 666.06, p, [0.4, 0.6])
+    b = th.flash(m, 666.06, p, [0.4, 0.6])
+    for name in ("Zl", "Zv", "rho_l", "rho_v", "V"):
+        assert abs(getattr(a, name) / getattr(b, name) - 1) < 1e-10, name
+    for name in ("x", "y", "K", "rbar_l", "rbar_v", "gamma", "fug_l", "fug_v"):
+        assert np.allclose(getattr(a, name), getattr(b, name), rtol=1e-10, atol=0), name
+    assert a.residual < 1e-20
+
+
+def test_bubble_dew_match_oracle():
+    d, m = c3_nc5_dict()
+    assert abs(lbm.lbm_bubble_pressure(d, 666.06, [0.4, 0.6]) / th.bubble_pressure(m, 666.06, [0.4, 0.6]) - 1) < 1e-11
+    assert abs(lbm.lbm_dew_pressure(d, 666.06, [0.4, 0.6]) / th.dew_pressure(m, 666.06, [0.4, 0.6]) - 1) < 1e-11
+
+
+def test_fugacity_of_states_matches_oracle():
+    d, m = c3_nc5_dict()
+    fl = th.flash(m, 666.06, 200.0, [0.4, 0.6])
+    n = np.array([fl.rho_l * fl.x, fl.rho_v * fl.y, [0.02, 0.03]])
+    out = lbm.lbm_fugacity(d, 666.06, n)
+    for i in range(3):
+        s = th.state_from_molar(m, 666.06, n[i])
+        assert abs(out["p"][i] / s["p"] - 1) < 1e-12
+        assert abs(out["Z"][i] / s["Z"] - 1) < 1e-12
+        assert np.allclose(out["lnphi"][i], s["lnphi"], rtol=1e-11, atol=1e-13)
+        assert np.allclose(out["fug"][i], s["fug"], rtol=1e-11)
+    # the two flashed phases are in iso-fugacity (Eq. error)
+    assert np.allclose(out["fug"][0], out["fug"][1], rtol=1e-10)
+
+
+@pytest.mark.parametrize("maker", [inputs.config_c1, inputs.config_c2, inputs.config_c5])
+def test_generated_lattice_unit_states_agree(maker):
+    # the seeded configuration drawn with either backend lands on the same state
+    a = maker(BACKEND)
+    b = maker(lbm.LibThermo())
+    assert abs(a.T / b.T - 1) < 1e-14
+    assert abs(a.p_star / b.p_star - 1) < 1e-10
+    assert np.allclose(a.gamma, b.gamma, rtol=1e-9)
+    assert np.allclose(a.rbar_l, b.rbar_l, rtol=1e-9)
+    assert np.allclose(a.rbar_v, b.rbar_v, rtol=1e-9)
+
+
+def test_single_phase_reported():
+    d, _ = c3_nc5_dict()
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_flash(d, 666.06, 400.0, [0.4, 0.6])
+    assert e.value.code == lbm.LBM_ERR_SINGLEPHASE
+
+
+def test_c3_four_component_state_agrees():
+    a = inputs.config_c3(BACKEND, shape=(8, 8, 8), R0=2.0)
+    b = inputs.config_c3(lbm.LibThermo(), shape=(8, 8, 8), R0=2.0)
+    assert np.allclose(a.gamma, b.gamma, rtol=1e-9)
+    assert np.allclose(a.rbar_l, b.rbar_l, rtol=1e-9)
+    mix = to_mixture(a.mix)
+    assert int(np.sum(a.T > mix.Tc)) == 1          # exactly one supercritical component
