@@ -1,0 +1,321 @@
+#!/usr/bin/env python3
+"""Benchmark of the multi-component pseudo-potential LB step on one MI355X.
+
+Workload (default): four-component D3Q19 box of 128^3 cells with a spherical drop
+of radius 32 in vapor, MRT collision with exact-difference forcing, one component
+supercritical (the seeded four-component configuration of inputs.config_c3), with
+populations stored as float16 offsets (float32 collision, float64 EOS / psi).
+
+One step = one lbm_step (densities, EOS, psi, force stencil, split, collision,
+streaming); every `--diag-every` steps the conservation totals are reduced on
+the device as well.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line.  `value` is MLUPS x components (cells * nc * steps / s / 1e6)
+of the whole job.  `roofline` prices the dominant kernel: algorithmic bytes per
+cell update (populations read + written once, psi written + read once, the
+float32 base of the offset formats) times the cells of one launch, divided by the
+kernel's average duration from HIP events over the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS×components + HBM GB/s % peak, FP16/FP32 vs FP64 at 1e-4 mole-frac err"
+PEAK_HBM_GBS = 8000.0
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def b_alg(nc: int, Q: int, storage: str) -> int:
+    """Algorithmic bytes per cell update: 2 nc Q s (populations) + 16 (psi written
+    and read once) + 8 nc for the float32 base (read + write) of the offset formats."""
+    s = STORAGE_BYTES[storage]
+    return 2 * nc * Q * s + 16 + (8 * nc if storage != "f64" else 0)
+
+
+def b_alg_collide(nc: int, Q: int, storage: str) -> int:
+    """Share of b_alg carried by the collide kernel: populations read and written
+    once, the float32 base read and written once (offset formats), psi read once
+    (the psi write, 8 B, belongs to the density/psi kernel)."""
+    return b_alg(nc, Q, storage) - 8
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1909_12390_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch recorded from rocprofv3 FETCH_SIZE/WRITE_SIZE runs for
+    this kernel, or None if absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(kernel_key)
+    if not ent or ent.get("source_sha") != kernel_source_sha():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def phase_mole_fractions(rho_s, M, geometry, shape):
+    """Bulk liquid/vapor mole fractions with fixed masks: drop liquid = r <= R0/2,
+    vapor = r >= min(L)/2 (box corners); x_i = sum_mask n_i / sum_mask n."""
+    import torch
+    dev = rho_s.device
+    grids = torch.meshgrid(*[torch.arange(n, dtype=torch.float64, device=dev) for n in shape], indexing="ij")
+    r2 = sum((g - n / 2.0) ** 2 for g, n in zip(grids, shape))
+    r = torch.sqrt(r2)
+    R0 = geometry["R0"]
+    liq = r <= R0 / 2.0
+    vap = r >= min(shape) / 2.0
+    n = rho_s / torch.as_tensor(M, dtype=torch.float64, device=dev).reshape((-1,) + (1,) * len(shape))
+    out = {}
+    for name, mask in (("liquid", liq), ("vapor", vap)):
+        ni = torch.stack([n[i][mask].sum() for i in range(n.shape[0])])
+        out[name] = (ni / ni.sum()).cpu().numpy()
+    return out
+
+
+def copy_bandwidth(torch, nbytes=2 << 30, reps=5):
+    """Device-to-device copy of nbytes (read nbytes, write nbytes): achievable HBM GB/s."""
+    n = nbytes // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline_worker(side: int, steps: int):
+    """Oracle timing on a bounded sample (runs in a child with one BLAS/OpenMP thread)."""
+    from oracle import lattice as olat
+    from oracle import lbm as olbm
+    from oracle import thermo as oth
+    from paper_1909_12390_amd import inputs
+
+    class _Oracle:
+        def critical_temperature(self, mix):
+            return oth.Mixture(**mix).Tc
+
+        def bubble_pressure(self, mix, T, z):
+            return oth.bubble_pressure(oth.Mixture(**mix), T, z)
+
+        def dew_pressure(self, mix, T, z):
+            return oth.dew_pressure(oth.Mixture(**mix), T, z)
+
+        def flash(self, mix, T, p, z):
+            return oth.flash(oth.Mixture(**mix), T, p, z)
+
+    cfg = inputs.config_c3(_Oracle(), shape=(side, side, side), R0=side / 4.0)
+    lat = olat.d3q19()
+    prm = olbm.StepParams(T=cfg.T, tau=cfg.tau, gamma=cfg.gamma, beta=cfg.beta, collision=cfg.collision,
+                          forcing=cfg.forcing, mrt_s=cfg.mrt_s)
+    mix = oth.Mixture(**cfg.mix)
+    f = olbm.init_populations(cfg.rho0, lat)
+    f = olbm.step(f, mix, prm, lat)            # warm-up
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = olbm.step(f, mix, prm, lat)
+    dt = time.perf_counter() - t0
+    cells = side ** 3
+    print(json.dumps({"value": cells * cfg.nc * steps / dt / 1e6, "seconds": dt}))
+
+
+def cpu_baseline(side: int, steps: int):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
+                          "--cpu-side", str(side), "--cpu-steps", str(steps)],
+                         capture_output=True, text=True, env=env, timeout=600)
+    if res.returncode != 0:
+        sys.stderr.write(res.stderr)
+        return None
+    rec = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": rec["value"], "unit": "MLUPS×components", "cores": 1, "kind": "oracle",
+            "sample": f"same four-component D3Q19 MRT+EDM mixture on a {side}^3 periodic box, "
+                      f"{steps} steps after 1 warm-up step, float64 NumPy, one thread "
+                      f"({rec['seconds']:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f16", choices=list(STORAGE_BYTES))
+    ap.add_argument("--schedule", default="blocked", choices=["two_pass", "blocked"])
+    ap.add_argument("--slab-planes", type=int, default=0, help="blocked schedule: planes per slab (0 = auto)")
+    ap.add_argument("--side", type=int, default=128)
+    ap.add_argument("--diag-every", type=int, default=100)
+    ap.add_argument("--modes", default="f64,f32,f16", help="storage modes also timed (comma list, '' = none)")
+    ap.add_argument("--precision-steps", type=int, default=5000,
+                    help="steps run per storage mode for the mole-fraction error (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-side", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-baseline-worker", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.cpu_baseline_worker:
+        cpu_baseline_worker(args.cpu_side, args.cpu_steps)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
+              f"described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1909_12390_amd import inputs, lbm
+
+    torch.cuda.set_device(0)
+    side = args.side
+    cfg = inputs.config_c3(lbm.LibThermo(), shape=(side, side, side), R0=side / 4.0)
+    nc, Q, cells = cfg.nc, 19, cfg.cells
+    rho0 = torch.as_tensor(cfg.rho0, dtype=torch.float64, device="cuda")
+
+    def make(storage, schedule=None, slab=None):
+        return lbm.LbmContext(cfg.mix, "D3Q19", cfg.shape, cfg.T, cfg.tau, cfg.beta, cfg.gamma, rho0,
+                              collision=cfg.collision, forcing=cfg.forcing, storage=storage,
+                              schedule=schedule or args.schedule, mrt_s=cfg.mrt_s,
+                              slab_planes=args.slab_planes if slab is None else slab)
+
+    def timed(ctx, steps, warmup, diag_every):
+        """Time exactly `steps` steps (HIP events around every kernel; totals every
+        diag_every steps).  Returns wall ms, summed kernel ms."""
+        ctx.step(warmup)
+        ctx.check()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms = [0.0, 0.0]
+        done = 0
+        while done < steps:
+            n = min(diag_every, steps - done)
+            a, b = ctx.step_timed(n)
+            kms[0] += a
+            kms[1] += b
+            done += n
+            if done % diag_every == 0:
+                ctx.moments(fields=False, totals=True)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        ctx.check()
+        return wall, kms
+
+    # headline: the chosen storage mode
+    ctx = make(args.storage)
+    t_start_mass = ctx.moments(fields=False)["mass"]
+    wall_ms, kms = timed(ctx, args.steps, args.warmup, args.diag_every)
+    mass_drift = float(np.max(np.abs(ctx.moments(fields=False)["mass"] / t_start_mass - 1)))
+    ms_per_step = wall_ms / args.steps
+    value = cells * nc * args.steps / (wall_ms * 1e-3) / 1e6
+    # dominant kernel: the collide pass (it carries all but the psi write of b_alg)
+    kname = "k_collide"
+    avg_ms = kms[1] / args.steps                      # collide time per step (all slabs)
+    bytes_launch = b_alg_collide(nc, Q, args.storage) * cells
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    key = f"{kname}:{args.schedule}:{args.storage}:D3Q19:nc{nc}:{side}^3"
+    traffic = measured_traffic(key)
+    del ctx
+    torch.cuda.empty_cache()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "MLUPS×components", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
+        "config": {"workload": f"four-component D3Q19 {side}^3 drop (R0={side // 4}), MRT + exact-difference "
+                               f"forcing, one supercritical component, {args.storage} population storage "
+                               f"(float64 EOS/psi), {args.schedule} schedule",
+                   "lattice": "D3Q19", "shape": [side] * 3, "nc": nc, "collision": cfg.collision,
+                   "forcing": cfg.forcing, "storage": args.storage, "schedule": args.schedule,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
+                     "kernel": kname, "kernel_ms_per_step": avg_ms,
+                     "kernel_alg_bytes_per_cell": b_alg_collide(nc, Q, args.storage),
+                     "cells_per_step": cells, "traffic_bytes_per_step": traffic},
+        "step_alg_GBps": b_alg(nc, Q, args.storage) * cells / (ms_per_step * 1e-3) / 1e9,
+        "step_alg_bytes_per_cell": b_alg(nc, Q, args.storage),
+        "kernel_ms_per_step": {"psi": kms[0] / args.steps, "collide": kms[1] / args.steps},
+        "mass_drift_rel": mass_drift,
+    }
+
+    if not args.no_copy:
+        out["copy_GBps_2GiB"] = copy_bandwidth(torch)
+
+    modes = [m for m in args.modes.split(",") if m]
+    if modes:
+        res = {}
+        for m in modes:
+            for sched in ("two_pass", "blocked"):
+                c = make(m, sched)
+                w, k = timed(c, args.steps, args.warmup, args.diag_every)
+                res[f"{m}/{sched}"] = {
+                    "ms_per_step": w / args.steps, "mlups_x_comp": cells * nc * args.steps / (w * 1e-3) / 1e6,
+                    "kernel_ms": [x / args.steps for x in k],
+                    "alg_GBps_step": b_alg(nc, Q, m) * cells / (w / args.steps * 1e-3) / 1e9}
+                del c
+                torch.cuda.empty_cache()
+        ref = res.get("f64/two_pass")
+        if ref:
+            for key in res:
+                res[key]["speedup_vs_f64_two_pass"] = ref["ms_per_step"] / res[key]["ms_per_step"]
+        out["modes"] = res
+
+    if args.precision_steps > 0:
+        prec = {"steps": args.precision_steps}
+        fr = {}
+        for m in ("f64", "f32", "f16"):
+            c = make(m)
+            c.step(args.precision_steps)
+            mo = c.moments(fields=True, totals=False)
+            c.check()
+            fr[m] = phase_mole_fractions(mo["rho_s"], cfg.mix["M"], cfg.geometry, cfg.shape)
+            del c, mo
+            torch.cuda.empty_cache()
+        for m in ("f32", "f16"):
+            prec[f"{m}_max_abs_molefrac_err_vs_f64"] = float(max(
+                np.max(np.abs(fr[m][ph] - fr["f64"][ph])) for ph in ("liquid", "vapor")))
+        prec["f64_liquid_x"] = fr["f64"]["liquid"].tolist()
+        prec["f64_vapor_y"] = fr["f64"]["vapor"].tolist()
+        out["precision"] = prec
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_side, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -57,10 +57,14 @@ enum { LBM_GUO = 0, LBM_EDM = 1 };
  * offsets r_a = f_a / b - w_a stored in float32 / float16 (round to nearest even);
  * collision in float32; EOS, psi and the force stencil stay float64. */
 enum { LBM_F64 = 0, LBM_F32_OFS = 1, LBM_F16_OFS = 2 };
-/* Kernel schedule of one step. TWO_PASS: density/psi pass then collide pass;
- * FUSED: one launch that recomputes densities on a halo and marches along the
- * slowest axis (same results). */
-enum { LBM_SCHED_TWO_PASS = 0, LBM_SCHED_FUSED = 1 };
+/* Kernel schedule of one step (identical results).
+ * TWO_PASS: a density/EOS/psi pass over the whole box, then a collide pass.
+ * BLOCKED : the same two passes slab by slab along the slowest axis (y in 2-D, z in
+ *           3-D): psi on the slab plus one plane each side, then the collide pass of
+ *           the slab, so the collide pass re-reads populations the psi pass has just
+ *           brought into the last-level cache.  Slab height lbm_params.slab_planes
+ *           (0 = sized for about 64 MiB of population input per slab). */
+enum { LBM_SCHED_TWO_PASS = 0, LBM_SCHED_BLOCKED = 1 };
 
 #define LBM_MAX_NC 4
 #define LBM_MAX_Q 19
@@ -81,7 +85,8 @@ typedef struct {
   int collision;             /* LBM_BGK | LBM_MRT                               */
   int forcing;               /* LBM_GUO | LBM_EDM                               */
   int storage;               /* LBM_F64 | LBM_F32_OFS | LBM_F16_OFS             */
-  int schedule;              /* LBM_SCHED_TWO_PASS | LBM_SCHED_FUSED            */
+  int schedule;              /* LBM_SCHED_TWO_PASS | LBM_SCHED_BLOCKED          */
+  int slab_planes;           /* BLOCKED: planes per slab (0 = automatic)        */
   double T;                  /* temperature                                     */
   double tau;                /* relaxation time, > 0.5 (Sec. 2.1)               */
   double G;                  /* interaction strength, < 0 (Sec. 4.1: only its sign matters) */
@@ -155,6 +160,13 @@ lbm_status lbm_moments(lbm_ctx* ctx, double* rho_bar_dev, double* u_dev, double*
  * Import encodes into the context's storage (rounding for reduced precision). */
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* f_dev);
 lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f_dev);
+
+/* lbm_step with HIP events recorded on the context's stream around every kernel
+ * launch: kernel_ms_host[0] receives the summed duration (ms) of the density/psi
+ * launches, kernel_ms_host[1] that of the collide launches.  Synchronises the
+ * stream at the end.  Used by the benchmark to price the dominant kernel against
+ * the roofline. */
+lbm_status lbm_step_timed(lbm_ctx* ctx, int nsteps, double* kernel_ms_host);
 
 /* Synchronise the stream and report the device error flag (LBM_OK / LBM_ERR_DOMAIN). */
 lbm_status lbm_check(lbm_ctx* ctx);

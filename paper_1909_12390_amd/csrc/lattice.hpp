@@ -30,6 +30,11 @@ struct VS<LBM_D2Q9> {
   __host__ __device__ static constexpr double w(int a) {
     return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
   }
+  // opposite velocity and the first member of each opposite pair
+  __host__ __device__ static constexpr int opp(int a) {
+    return a == 0 ? 0 : (a < 5 ? (a + 1) % 4 + 1 : (a - 3) % 4 + 5);
+  }
+  __host__ __device__ static constexpr int pair_first(int p) { return p < 2 ? p + 1 : p + 3; }
   // moment row k evaluated at velocity a
   __host__ __device__ static constexpr double mrow(int k, int a) {
     const double x = cx(a), y = cy(a);
@@ -67,6 +72,14 @@ struct VS<LBM_D3Q19> {
   __host__ __device__ static constexpr double w(int a) {
     return a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
   }
+  // opposite velocity and the first member of each opposite pair
+  __host__ __device__ static constexpr int opp(int a) {
+    // faces pair as (1,2) (3,4) (5,6); each edge group (+,+)(-,+)(+,-)(-,-) pairs 0<->3, 1<->2
+    return a == 0 ? 0 : (a < 7 ? (a % 2 ? a + 1 : a - 1) : (7 + ((a - 7) / 4) * 4 + (3 - (a - 7) % 4)));
+  }
+  __host__ __device__ static constexpr int pair_first(int p) {
+    return p < 3 ? 2 * p + 1 : 7 + ((p - 3) / 2) * 4 + (p - 3) % 2;
+  }
   __host__ __device__ static constexpr double mrow(int k, int a) {
     const double x = cx(a), y = cy(a), z = cz(a);
     const double e2 = x * x + y * y + z * z;
@@ -94,11 +107,48 @@ struct VS<LBM_D3Q19> {
   }
 };
 
+// true if moment row k is odd under velocity reversal (M_k,opp(a) = -M_k,a)
+template <int LAT>
+__host__ __device__ constexpr bool row_odd_impl(int k) {
+  for (int a = 0; a < VS<LAT>::Q; ++a)
+    if (VS<LAT>::mrow(k, VS<LAT>::opp(a)) != -VS<LAT>::mrow(k, a)) return false;
+  return true;
+}
+
 template <int LAT>
 __host__ __device__ constexpr double mrow_norm2(int k) {
   double s = 0.0;
   for (int a = 0; a < VS<LAT>::Q; ++a) s += VS<LAT>::mrow(k, a) * VS<LAT>::mrow(k, a);
   return s;
 }
+
+template <int LAT>
+__host__ __device__ constexpr bool row_odd(int k) { return row_odd_impl<LAT>(k); }
+
+// compile-time checks of the tables: opp is an involution that reverses e_a, the
+// pairs cover every moving velocity once, every MRT row is even or odd.
+template <int LAT>
+constexpr bool tables_consistent() {
+  using V = VS<LAT>;
+  bool seen[V::Q] = {};
+  for (int a = 0; a < V::Q; ++a) {
+    const int o = V::opp(a);
+    if (V::opp(o) != a || V::cx(o) != -V::cx(a) || V::cy(o) != -V::cy(a) || V::cz(o) != -V::cz(a)) return false;
+  }
+  for (int p = 0; p < (V::Q - 1) / 2; ++p) {
+    const int a = V::pair_first(p), o = V::opp(a);
+    if (a == 0 || seen[a] || seen[o]) return false;
+    seen[a] = seen[o] = true;
+  }
+  for (int k = 0; k < V::Q; ++k) {
+    bool even = true;
+    for (int a = 0; a < V::Q; ++a)
+      if (V::mrow(k, V::opp(a)) != V::mrow(k, a)) even = false;
+    if (!even && !row_odd<LAT>(k)) return false;
+  }
+  return true;
+}
+static_assert(tables_consistent<LBM_D2Q9>(), "D2Q9 tables");
+static_assert(tables_consistent<LBM_D3Q19>(), "D3Q19 tables");
 
 }  // namespace lbmk

@@ -1,27 +1,28 @@
-// Kernels and C ABI of the multi-component pseudo-potential LB step on gfx950.
+// C ABI of the multi-component pseudo-potential LB step on gfx950 (host side).
 //
-// Two-pass schedule of one step (Sec. 3.4 order):
+// One step (Sec. 3.4 order) is two kernel passes (lbm_kernels.hpp):
 //   k_psi     : pull + decode the populations, cell-volume densities (float64),
 //               mixture EOS and psi (Eqs. MCPengRobinson, psicorrected) -> psi[cells]
 //   k_collide : pull + decode again, psi stencil (Eq. coupledMCforce), split
 //               (Eq. distributionforce), velocity, collision with forcing
 //               (Eq. LBE / equilibrium; exact-difference method), encode + store.
-// The fused schedule (lbm_fused.hpp) does the same arithmetic in one launch.
 // Pull streaming over ping-pong copies: the kernel at cell x reads direction a
 // from cell x - e_a of the "in" copy and writes its post-collision populations at
 // x of the "out" copy, so no cell is read and written by different threads.
+// The blocked schedule runs both passes slab by slab along the slowest axis.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
 
 #include "lbm.h"
-#include "lbm_fused.hpp"
+#include "lbm_dispatch.hpp"
 #include "lbm_internal.hpp"
-#include "lbm_kernels.hpp"
 
 namespace {
 thread_local char g_err[512] = "";
@@ -39,171 +40,7 @@ extern "C" const char* lbm_last_error(void) { return g_err; }
 
 namespace lbmk {
 
-constexpr int kBlock = 256;
 constexpr int kMaxRed = LBM_MAX_NC + 6;   // reduction width: nc masses + 2 * D
-
-// ---------------------------------------------------------------------------
-// pass 1: densities -> EOS -> psi
-// ---------------------------------------------------------------------------
-template <int LAT, int NC, int ST>
-__global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* __restrict__ psi) {
-  using V = VS<LAT>;
-  const int cell = blockIdx.x * kBlock + threadIdx.x;
-  if (cell >= P.cells) return;
-  const Coord c = make_coord(cell, P);
-  double rb[NC];
-#pragma unroll
-  for (int s = 0; s < NC; ++s) {
-    double acc = 0.0;
-#pragma unroll
-    for (int a = 0; a < V::Q; ++a)
-      acc += (double)in.get(s, a, V::Q, c.at(-V::cx(a), -V::cy(a), -V::cz(a), P.nx, P.ny), P.cells,
-                            (typename Pops<ST>::R)V::w(a));
-    rb[s] = acc;
-  }
-  psi[cell] = eos_psi<NC>(P, rb);
-}
-
-// total force of Eq. (coupledMCforce) at one cell from psi(x) and its neighbours
-template <int LAT, typename PsiAt>
-__device__ __forceinline__ void force_at(const KParams& P, double ps, PsiAt psi_at, double* F) {
-  using V = VS<LAT>;
-  double fx = 0.0, fy = 0.0, fz = 0.0;
-  const double hb = 0.5 * (1.0 - P.beta);
-#pragma unroll
-  for (int a = 1; a < V::Q; ++a) {
-    const double pn = psi_at(a);
-    const double t = V::w(a) * pn * (P.beta * ps + hb * pn);
-    if (V::cx(a)) fx += V::cx(a) * t;
-    if (V::cy(a)) fy += V::cy(a) * t;
-    if (V::cz(a)) fz += V::cz(a) * t;
-  }
-  F[0] = -P.G * fx;
-  F[1] = -P.G * fy;
-  F[2] = -P.G * fz;
-}
-
-// ---------------------------------------------------------------------------
-// pass 2: force, split, collide, store
-// ---------------------------------------------------------------------------
-template <int LAT, int NC, int ST>
-__global__ __launch_bounds__(kBlock) void k_collide(KParams P, Pops<ST> in, Pops<ST> out,
-                                                   const double* __restrict__ psi) {
-  using V = VS<LAT>;
-  using R = typename Pops<ST>::R;
-  constexpr int Q = V::Q;
-  const int cell = blockIdx.x * kBlock + threadIdx.x;
-  if (cell >= P.cells) return;
-  const Coord c = make_coord(cell, P);
-  R f[NC][Q];
-  double rb[NC], j[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int s = 0; s < NC; ++s) {
-    double acc = 0.0;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const R v = in.get(s, a, Q, c.at(-V::cx(a), -V::cy(a), -V::cz(a), P.nx, P.ny), P.cells, (R)V::w(a));
-      f[s][a] = v;
-      acc += (double)v;
-      if (V::cx(a)) j[0] += V::cx(a) * (double)v;
-      if (V::cy(a)) j[1] += V::cy(a) * (double)v;
-      if (V::cz(a)) j[2] += V::cz(a) * (double)v;
-    }
-    rb[s] = acc;
-  }
-  double F[3];
-  force_at<LAT>(P, psi[cell], [&](int a) { return psi[c.at(V::cx(a), V::cy(a), V::cz(a), P.nx, P.ny)]; }, F);
-  double u[3], Fs[NC][3], du[NC][3];
-  cell_forces<NC>(P, rb, j, F, u, Fs, du);
-#pragma unroll
-  for (int s = 0; s < NC; ++s) collide_store<LAT, ST>(P, out, s, cell, f[s], rb[s], u, Fs[s], du[s]);
-}
-
-// ---------------------------------------------------------------------------
-// macroscopic fields + per-block partial sums for the conservation totals
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-template <int K>
-__device__ __forceinline__ void block_partials(double* vals, double* partials) {
-  __shared__ double red[kBlock / 64][K];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double s = wave_sum(vals[k]);
-    if (lane == 0) red[wv][k] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < K) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
-    partials[(size_t)blockIdx.x * K + threadIdx.x] = s;
-  }
-}
-
-template <int LAT, int NC, int ST>
-__global__ __launch_bounds__(kBlock) void k_moments(KParams P, Pops<ST> in, const double* __restrict__ psi,
-                                                   double* rho_out, double* u_out, double* p_out, double* psi_out,
-                                                   double* partials) {
-  using V = VS<LAT>;
-  using R = typename Pops<ST>::R;
-  constexpr int Q = V::Q, D = V::D, K = NC + 2 * D;
-  const int cell = blockIdx.x * kBlock + threadIdx.x;
-  double vals[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) vals[k] = 0.0;
-  if (cell < P.cells) {
-    const Coord c = make_coord(cell, P);
-    double rb[NC], j[3] = {0.0, 0.0, 0.0}, rho = 0.0;
-#pragma unroll
-    for (int s = 0; s < NC; ++s) {
-      double acc = 0.0;
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        const double v = (double)in.get(s, a, Q, c.at(-V::cx(a), -V::cy(a), -V::cz(a), P.nx, P.ny), P.cells, (R)V::w(a));
-        acc += v;
-        if (V::cx(a)) j[0] += V::cx(a) * v;
-        if (V::cy(a)) j[1] += V::cy(a) * v;
-        if (V::cz(a)) j[2] += V::cz(a) * v;
-      }
-      rb[s] = acc;
-      rho += acc;
-    }
-    double F[3];
-    const double ps = psi[cell];
-    force_at<LAT>(P, ps, [&](int a) { return psi[c.at(V::cx(a), V::cy(a), V::cz(a), P.nx, P.ny)]; }, F);
-    double Ft[3], u[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      Ft[d] = F[d] + rho * P.accel[d];
-      u[d] = (j[d] + 0.5 * Ft[d]) / rho;
-    }
-    if (rho_out)
-#pragma unroll
-      for (int s = 0; s < NC; ++s) rho_out[(size_t)s * P.cells + cell] = rb[s];
-    if (u_out)
-#pragma unroll
-      for (int d = 0; d < D; ++d) u_out[(size_t)d * P.cells + cell] = u[d];
-    if (p_out) {
-      double Bn;
-      p_out[cell] = eos_pressure<NC>(P, rb, &Bn);
-    }
-    if (psi_out) psi_out[cell] = ps;
-#pragma unroll
-    for (int s = 0; s < NC; ++s) vals[s] = rb[s];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      vals[NC + d] = j[d] + 0.5 * Ft[d];
-      vals[NC + D + d] = F[d];
-    }
-  }
-  block_partials<K>(vals, partials);
-}
 
 // sum of the per-block partials in a fixed order (one block)
 __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ partials, int nblocks, int K,
@@ -223,164 +60,8 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
   }
 }
 
-// ---------------------------------------------------------------------------
-// state import / export / initialisation (pull layout: the stored direction a at
-// cell y is the population that arrives at y + e_a)
-// ---------------------------------------------------------------------------
-template <int LAT, int NC, int ST>
-__global__ __launch_bounds__(kBlock) void k_export(KParams P, Pops<ST> in, double* __restrict__ f) {
-  using V = VS<LAT>;
-  using R = typename Pops<ST>::R;
-  const int cell = blockIdx.x * kBlock + threadIdx.x;
-  if (cell >= P.cells) return;
-  const Coord c = make_coord(cell, P);
-#pragma unroll
-  for (int s = 0; s < NC; ++s)
-#pragma unroll
-    for (int a = 0; a < V::Q; ++a)
-      f[(size_t)(s * V::Q + a) * P.cells + cell] =
-          (double)in.get(s, a, V::Q, c.at(-V::cx(a), -V::cy(a), -V::cz(a), P.nx, P.ny), P.cells, (R)V::w(a));
-}
-
-// mode 0: import canonical f (float64 [nc][Q][cells]);  mode 1: equilibrium of
-// rho0 [nc][cells] and u0 [D][cells] (u0 may be NULL)
-template <int LAT, int NC, int ST>
-__global__ __launch_bounds__(kBlock) void k_import(KParams P, Pops<ST> out, const double* __restrict__ f,
-                                                  const double* __restrict__ rho0, const double* __restrict__ u0,
-                                                  int mode) {
-  using V = VS<LAT>;
-  using R = typename Pops<ST>::R;
-  constexpr int Q = V::Q;
-  const int cell = blockIdx.x * kBlock + threadIdx.x;
-  if (cell >= P.cells) return;
-  const Coord c = make_coord(cell, P);
-#pragma unroll
-  for (int s = 0; s < NC; ++s) {
-    double v[Q];
-    double sum = 0.0;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const int dst = c.at(V::cx(a), V::cy(a), V::cz(a), P.nx, P.ny);
-      if (mode == 0) {
-        v[a] = f[(size_t)(s * Q + a) * P.cells + dst];
-      } else {
-        const double r = rho0[(size_t)s * P.cells + dst];
-        double ux = 0.0, uy = 0.0, uz = 0.0;
-        if (u0) {
-          ux = u0[dst];
-          uy = u0[(size_t)P.cells + dst];
-          if (V::D == 3) uz = u0[(size_t)2 * P.cells + dst];
-        }
-        v[a] = feq<LAT, double>(a, r, ux, uy, uz, ux * ux + uy * uy + uz * uz);
-      }
-      sum += v[a];
-    }
-    const R base = (R)sum;
-    out.put_base(s, cell, P.cells, base);
-#pragma unroll
-    for (int a = 0; a < Q; ++a) out.put(s, a, Q, cell, P.cells, (R)v[a], base, (R)V::w(a));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// dispatch table over (lattice, nc, storage)
-// ---------------------------------------------------------------------------
-struct Bufs {
-  void* p0;   // F64: f;  offset: base
-  void* p1;   // offset: r
-};
-
-template <int ST>
-Pops<ST> make_pops(const Bufs& b);
-template <>
-Pops<LBM_F64> make_pops<LBM_F64>(const Bufs& b) {
-  Pops<LBM_F64> p;
-  p.f = (double*)b.p0;
-  return p;
-}
-template <>
-Pops<LBM_F32_OFS> make_pops<LBM_F32_OFS>(const Bufs& b) {
-  Pops<LBM_F32_OFS> p;
-  p.base = (float*)b.p0;
-  p.r = (float*)b.p1;
-  return p;
-}
-template <>
-Pops<LBM_F16_OFS> make_pops<LBM_F16_OFS>(const Bufs& b) {
-  Pops<LBM_F16_OFS> p;
-  p.base = (float*)b.p0;
-  p.r = (__half*)b.p1;
-  return p;
-}
-
-struct Ops {
-  void (*step_two_pass)(const KParams&, const Bufs&, const Bufs&, double*, hipStream_t);
-  void (*step_fused)(const KParams&, const Bufs&, const Bufs&, const FusedShape&, hipStream_t);
-  void (*moments)(const KParams&, const Bufs&, double*, double*, double*, double*, double*, double*, hipStream_t);
-  void (*exp)(const KParams&, const Bufs&, double*, hipStream_t);
-  void (*imp)(const KParams&, const Bufs&, const double*, const double*, const double*, int, hipStream_t);
-};
-
-inline int nblocks(int cells) { return (cells + kBlock - 1) / kBlock; }
-
-template <int LAT, int NC, int ST>
-struct OpsImpl {
-  static void step_two_pass(const KParams& P, const Bufs& in, const Bufs& out, double* psi, hipStream_t st) {
-    const int nb = nblocks(P.cells);
-    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(nb), dim3(kBlock), 0, st, P, make_pops<ST>(in), psi);
-    hipLaunchKernelGGL((k_collide<LAT, NC, ST>), dim3(nb), dim3(kBlock), 0, st, P, make_pops<ST>(in),
-                       make_pops<ST>(out), (const double*)psi);
-  }
-  static void step_fused(const KParams& P, const Bufs& in, const Bufs& out, const FusedShape& fs, hipStream_t st) {
-    launch_fused<LAT, NC, ST>(P, make_pops<ST>(in), make_pops<ST>(out), fs, st);
-  }
-  static void moments(const KParams& P, const Bufs& in, double* psi, double* rho, double* u, double* p,
-                      double* psi_out, double* partials, hipStream_t st) {
-    const int nb = nblocks(P.cells);
-    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(nb), dim3(kBlock), 0, st, P, make_pops<ST>(in), psi);
-    hipLaunchKernelGGL((k_moments<LAT, NC, ST>), dim3(nb), dim3(kBlock), 0, st, P, make_pops<ST>(in),
-                       (const double*)psi, rho, u, p, psi_out, partials);
-  }
-  static void exp(const KParams& P, const Bufs& in, double* f, hipStream_t st) {
-    hipLaunchKernelGGL((k_export<LAT, NC, ST>), dim3(nblocks(P.cells)), dim3(kBlock), 0, st, P,
-                       make_pops<ST>(in), f);
-  }
-  static void imp(const KParams& P, const Bufs& out, const double* f, const double* rho0, const double* u0, int mode,
-                  hipStream_t st) {
-    hipLaunchKernelGGL((k_import<LAT, NC, ST>), dim3(nblocks(P.cells)), dim3(kBlock), 0, st, P,
-                       make_pops<ST>(out), f, rho0, u0, mode);
-  }
-  static Ops ops() { return Ops{&step_two_pass, &step_fused, &moments, &exp, &imp}; }
-};
-
-template <int LAT, int NC>
-Ops ops_for_storage(int st) {
-  switch (st) {
-    case LBM_F64: return OpsImpl<LAT, NC, LBM_F64>::ops();
-    case LBM_F32_OFS: return OpsImpl<LAT, NC, LBM_F32_OFS>::ops();
-    default: return OpsImpl<LAT, NC, LBM_F16_OFS>::ops();
-  }
-}
-
-template <int LAT>
-Ops ops_for_nc(int nc, int st) {
-  switch (nc) {
-    case 1: return ops_for_storage<LAT, 1>(st);
-    case 2: return ops_for_storage<LAT, 2>(st);
-    case 3: return ops_for_storage<LAT, 3>(st);
-    default: return ops_for_storage<LAT, 4>(st);
-  }
-}
-
-Ops ops_for(int lat, int nc, int st) {
-  return lat == LBM_D2Q9 ? ops_for_nc<LBM_D2Q9>(nc, st) : ops_for_nc<LBM_D3Q19>(nc, st);
-}
-
 }  // namespace lbmk
 
-// ---------------------------------------------------------------------------
-// host side
-// ---------------------------------------------------------------------------
 using namespace lbmk;
 
 struct lbm_ctx {
@@ -388,11 +69,12 @@ struct lbm_ctx {
   lbm_params prm;
   KParams kp;
   Ops ops;
-  FusedShape fshape;
   int Q, D, K;
+  int slab;               // planes per slab (blocked schedule)
   size_t cells;
   hipStream_t stream;
   Bufs pops[2];
+  StepScratch sc;
   double* psi;
   double* partials;
   double* totals;
@@ -409,11 +91,13 @@ struct Layout {
   size_t pop0[2], pop1[2], psi, partials, totals, err, total;
 };
 
-bool make_layout(const lbm_params* prm, int nc, Layout* L) {
+size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32_OFS ? 4 : 2); }
+
+void make_layout(const lbm_params* prm, int nc, Layout* L) {
   const int Q = prm->lattice == LBM_D2Q9 ? 9 : 19;
   const size_t cells = (size_t)prm->nx * prm->ny * prm->nz;
+  const size_t s = storage_bytes(prm->storage);
   size_t off = 0;
-  const size_t s = prm->storage == LBM_F64 ? 8 : (prm->storage == LBM_F32_OFS ? 4 : 2);
   for (int k = 0; k < 2; ++k) {
     if (prm->storage == LBM_F64) {
       L->pop0[k] = off;
@@ -429,13 +113,12 @@ bool make_layout(const lbm_params* prm, int nc, Layout* L) {
   L->psi = off;
   off = align_up(off + cells * 8);
   L->partials = off;
-  off = align_up(off + (size_t)nblocks((int)cells) * kMaxRed * 8);
+  off = align_up(off + (size_t)nblocks_for((int)cells) * kMaxRed * 8);
   L->totals = off;
   off = align_up(off + 16 * 8);
   L->err = off;
   off = align_up(off + 64);
   L->total = off;
-  return true;
 }
 
 lbm_status validate(const lbm_mixture* mix, const lbm_params* prm) {
@@ -445,15 +128,15 @@ lbm_status validate(const lbm_mixture* mix, const lbm_params* prm) {
   if (prm->collision != LBM_BGK && prm->collision != LBM_MRT) return lbm_fail(LBM_ERR_ARG, "unknown collision");
   if (prm->forcing != LBM_GUO && prm->forcing != LBM_EDM) return lbm_fail(LBM_ERR_ARG, "unknown forcing");
   if (prm->storage < LBM_F64 || prm->storage > LBM_F16_OFS) return lbm_fail(LBM_ERR_ARG, "unknown storage");
-  if (prm->schedule != LBM_SCHED_TWO_PASS && prm->schedule != LBM_SCHED_FUSED)
+  if (prm->schedule != LBM_SCHED_TWO_PASS && prm->schedule != LBM_SCHED_BLOCKED)
     return lbm_fail(LBM_ERR_ARG, "unknown schedule");
-  if (prm->schedule == LBM_SCHED_FUSED && !fused_supported(prm->lattice))
-    return lbm_fail(LBM_ERR_UNSUPPORTED, "fused schedule not built for this lattice");
+  if (prm->slab_planes < 0) return lbm_fail(LBM_ERR_ARG, "slab_planes must be >= 0");
   if (prm->nx < 1 || prm->ny < 1 || prm->nz < 1) return lbm_fail(LBM_ERR_ARG, "box sides must be >= 1");
   if (prm->lattice == LBM_D2Q9 && prm->nz != 1) return lbm_fail(LBM_ERR_ARG, "D2Q9 needs nz == 1");
   const double cells = (double)prm->nx * prm->ny * prm->nz;
-  const int Q = prm->lattice == LBM_D2Q9 ? 9 : 19;
-  if (cells * mix->nc * Q >= 2147483647.0) return lbm_fail(LBM_ERR_ARG, "box too large for 32-bit plane indexing");
+  const double Qd = prm->lattice == LBM_D2Q9 ? 9.0 : 19.0;
+  if (cells * 8.0 * Qd >= 4294967295.0)   // one component's planes are addressed with 32-bit offsets
+    return lbm_fail(LBM_ERR_ARG, "box too large: one component's population planes must stay below 4 GiB");
   if (!(prm->tau > 0.5)) return lbm_fail(LBM_ERR_ARG, "tau must exceed 0.5");
   if (!(prm->G < 0.0)) return lbm_fail(LBM_ERR_ARG, "G must be negative");
   if (!(prm->T > 0.0)) return lbm_fail(LBM_ERR_ARG, "T must be positive");
@@ -465,6 +148,7 @@ lbm_status validate(const lbm_mixture* mix, const lbm_params* prm) {
     for (int j = 0; j < mix->nc; ++j)
       if (mix->k[i][j] != mix->k[j][i]) return lbm_fail(LBM_ERR_ARG, "k must be symmetric");
   }
+  const int Q = prm->lattice == LBM_D2Q9 ? 9 : 19;
   if (prm->collision == LBM_MRT)
     for (int k = 0; k < Q; ++k)
       if (!(prm->mrt_s[k] >= 0.0 && prm->mrt_s[k] < 2.0)) return lbm_fail(LBM_ERR_ARG, "MRT rate %d outside [0, 2)", k);
@@ -480,6 +164,36 @@ void fill_mrt(const lbm_params* prm, KParams* kp) {
 lbm_status hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) return lbm_fail(LBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
   return LBM_OK;
+}
+
+// Enqueue one step; mark(k) runs after every psi (k = 0) / collide (k = 1) launch.
+template <typename Mark>
+void enqueue_step(lbm_ctx* c, Mark mark) {
+  const Bufs& in = c->pops[c->cur];
+  const Bufs& out = c->pops[1 - c->cur];
+  const int np = c->kp.nplanes;
+  if (c->prm.schedule == LBM_SCHED_TWO_PASS || c->slab >= np) {
+    c->ops.psi(c->kp, in, c->sc, 0, np, c->stream);
+    mark(0);
+    c->ops.collide(c->kp, in, out, c->sc, 0, np, c->stream);
+    mark(1);
+  } else {
+    for (int m0 = 0; m0 < np; m0 += c->slab) {
+      const int n = std::min(c->slab, np - m0);
+      if (n + 2 >= np) c->ops.psi(c->kp, in, c->sc, 0, np, c->stream);
+      else c->ops.psi(c->kp, in, c->sc, m0 == 0 ? np - 1 : m0 - 1, n + 2, c->stream);
+      mark(0);
+      c->ops.collide(c->kp, in, out, c->sc, m0, n, c->stream);
+      mark(1);
+    }
+  }
+  c->cur = 1 - c->cur;
+}
+
+int launches_per_step(const lbm_ctx* c) {
+  const int np = c->kp.nplanes;
+  if (c->prm.schedule == LBM_SCHED_TWO_PASS || c->slab >= np) return 2;
+  return 2 * ((np + c->slab - 1) / c->slab);
 }
 
 }  // namespace
@@ -521,6 +235,7 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
     c->pops[k].p1 = prm->storage == LBM_F64 ? nullptr : base + L.pop1[k];
   }
   c->psi = (double*)(base + L.psi);
+  c->sc.psi = c->psi;
   c->partials = (double*)(base + L.partials);
   c->totals = (double*)(base + L.totals);
   c->err = (int*)(base + L.err);
@@ -532,8 +247,8 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
   kp.ny = prm->ny;
   kp.nz = prm->nz;
   kp.cells = (int)c->cells;
-  kp.collision = prm->collision;
-  kp.forcing = prm->forcing;
+  kp.plane_cells = prm->lattice == LBM_D2Q9 ? prm->nx : prm->nx * prm->ny;
+  kp.nplanes = prm->lattice == LBM_D2Q9 ? prm->ny : prm->nz;
   kp.RT = mix->R * prm->T;
   kp.G = prm->G;
   kp.beta = prm->beta;
@@ -552,8 +267,16 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
   }
   for (int d = 0; d < 3; ++d) kp.accel[d] = (d < c->D) ? prm->accel[d] : 0.0;
   kp.err = c->err;
-  c->ops = ops_for(prm->lattice, mix->nc, prm->storage);
-  c->fshape = fused_shape(prm->lattice, prm->nx, prm->ny, prm->nz);
+  c->ops = prm->lattice == LBM_D2Q9 ? ops_d2q9(mix->nc, prm->storage, prm->collision, prm->forcing)
+                                    : ops_d3q19(mix->nc, prm->storage, prm->collision, prm->forcing);
+  if (prm->slab_planes > 0) {
+    c->slab = prm->slab_planes;
+  } else {
+    // about 64 MiB of population input (+ base) per slab
+    const double plane_bytes = (double)kp.plane_cells * mix->nc *
+                               (c->Q * (double)storage_bytes(prm->storage) + (prm->storage == LBM_F64 ? 0.0 : 4.0));
+    c->slab = std::max(1, (int)((64.0 * 1048576.0) / plane_bytes));
+  }
 
   st = hip_check(hipMemsetAsync(c->err, 0, sizeof(int), c->stream), "hipMemsetAsync(err)");
   if (st != LBM_OK) {
@@ -572,14 +295,50 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
 
 extern "C" lbm_status lbm_step(lbm_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return lbm_fail(LBM_ERR_ARG, "bad lbm_step arguments");
-  for (int i = 0; i < nsteps; ++i) {
-    const Bufs& in = c->pops[c->cur];
-    const Bufs& out = c->pops[1 - c->cur];
-    if (c->prm.schedule == LBM_SCHED_FUSED) c->ops.step_fused(c->kp, in, out, c->fshape, c->stream);
-    else c->ops.step_two_pass(c->kp, in, out, c->psi, c->stream);
-    c->cur = 1 - c->cur;
-  }
+  for (int i = 0; i < nsteps; ++i) enqueue_step(c, [](int) {});
   return hip_check(hipGetLastError(), "step launch");
+}
+
+extern "C" lbm_status lbm_step_timed(lbm_ctx* c, int nsteps, double* kernel_ms) {
+  if (!c || nsteps < 0 || !kernel_ms) return lbm_fail(LBM_ERR_ARG, "bad lbm_step_timed arguments");
+  kernel_ms[0] = kernel_ms[1] = 0.0;
+  if (nsteps == 0) return LBM_OK;
+  const int nev = nsteps * launches_per_step(c) + 1;
+  hipEvent_t* ev = new (std::nothrow) hipEvent_t[nev];
+  int* kind = new (std::nothrow) int[nev];
+  if (!ev || !kind) {
+    delete[] ev;
+    delete[] kind;
+    return lbm_fail(LBM_ERR_ARG, "out of host memory");
+  }
+  int made = 0;
+  lbm_status st = LBM_OK;
+  for (; made < nev; ++made) {
+    st = hip_check(hipEventCreate(&ev[made]), "hipEventCreate");
+    if (st != LBM_OK) break;
+  }
+  if (st == LBM_OK) {
+    int e = 0;
+    hipEventRecord(ev[e++], c->stream);
+    for (int i = 0; i < nsteps; ++i)
+      enqueue_step(c, [&](int k) {
+        kind[e] = k;
+        hipEventRecord(ev[e++], c->stream);
+      });
+    st = hip_check(hipGetLastError(), "step launch");
+    if (st == LBM_OK) st = hip_check(hipEventSynchronize(ev[nev - 1]), "hipEventSynchronize");
+    if (st == LBM_OK) {
+      for (int k = 1; k < nev; ++k) {
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, ev[k - 1], ev[k]);
+        kernel_ms[kind[k]] += ms;
+      }
+    }
+  }
+  for (int k = 0; k < made; ++k) hipEventDestroy(ev[k]);
+  delete[] ev;
+  delete[] kind;
+  return st;
 }
 
 extern "C" lbm_status lbm_check(lbm_ctx* c) {
@@ -600,12 +359,12 @@ extern "C" lbm_status lbm_clear_error(lbm_ctx* c) {
 
 extern "C" lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, double* psi, double* totals) {
   if (!c) return lbm_fail(LBM_ERR_ARG, "ctx is NULL");
-  c->ops.moments(c->kp, c->pops[c->cur], c->psi, rho, u, p, psi, c->partials, c->stream);
+  c->ops.moments(c->kp, c->pops[c->cur], c->sc, rho, u, p, psi, c->partials, c->stream);
   lbm_status st = hip_check(hipGetLastError(), "moments launch");
   if (st != LBM_OK) return st;
   if (totals) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partials,
-                       nblocks((int)c->cells), c->K, c->totals);
+                       nblocks_for((int)c->cells), c->K, c->totals);
     st = hip_check(hipGetLastError(), "finish launch");
     if (st != LBM_OK) return st;
     st = hip_check(hipMemcpyAsync(totals, c->totals, sizeof(double) * c->K, hipMemcpyDeviceToHost, c->stream),

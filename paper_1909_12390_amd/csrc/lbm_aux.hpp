@@ -1,0 +1,146 @@
+// Kernels around the step: macroscopic fields with per-block partial sums for the
+// conservation totals, and import / export / equilibrium initialisation of the
+// population state (pull layout: the stored direction a at cell y is the
+// population that arrives at y + e_a).
+#pragma once
+#include "lbm_kernels.hpp"
+
+namespace lbmk {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int K>
+__device__ __forceinline__ void block_partials(double* vals, double* partials) {
+  __shared__ double red[kBlock / 64][K];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double s = wave_sum(vals[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+    partials[(size_t)blockIdx.x * K + threadIdx.x] = s;
+  }
+}
+
+// rbar_s, u = (j + F_total/2)/rho, p_EOS and psi of every cell; per-block partial
+// sums of [mass_s (nc), momentum (D), force (D)] in a fixed order.
+template <int LAT, int NC, int ST>
+__global__ __launch_bounds__(kBlock) void k_moments(KParams P, Pops<ST> in, const double* __restrict__ psi,
+                                                   double* rho_out, double* u_out, double* p_out, double* psi_out,
+                                                   double* partials) {
+  using V = VS<LAT>;
+  using R = typename Pops<ST>::R;
+  constexpr int D = V::D, K = NC + 2 * D;
+  double vals[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) vals[k] = 0.0;
+  unsigned cell;
+  if (launch_cell(P, 0, P.nplanes, &cell)) {
+    const Coord c = make_coord(cell, P);
+    double rb[NC], rho = 0.0;
+    R jr[3] = {0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+      rb[s] = pull_moments<LAT, ST>(P, in, s, c, jr);
+      rho += rb[s];
+    }
+    const double j[3] = {(double)jr[0], (double)jr[1], (double)jr[2]};
+    double F[3];
+    const double ps = psi[cell];
+    force_at<LAT>(P, ps, [&](int a) { return psi[c.at(V::cx(a), V::cy(a), V::cz(a))]; }, F);
+    double Ft[3], u[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Ft[d] = F[d] + rho * P.accel[d];
+      u[d] = (j[d] + 0.5 * Ft[d]) / rho;
+    }
+    if (rho_out)
+#pragma unroll
+      for (int s = 0; s < NC; ++s) rho_out[(size_t)s * P.cells + cell] = rb[s];
+    if (u_out)
+#pragma unroll
+      for (int d = 0; d < D; ++d) u_out[(size_t)d * P.cells + cell] = u[d];
+    if (p_out) {
+      double Bn;
+      p_out[cell] = eos_pressure<NC>(P, rb, &Bn);
+    }
+    if (psi_out) psi_out[cell] = ps;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) vals[s] = rb[s];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      vals[NC + d] = j[d] + 0.5 * Ft[d];
+      vals[NC + D + d] = F[d];
+    }
+  }
+  block_partials<K>(vals, partials);
+}
+
+// canonical post-streaming populations float64 [nc][Q][cells]
+template <int LAT, int NC, int ST>
+__global__ __launch_bounds__(kBlock) void k_export(KParams P, Pops<ST> in, double* __restrict__ f) {
+  using V = VS<LAT>;
+  using R = typename Pops<ST>::R;
+  unsigned cell;
+  if (!launch_cell(P, 0, P.nplanes, &cell)) return;
+  const Coord c = make_coord(cell, P);
+#pragma unroll 1
+  for (int s = 0; s < NC; ++s) {
+    const auto cv = in.comp(s, V::Q, P.cells);
+#pragma unroll
+    for (int a = 0; a < V::Q; ++a)
+      f[(size_t)(s * V::Q + a) * P.cells + cell] = (double)cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+  }
+}
+
+// mode 0: import canonical f (float64 [nc][Q][cells]);  mode 1: equilibrium of
+// rho0 [nc][cells] and u0 [D][cells] (u0 may be NULL).  The base of the offset
+// formats is the sum of the Q values stored at the cell.
+template <int LAT, int NC, int ST>
+__global__ __launch_bounds__(kBlock) void k_import(KParams P, Pops<ST> out, const double* __restrict__ f,
+                                                  const double* __restrict__ rho0, const double* __restrict__ u0,
+                                                  int mode) {
+  using V = VS<LAT>;
+  using R = typename Pops<ST>::R;
+  constexpr int Q = V::Q;
+  unsigned cell;
+  if (!launch_cell(P, 0, P.nplanes, &cell)) return;
+  const Coord c = make_coord(cell, P);
+#pragma unroll 1
+  for (int s = 0; s < NC; ++s) {
+    double v[Q];
+    double sum = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const unsigned dst = c.at(V::cx(a), V::cy(a), V::cz(a));
+      if (mode == 0) {
+        v[a] = f[(size_t)(s * Q + a) * P.cells + dst];
+      } else {
+        const double r = rho0[(size_t)s * P.cells + dst];
+        double ux = 0.0, uy = 0.0, uz = 0.0;
+        if (u0) {
+          ux = u0[dst];
+          uy = u0[(size_t)P.cells + dst];
+          if (V::D == 3) uz = u0[(size_t)2 * P.cells + dst];
+        }
+        v[a] = feq<LAT, double>(a, r, ux, uy, uz, ux * ux + uy * uy + uz * uz);
+      }
+      sum += v[a];
+    }
+    R vr[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) vr[a] = (R)v[a];
+    out.comp(s, Q, P.cells).template put_all<Q>(cell, vr, (R)sum, [](int a) { return (R)V::w(a); });
+  }
+}
+
+}  // namespace lbmk

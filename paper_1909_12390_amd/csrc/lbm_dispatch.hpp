@@ -1,0 +1,115 @@
+// Launchers of the step and auxiliary kernels, instantiated per (lattice, nc,
+// storage, collision, forcing) in the per-lattice translation units.
+#pragma once
+#include "lbm_aux.hpp"
+
+namespace lbmk {
+
+struct Bufs {
+  void* p0;   // F64: f;  offset formats: base
+  void* p1;   // offset formats: r
+};
+
+// scratch field of one step: psi
+struct StepScratch {
+  double* psi;
+};
+
+struct Ops {
+  void (*psi)(const KParams&, const Bufs&, const StepScratch&, int, int, hipStream_t);
+  void (*collide)(const KParams&, const Bufs&, const Bufs&, const StepScratch&, int, int, hipStream_t);
+  void (*moments)(const KParams&, const Bufs&, const StepScratch&, double*, double*, double*, double*, double*,
+                  hipStream_t);
+  void (*exp)(const KParams&, const Bufs&, double*, hipStream_t);
+  void (*imp)(const KParams&, const Bufs&, const double*, const double*, const double*, int, hipStream_t);
+};
+
+inline int nblocks_for(int cells) { return (cells + kBlock - 1) / kBlock; }
+
+template <int ST>
+inline Pops<ST> make_pops(const Bufs& b);
+template <>
+inline Pops<LBM_F64> make_pops<LBM_F64>(const Bufs& b) {
+  Pops<LBM_F64> p;
+  p.f = (double*)b.p0;
+  return p;
+}
+template <>
+inline Pops<LBM_F32_OFS> make_pops<LBM_F32_OFS>(const Bufs& b) {
+  Pops<LBM_F32_OFS> p;
+  p.base = (float*)b.p0;
+  p.r = (float*)b.p1;
+  return p;
+}
+template <>
+inline Pops<LBM_F16_OFS> make_pops<LBM_F16_OFS>(const Bufs& b) {
+  Pops<LBM_F16_OFS> p;
+  p.base = (float*)b.p0;
+  p.r = (__half*)b.p1;
+  return p;
+}
+
+template <int LAT, int NC, int ST, int COLL, int FORC>
+struct OpsImpl {
+  static void psi(const KParams& P, const Bufs& in, const StepScratch& sc, int plane0, int np, hipStream_t st) {
+    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(nblocks_for(np * P.plane_cells)), dim3(kBlock), 0, st, P,
+                       make_pops<ST>(in), sc.psi, plane0, np);
+  }
+  static void collide(const KParams& P, const Bufs& in, const Bufs& out, const StepScratch& sc, int plane0,
+                      int np, hipStream_t st) {
+    const int nb = (np * P.plane_cells + kCells - 1) / kCells;
+    hipLaunchKernelGGL((k_collide<LAT, NC, ST, COLL, FORC>), dim3(nb), dim3(kCells * NC), 0, st, P,
+                       make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
+  }
+  static void moments(const KParams& P, const Bufs& in, const StepScratch& sc, double* rho, double* u, double* p,
+                      double* psi_out, double* partials, hipStream_t st) {
+    const int nb = nblocks_for(P.cells);
+    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(nb), dim3(kBlock), 0, st, P, make_pops<ST>(in), sc.psi, 0,
+                       P.nplanes);
+    hipLaunchKernelGGL((k_moments<LAT, NC, ST>), dim3(nb), dim3(kBlock), 0, st, P, make_pops<ST>(in),
+                       (const double*)sc.psi, rho, u, p, psi_out, partials);
+  }
+  static void exp(const KParams& P, const Bufs& in, double* f, hipStream_t st) {
+    hipLaunchKernelGGL((k_export<LAT, NC, ST>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
+                       make_pops<ST>(in), f);
+  }
+  static void imp(const KParams& P, const Bufs& out, const double* f, const double* rho0, const double* u0, int mode,
+                  hipStream_t st) {
+    hipLaunchKernelGGL((k_import<LAT, NC, ST>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
+                       make_pops<ST>(out), f, rho0, u0, mode);
+  }
+  static Ops ops() { return Ops{&psi, &collide, &moments, &exp, &imp}; }
+};
+
+template <int LAT, int NC, int ST>
+Ops ops_cf(int coll, int forc) {
+  if (coll == LBM_BGK) {
+    return forc == LBM_GUO ? OpsImpl<LAT, NC, ST, LBM_BGK, LBM_GUO>::ops() : OpsImpl<LAT, NC, ST, LBM_BGK, LBM_EDM>::ops();
+  }
+  return forc == LBM_GUO ? OpsImpl<LAT, NC, ST, LBM_MRT, LBM_GUO>::ops() : OpsImpl<LAT, NC, ST, LBM_MRT, LBM_EDM>::ops();
+}
+
+template <int LAT, int NC>
+Ops ops_st(int st, int coll, int forc) {
+  switch (st) {
+    case LBM_F64: return ops_cf<LAT, NC, LBM_F64>(coll, forc);
+    case LBM_F32_OFS: return ops_cf<LAT, NC, LBM_F32_OFS>(coll, forc);
+    default: return ops_cf<LAT, NC, LBM_F16_OFS>(coll, forc);
+  }
+}
+
+template <int LAT>
+Ops ops_lat(int nc, int st, int coll, int forc) {
+  switch (nc) {
+    case 1: return ops_st<LAT, 1>(st, coll, forc);
+    case 2: return ops_st<LAT, 2>(st, coll, forc);
+    case 3: return ops_st<LAT, 3>(st, coll, forc);
+    default: return ops_st<LAT, 4>(st, coll, forc);
+  }
+}
+
+// defined in lbm_d2q9.hip / lbm_d3q19.hip
+Ops ops_d2q9(int nc, int st, int coll, int forc);
+Ops ops_d3q19(int nc, int st, int coll, int forc);
+
+}  // namespace lbmk

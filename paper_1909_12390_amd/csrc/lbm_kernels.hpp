@@ -1,19 +1,23 @@
-// Device code of one time step (Sec. 3.4 order) shared by the two-pass and fused
-// schedules: population storage/decoding, the mixture EOS and psi (float64), the
-// force stencil, the split and the per-component collision with forcing.
+// Device code of one time step (Sec. 3.4 order): population storage and decoding,
+// the mixture EOS and psi (float64), the force stencil, the split and the
+// per-component collision with forcing, plus the kernels built from them.
 #pragma once
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "lattice.hpp"
 #include "lbm.h"
 
 namespace lbmk {
 
+constexpr int kBlock = 256;
+
 // Per-run constants handed to every kernel by value.
 struct KParams {
   int nx, ny, nz, cells;
-  int collision, forcing;
+  int plane_cells, nplanes;        // planes of the slowest axis (y in 2-D, z in 3-D)
   double RT;                       // R * T
   double G, beta, omega;           // omega = 1 / tau
   double aa[LBM_MAX_NC][LBM_MAX_NC];  // sqrt(a_i alpha_i a_j alpha_j)(1 - zeta_ij)
@@ -25,11 +29,49 @@ struct KParams {
   int* err;                        // device error flag (set to 1 on a domain violation)
 };
 
+// Load / store one element at a 32-bit byte offset from an array base held in
+// scalar registers (used for psi).  Every array stays below 4 GiB (host check).
+template <typename T>
+__device__ __forceinline__ T ldb(const T* base, unsigned byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// Raw buffer access for the population planes: a scalar buffer descriptor per
+// component, the per-lane byte offset of the cell in a vector register and the
+// byte offset of the direction plane in a scalar register.  Descriptor word 3 is
+// the gfx9 raw-buffer format (32-bit data format, no swizzle, no index stride);
+// num_records bounds every access to the component's planes.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double bload(rsrc_t r, unsigned voff, unsigned soff, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ float bload(rsrc_t r, unsigned voff, unsigned soff, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ float bload(rsrc_t r, unsigned voff, unsigned soff, __half) {
+  return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+}
+__device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                        r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, __half v) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, 0);
+}
+
 // ---------------------------------------------------------------------------
 // Population storage.  Layout [nc][Q][cells] for the per-direction planes; the
 // offset formats add a float base [nc][cells] per cell and component:
 //   stored value of direction a at cell y (the post-collision population that
 //   streams to y + e_a) = base(y) * (w_a + r_a(y)).
+// comp(s) returns a view of component s; get(a, idx) decodes direction a at
+// cell idx, put_all stores the Q post-collision values (and the base) of a cell.
 // ---------------------------------------------------------------------------
 template <int ST>
 struct Pops;
@@ -38,13 +80,22 @@ template <>
 struct Pops<LBM_F64> {
   using R = double;   // collision arithmetic
   double* f;
-  __device__ __forceinline__ double get(int s, int a, int Q, int idx, int cells, double) const {
-    return f[(size_t)(s * Q + a) * cells + idx];
+  struct View {
+    rsrc_t rf;
+    unsigned plane;   // bytes per direction plane
+    __device__ __forceinline__ double get(int a, unsigned idx, double) const {
+      return bload(rf, idx * 8u, (unsigned)a * plane, 0.0);
+    }
+    template <int Q, typename W>
+    __device__ __forceinline__ void put_all(unsigned idx, const double* v, double, W) const {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) bstore(rf, idx * 8u, (unsigned)a * plane, v[a]);
+    }
+  };
+  __device__ __forceinline__ View comp(int s, int Q, int cells) const {
+    const unsigned plane = (unsigned)cells * 8u;
+    return View{make_rsrc(f + (size_t)s * Q * cells, (unsigned)Q * plane), plane};
   }
-  __device__ __forceinline__ void put(int s, int a, int Q, int idx, int cells, double v, double, double) const {
-    f[(size_t)(s * Q + a) * cells + idx] = v;
-  }
-  __device__ __forceinline__ void put_base(int, int, int, double) const {}
 };
 
 template <typename H>
@@ -52,21 +103,31 @@ struct OffsetPops {
   using R = float;
   float* base;
   H* r;
-  __device__ __forceinline__ float get(int s, int a, int Q, int idx, int cells, float w) const {
-    return base[(size_t)s * cells + idx] * (w + load(r + (size_t)(s * Q + a) * cells + idx));
+  struct View {
+    rsrc_t rb, rr;
+    unsigned plane;   // bytes per direction plane of r
+    __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
+      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
+    }
+    // v: post-collision populations; b: this cell's base (rbar_s); w(a): weights
+    template <int Q, typename W>
+    __device__ __forceinline__ void put_all(unsigned idx, const float* v, float b, W w) const {
+      bstore(rb, idx * 4u, 0u, b);
+      const float inv = (b != 0.0f) ? 1.0f / b : 0.0f;
+#pragma unroll
+      for (int a = 0; a < Q; ++a)
+        bstore(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, enc(v[a] * inv - (b != 0.0f ? w(a) : 0.0f)));
+    }
+  };
+  __device__ __forceinline__ View comp(int s, int Q, int cells) const {
+    const unsigned plane = (unsigned)cells * (unsigned)sizeof(H);
+    return View{make_rsrc(base + (size_t)s * cells, (unsigned)cells * 4u),
+                make_rsrc(r + (size_t)s * Q * cells, (unsigned)Q * plane), plane};
   }
-  // v: post-collision population; b: the base this cell stores; w: weight of a
-  __device__ __forceinline__ void put(int s, int a, int Q, int idx, int cells, float v, float b, float w) const {
-    const float rr = (b != 0.0f) ? v / b - w : 0.0f;
-    store(r + (size_t)(s * Q + a) * cells + idx, rr);
+  static __device__ __forceinline__ H enc(float v) {
+    if constexpr (std::is_same<H, __half>::value) return __float2half_rn(v);
+    else return v;
   }
-  __device__ __forceinline__ void put_base(int s, int idx, int cells, float b) const {
-    base[(size_t)s * cells + idx] = b;
-  }
-  static __device__ __forceinline__ float load(const float* p) { return *p; }
-  static __device__ __forceinline__ float load(const __half* p) { return __half2float(*p); }
-  static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
-  static __device__ __forceinline__ void store(__half* p, float v) { *p = __float2half_rn(v); }
 };
 
 template <>
@@ -74,30 +135,46 @@ struct Pops<LBM_F32_OFS> : OffsetPops<float> {};
 template <>
 struct Pops<LBM_F16_OFS> : OffsetPops<__half> {};
 
-// Cell coordinates with periodic neighbours.
+// Cell coordinates with periodic neighbours; at(dx,dy,dz) is the linear index of
+// the neighbour at offset (dx, dy, dz).
 struct Coord {
-  int x, y, z, xm, xp, ym, yp, zm, zp;
-  __device__ __forceinline__ int at(int dx, int dy, int dz, int nx, int ny) const {
-    const int xx = dx == 0 ? x : (dx > 0 ? xp : xm);
-    const int yy = dy == 0 ? y : (dy > 0 ? yp : ym);
-    const int zz = dz == 0 ? z : (dz > 0 ? zp : zm);
-    return (zz * ny + yy) * nx + xx;
+  unsigned xs[3], ys[3], zs[3];   // [x-1, x, x+1], row offsets, plane offsets
+  __device__ __forceinline__ unsigned at(int dx, int dy, int dz) const {
+    return zs[dz + 1] + ys[dy + 1] + xs[dx + 1];
   }
 };
 
-__device__ __forceinline__ Coord make_coord(int cell, const KParams& P) {
+__device__ __forceinline__ Coord make_coord(unsigned cell, const KParams& P) {
+  const unsigned nx = P.nx, ny = P.ny, nz = P.nz;
+  const unsigned x = cell % nx;
+  const unsigned t = cell / nx;
+  const unsigned y = t % ny;
+  const unsigned z = t / ny;
   Coord c;
-  c.x = cell % P.nx;
-  const int t = cell / P.nx;
-  c.y = t % P.ny;
-  c.z = t / P.ny;
-  c.xm = c.x == 0 ? P.nx - 1 : c.x - 1;
-  c.xp = c.x == P.nx - 1 ? 0 : c.x + 1;
-  c.ym = c.y == 0 ? P.ny - 1 : c.y - 1;
-  c.yp = c.y == P.ny - 1 ? 0 : c.y + 1;
-  c.zm = c.z == 0 ? P.nz - 1 : c.z - 1;
-  c.zp = c.z == P.nz - 1 ? 0 : c.z + 1;
+  c.xs[0] = x == 0 ? nx - 1 : x - 1;
+  c.xs[1] = x;
+  c.xs[2] = x == nx - 1 ? 0 : x + 1;
+  c.ys[0] = (y == 0 ? ny - 1 : y - 1) * nx;
+  c.ys[1] = y * nx;
+  c.ys[2] = (y == ny - 1 ? 0 : y + 1) * nx;
+  const unsigned pl = nx * ny;
+  c.zs[0] = (z == 0 ? nz - 1 : z - 1) * pl;
+  c.zs[1] = z * pl;
+  c.zs[2] = (z == nz - 1 ? 0 : z + 1) * pl;
   return c;
+}
+
+// Linear index of the k-th cell of a launch covering `nplanes` planes starting at
+// plane `plane0` (periodic in the plane index); false past the end.
+__device__ __forceinline__ bool launch_cell(const KParams& P, int plane0, int nplanes, unsigned* cell) {
+  const unsigned lin = blockIdx.x * kBlock + threadIdx.x;
+  const unsigned pc = P.plane_cells;
+  if (lin >= (unsigned)nplanes * pc) return false;
+  const unsigned k = lin / pc;
+  unsigned plane = plane0 + k;
+  if (plane >= (unsigned)P.nplanes) plane -= P.nplanes;
+  *cell = plane * pc + (lin - k * pc);
+  return true;
 }
 
 __device__ __forceinline__ void flag_error(const KParams& P) { *P.err = 1; }
@@ -140,6 +217,59 @@ __device__ __forceinline__ double eos_psi(const KParams& P, const double* rb) {
   return sqrt(X);
 }
 
+// Density of component s at the cell and its momentum contribution, summed in the
+// collision precision R (float64 for float64 storage; float32 for the offset
+// formats, whose decoded populations carry float32 precision), returned as float64.
+template <int LAT, int ST>
+__device__ __forceinline__ double pull_moments(const KParams& P, const Pops<ST>& in, int s, const Coord& c,
+                                               typename Pops<ST>::R* j) {
+  using V = VS<LAT>;
+  using R = typename Pops<ST>::R;
+  const auto cv = in.comp(s, V::Q, P.cells);
+  R acc = 0;
+  R jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int a = 0; a < V::Q; ++a) {
+    const R v = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+    acc += v;
+    if (V::cx(a)) jx += (R)V::cx(a) * v;
+    if (V::cy(a)) jy += (R)V::cy(a) * v;
+    if (V::cz(a)) jz += (R)V::cz(a) * v;
+  }
+  j[0] += jx;
+  j[1] += jy;
+  j[2] += jz;
+  return (double)acc;
+}
+
+// total force of Eq. (coupledMCforce) at one cell from psi(x) and its neighbours
+template <int LAT, typename PsiAt>
+__device__ __forceinline__ void force_at(const KParams& P, double ps, PsiAt psi_at, double* F) {
+  using V = VS<LAT>;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  const double hb = 0.5 * (1.0 - P.beta);
+#pragma unroll
+  for (int a = 1; a < V::Q; ++a) {
+    const double pn = psi_at(a);
+    const double t = V::w(a) * pn * (P.beta * ps + hb * pn);
+    if (V::cx(a)) fx += V::cx(a) * t;
+    if (V::cy(a)) fy += V::cy(a) * t;
+    if (V::cz(a)) fz += V::cz(a) * t;
+  }
+  F[0] = -P.G * fx;
+  F[1] = -P.G * fy;
+  F[2] = -P.G * fz;
+}
+
+// Compile-time loop: f(integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(fn);
+  }
+}
+
 // Equilibrium of Eq. (equilibrium a) for direction a.
 template <int LAT, typename R>
 __device__ __forceinline__ R feq(int a, R rho, R ux, R uy, R uz, R uu) {
@@ -148,89 +278,13 @@ __device__ __forceinline__ R feq(int a, R rho, R ux, R uy, R uz, R uu) {
   return rho * (R)V::w(a) * ((R)1 + (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * uu);
 }
 
-// Collision with forcing of one component followed by the store of its Q
-// post-collision populations at `cell` (pull streaming: the next step reads
-// direction a of this cell from the neighbour at cell + e_a).
-//   f   : populations of component s at this cell (time t, post-streaming)
-//   rs  : rbar_s;  u: shared velocity (Guo: (j+F/2)/rho; EDM: j/rho)
-//   Fs  : F_s = chi_s F + rbar_s g (Guo);  du: gamma_s F / Gamma + g (EDM)
-template <int LAT, int ST>
-__device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& out, int s, int cell,
-                                              typename Pops<ST>::R* f, double rs_d, const double* u_d,
-                                              const double* Fs_d, const double* du_d) {
-  using V = VS<LAT>;
-  using R = typename Pops<ST>::R;
-  constexpr int Q = V::Q;
-  const R rs = (R)rs_d;
-  const R ux = (R)u_d[0], uy = (R)u_d[1], uz = (R)u_d[2];
-  const R uu = ux * ux + uy * uy + uz * uz;
-  R fe[Q], src[Q];
-  if (P.forcing == LBM_GUO) {
-    const R Fx = (R)Fs_d[0], Fy = (R)Fs_d[1], Fz = (R)Fs_d[2];
-    const R uF = ux * Fx + uy * Fy + uz * Fz;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      fe[a] = feq<LAT, R>(a, rs, ux, uy, uz, uu);
-      const R cx = (R)V::cx(a), cy = (R)V::cy(a), cz = (R)V::cz(a);
-      const R eu = cx * ux + cy * uy + cz * uz;
-      const R eF = cx * Fx + cy * Fy + cz * Fz;
-      // w_a [ (e_a - u)/cs2 + (e_a.u) e_a / cs4 ] . F_s  (Eq. (equilibrium b) shape)
-      src[a] = (R)V::w(a) * ((R)3 * (eF - uF) + (R)9 * eu * eF);
-    }
-  } else {
-    const R vx = ux + (R)du_d[0], vy = uy + (R)du_d[1], vz = uz + (R)du_d[2];
-    const R vv = vx * vx + vy * vy + vz * vz;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      fe[a] = feq<LAT, R>(a, rs, ux, uy, uz, uu);
-      src[a] = feq<LAT, R>(a, rs, vx, vy, vz, vv) - fe[a];   // exact-difference term
-    }
-  }
-  R fo[Q];
-  if (P.collision == LBM_BGK) {
-    const R om = (R)P.omega;
-    const R gpre = (P.forcing == LBM_GUO) ? (R)1 - (R)0.5 * om : (R)1;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) fo[a] = f[a] - om * (f[a] - fe[a]) + gpre * src[a];
-  } else {
-    // f* = f + src - M^T diag(s_k / |M_k|^2) M (f - feq + h src), h = 1/2 for Guo, 0 for EDM
-    const R h = (P.forcing == LBM_GUO) ? (R)0.5 : (R)0;
-    R d[Q];
-#pragma unroll
-    for (int a = 0; a < Q; ++a) d[a] = f[a] - fe[a] + h * src[a];
-    R m[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      R acc = 0;
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        const double mk = V::mrow(k, a);
-        if (mk != 0.0) acc += (R)mk * d[a];
-      }
-      m[k] = acc * (R)P.s_over_n[k];
-    }
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      R acc = 0;
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        const double mk = V::mrow(k, a);
-        if (mk != 0.0) acc += (R)mk * m[k];
-      }
-      fo[a] = f[a] + src[a] - acc;
-    }
-  }
-  const R base = rs;
-  out.put_base(s, cell, P.cells, base);
-#pragma unroll
-  for (int a = 0; a < Q; ++a) out.put(s, a, Q, cell, P.cells, fo[a], base, (R)V::w(a));
-}
-
-// Shared per-cell macroscopic work after the populations are known:
-// returns u, Gamma and fills F_s / du for each component.
-template <int NC>
+// Velocity shared by the components and the per-component forcing inputs:
+//   Guo: u = (j + F_total/2)/rho, Fs = chi_s F + rbar_s g;
+//   EDM: u = j/rho, du_s = gamma_s F / Gamma + g (= F_s / rbar_s);
+// chi_s = gamma_s rbar_s / Gamma, Gamma = sum gamma_i rbar_i (Eq. distributionforce).
+template <int NC, int FORC>
 __device__ __forceinline__ void cell_forces(const KParams& P, const double* rb, const double* j, const double* F,
-                                            double* u, double (*Fs)[3], double (*du)[3]) {
+                                            double* u, double (*Fs)[3]) {
   double rho = 0.0, Gam = 0.0;
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
@@ -239,7 +293,7 @@ __device__ __forceinline__ void cell_forces(const KParams& P, const double* rb, 
   }
   if (!(Gam > 0.0)) flag_error(P);
   const double g0 = P.accel[0], g1 = P.accel[1], g2 = P.accel[2];
-  if (P.forcing == LBM_GUO) {
+  if (FORC == LBM_GUO) {
     u[0] = (j[0] + 0.5 * (F[0] + rho * g0)) / rho;
     u[1] = (j[1] + 0.5 * (F[1] + rho * g1)) / rho;
     u[2] = (j[2] + 0.5 * (F[2] + rho * g2)) / rho;
@@ -248,16 +302,289 @@ __device__ __forceinline__ void cell_forces(const KParams& P, const double* rb, 
     u[1] = j[1] / rho;
     u[2] = j[2] / rho;
   }
+  const double iG = 1.0 / Gam;
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
-    const double c = P.gamma[s] / Gam;   // chi_s = gamma_s rbar_s / Gamma
-    Fs[s][0] = c * rb[s] * F[0] + rb[s] * g0;
-    Fs[s][1] = c * rb[s] * F[1] + rb[s] * g1;
-    Fs[s][2] = c * rb[s] * F[2] + rb[s] * g2;
-    du[s][0] = c * F[0] + g0;
-    du[s][1] = c * F[1] + g1;
-    du[s][2] = c * F[2] + g2;
+    const double c = P.gamma[s] * iG;
+    if (FORC == LBM_GUO) {
+      Fs[s][0] = c * rb[s] * F[0] + rb[s] * g0;
+      Fs[s][1] = c * rb[s] * F[1] + rb[s] * g1;
+      Fs[s][2] = c * rb[s] * F[2] + rb[s] * g2;
+    } else {
+      Fs[s][0] = c * F[0] + g0;
+      Fs[s][1] = c * F[1] + g1;
+      Fs[s][2] = c * F[2] + g2;
+    }
   }
+}
+
+// Collision with forcing of one component followed by the store of its Q
+// post-collision populations at `cell` (pull streaming: the next step reads
+// direction a of this cell from the neighbour at cell + e_a).
+//   f   : populations of component s at this cell (time t, post-streaming)
+//   rs  : rbar_s;  u: shared velocity;  Fs: F_s (Guo) or du_s (EDM)
+// BGK : f* = f - omega (f - feq) + (1 - omega/2) S_guo        | + [feq(u + du) - feq(u)]
+// MRT : f* = f + src - M^T diag(s_k/|M_k|^2) M (f - feq + h src),  h = 1/2 (Guo), 0 (EDM)
+// Everything is evaluated on opposite pairs (a, opp(a)): the equilibrium and the
+// sources split into a part even under e -> -e and an odd part,
+//   feq_a = E + O, feq_opp = E - O,  E = w rs (1 + 9/2 (e.u)^2 - 3/2 u.u), O = 3 w rs e.u,
+//   Guo : w[3(e - u).F + 9 (e.u)(e.F)]  -> even w(9 (e.u)(e.F) - 3 u.F), odd 3 w e.F,
+//   EDM : feq(u + du) - feq(u) = w rs [3 e.du + 9/2 (e.du)(2 e.u + e.du) - 3/2 du.(2u + du)]
+//         -> even w rs (9/2 (e.du)(2 e.u + e.du) - 3/2 du.(2u + du)), odd 3 w rs e.du;
+// MRT even rows act on f_a + f_opp, odd rows on f_a - f_opp; the density row is
+// skipped because sum_a (f - feq + h src) = 0.
+template <int LAT, int ST, int COLL, int FORC>
+__device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& out, int s, unsigned cell,
+                                              const typename Pops<ST>::R* f, typename Pops<ST>::R rs,
+                                              const typename Pops<ST>::R* u3, const typename Pops<ST>::R* F3) {
+  using V = VS<LAT>;
+  using R = typename Pops<ST>::R;
+  constexpr int Q = V::Q;
+  constexpr int NP = (Q - 1) / 2;
+  const R ux = u3[0], uy = u3[1], uz = u3[2];
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R Fx = F3[0], Fy = F3[1], Fz = F3[2];
+  const R uF = ux * Fx + uy * Fy + uz * Fz;                       // Guo: u.F_s
+  const R dvv = Fx * ((R)2 * ux + Fx) + Fy * ((R)2 * uy + Fy) + Fz * ((R)2 * uz + Fz);  // EDM: du.(2u+du)
+  const R base1 = (R)1 - (R)1.5 * uu;
+  // even / odd parts of feq and of the source for velocity a (a > 0) or the rest (a = 0)
+  auto parts = [&](auto A, R& Ev, R& Od, R& sE, R& sO) {
+    constexpr int a = decltype(A)::value;
+    constexpr R cx = V::cx(a), cy = V::cy(a), cz = V::cz(a);
+    const R wr = (R)V::w(a) * rs;
+    const R eu = cx * ux + cy * uy + cz * uz;
+    Ev = wr * (base1 + (R)4.5 * eu * eu);
+    Od = (R)3 * wr * eu;
+    if constexpr (FORC == LBM_GUO) {
+      const R eF = cx * Fx + cy * Fy + cz * Fz;
+      sE = (R)V::w(a) * ((R)9 * eu * eF - (R)3 * uF);
+      sO = (R)3 * (R)V::w(a) * eF;
+    } else {
+      const R ed = cx * Fx + cy * Fy + cz * Fz;
+      sE = wr * ((R)4.5 * ed * ((R)2 * eu + ed) - (R)1.5 * dvv);
+      sO = (R)3 * wr * ed;
+    }
+  };
+  R fo[Q];
+  if constexpr (COLL == LBM_BGK) {
+    const R om = (R)P.omega;
+    const R gpre = (FORC == LBM_GUO) ? (R)1 - (R)0.5 * om : (R)1;
+    {
+      R Ev, Od, sE, sO;
+      parts(std::integral_constant<int, 0>{}, Ev, Od, sE, sO);
+      fo[0] = f[0] - om * (f[0] - Ev) + gpre * sE;
+    }
+    static_for<0, NP>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
+      R Ev, Od, sE, sO;
+      parts(std::integral_constant<int, a>{}, Ev, Od, sE, sO);
+      fo[a] = f[a] - om * (f[a] - (Ev + Od)) + gpre * (sE + sO);
+      fo[b] = f[b] - om * (f[b] - (Ev - Od)) + gpre * (sE - sO);
+    });
+  } else {
+    const R h = (FORC == LBM_GUO) ? (R)0.5 : (R)0;
+    R d0;
+    {
+      R Ev, Od, sE, sO;
+      parts(std::integral_constant<int, 0>{}, Ev, Od, sE, sO);
+      d0 = f[0] - Ev + h * sE;
+      fo[0] = f[0] + sE;
+    }
+    R S[NP], D[NP];
+    static_for<0, NP>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
+      R Ev, Od, sE, sO;
+      parts(std::integral_constant<int, a>{}, Ev, Od, sE, sO);
+      S[p] = (f[a] + f[b]) - (R)2 * Ev + (R)2 * h * sE;   // d_a + d_b
+      D[p] = (f[a] - f[b]) - (R)2 * Od + (R)2 * h * sO;   // d_a - d_b
+      fo[a] = f[a] + (sE + sO);
+      fo[b] = f[b] + (sE - sO);
+    });
+    R m[Q];
+    static_for<1, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      R acc = 0;
+      if constexpr (!row_odd<LAT>(k)) {
+        if constexpr (V::mrow(k, 0) != 0.0) acc += (R)V::mrow(k, 0) * d0;
+        static_for<0, NP>([&](auto Pp) {
+          constexpr int p = decltype(Pp)::value;
+          constexpr double mk = V::mrow(k, V::pair_first(p));
+          if constexpr (mk != 0.0) acc += (R)mk * S[p];
+        });
+      } else {
+        static_for<0, NP>([&](auto Pp) {
+          constexpr int p = decltype(Pp)::value;
+          constexpr double mk = V::mrow(k, V::pair_first(p));
+          if constexpr (mk != 0.0) acc += (R)mk * D[p];
+        });
+      }
+      m[k] = acc * (R)P.s_over_n[k];
+    });
+    {
+      R acc = 0;
+      static_for<1, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (!row_odd<LAT>(k) && V::mrow(k, 0) != 0.0) acc += (R)V::mrow(k, 0) * m[k];
+      });
+      fo[0] -= acc;
+    }
+    static_for<0, NP>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
+      R E = 0, O = 0;
+      static_for<1, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr double mk = V::mrow(k, a);
+        if constexpr (mk != 0.0) {
+          if constexpr (row_odd<LAT>(k)) O += (R)mk * m[k];
+          else E += (R)mk * m[k];
+        }
+      });
+      fo[a] -= E + O;
+      fo[b] -= E - O;
+    });
+  }
+  out.comp(s, Q, P.cells).template put_all<Q>(cell, fo, rs, [](int a) { return (R)V::w(a); });
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// pass 1: densities -> EOS -> psi on planes [plane0, plane0 + nplanes)
+template <int LAT, int NC, int ST>
+__global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* __restrict__ psi, int plane0,
+                                               int nplanes) {
+  using V = VS<LAT>;
+  using R = typename Pops<ST>::R;
+  unsigned cell;
+  if (!launch_cell(P, plane0, nplanes, &cell)) return;
+  const Coord c = make_coord(cell, P);
+  double rb[NC];
+#pragma unroll
+  for (int s = 0; s < NC; ++s) rb[s] = 0.0;
+#pragma unroll 1
+  for (int s = 0; s < NC; ++s) {
+    const auto cv = in.comp(s, V::Q, P.cells);
+    R acc = 0;
+#pragma unroll
+    for (int a = 0; a < V::Q; ++a) acc += cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+#pragma unroll
+    for (int t = 0; t < NC; ++t)
+      if (t == s) rb[t] = (double)acc;
+  }
+  psi[cell] = eos_psi<NC>(P, rb);
+}
+
+// pass 2: a block is 64 cells x NC wavefronts, wavefront s working on component s.
+// Each wavefront pulls its component (rbar_s, j_s) and sums the psi stencil over
+// the directions a with (a - 1) mod NC == s; the block combines the per-component
+// sums through LDS in a fixed component order (rho, Gamma, j, F identical in every
+// wavefront), then each wavefront splits the force, collides and stores component s.
+constexpr int kCells = 64;
+
+template <int LAT, int NC, int ST, int COLL, int FORC>
+__global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, Pops<ST> out,
+                                                       const double* __restrict__ psi, int plane0, int nplanes) {
+  using V = VS<LAT>;
+  using R = typename Pops<ST>::R;
+  constexpr int Q = V::Q;
+  __shared__ double red[NC][7][kCells];
+  const int lane = threadIdx.x & (kCells - 1);
+  // uniform per wavefront (wave64): read it from lane 0 so it lives in a scalar register
+  const int s = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kCells));
+  const unsigned lin = blockIdx.x * kCells + lane;
+  const unsigned pc = P.plane_cells;
+  const bool valid = lin < (unsigned)nplanes * pc;
+  unsigned cell = 0;
+  if (valid) {
+    const unsigned k = lin / pc;
+    unsigned plane = plane0 + k;
+    if (plane >= (unsigned)P.nplanes) plane -= P.nplanes;
+    cell = plane * pc + (lin - k * pc);
+  }
+  const Coord c = make_coord(cell, P);
+  const auto cv = in.comp(s, Q, P.cells);
+  R f[Q];
+  R rs = 0, jx = 0, jy = 0, jz = 0;
+  double Fp[3] = {0.0, 0.0, 0.0};
+  if (valid) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      f[a] = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+      rs += f[a];
+      if (V::cx(a)) jx += (R)V::cx(a) * f[a];
+      if (V::cy(a)) jy += (R)V::cy(a) * f[a];
+      if (V::cz(a)) jz += (R)V::cz(a) * f[a];
+    }
+    // partial stencil of Eq. (coupledMCforce) over this wavefront's directions
+    const double ps = ldb(psi, cell * 8u);
+    const double hb = 0.5 * (1.0 - P.beta);
+    static_for<1, Q>([&](auto A) {
+      constexpr int a = decltype(A)::value;
+      if ((a - 1) % NC == s) {
+        const double pn = ldb(psi, c.at(V::cx(a), V::cy(a), V::cz(a)) * 8u);
+        const double t = V::w(a) * pn * (P.beta * ps + hb * pn);
+        if constexpr (V::cx(a) != 0) Fp[0] += V::cx(a) * t;
+        if constexpr (V::cy(a) != 0) Fp[1] += V::cy(a) * t;
+        if constexpr (V::cz(a) != 0) Fp[2] += V::cz(a) * t;
+      }
+    });
+  }
+  red[s][0][lane] = (double)rs;
+  red[s][1][lane] = (double)jx;
+  red[s][2][lane] = (double)jy;
+  red[s][3][lane] = (double)jz;
+  red[s][4][lane] = Fp[0];
+  red[s][5][lane] = Fp[1];
+  red[s][6][lane] = Fp[2];
+  __syncthreads();
+  if (!valid) return;
+  double rho = 0.0, Gam = 0.0, j[3] = {0.0, 0.0, 0.0}, F[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    const double r = red[t][0][lane];
+    rho += r;
+    Gam += P.gamma[t] * r;
+    j[0] += red[t][1][lane];
+    j[1] += red[t][2][lane];
+    j[2] += red[t][3][lane];
+    F[0] += red[t][4][lane];
+    F[1] += red[t][5][lane];
+    F[2] += red[t][6][lane];
+  }
+  F[0] *= -P.G;
+  F[1] *= -P.G;
+  F[2] *= -P.G;
+  if (!(Gam > 0.0)) flag_error(P);
+  const double g0 = P.accel[0], g1 = P.accel[1], g2 = P.accel[2];
+  const double irho = 1.0 / rho;
+  R u[3];
+  if (FORC == LBM_GUO) {
+    // u = (j + F_total/2) / rho, F_total = F + rho g
+    u[0] = (R)((j[0] + 0.5 * (F[0] + rho * g0)) * irho);
+    u[1] = (R)((j[1] + 0.5 * (F[1] + rho * g1)) * irho);
+    u[2] = (R)((j[2] + 0.5 * (F[2] + rho * g2)) * irho);
+  } else {
+    u[0] = (R)(j[0] * irho);
+    u[1] = (R)(j[1] * irho);
+    u[2] = (R)(j[2] * irho);
+  }
+  const double ch = P.gamma[s] / Gam;   // chi_s / rbar_s
+  R fs[3];
+  if (FORC == LBM_GUO) {                // F_s = chi_s F + rbar_s g
+    const double r = (double)rs;
+    fs[0] = (R)(ch * r * F[0] + r * g0);
+    fs[1] = (R)(ch * r * F[1] + r * g1);
+    fs[2] = (R)(ch * r * F[2] + r * g2);
+  } else {                              // du_s = F_s / rbar_s = gamma_s F / Gamma + g
+    fs[0] = (R)(ch * F[0] + g0);
+    fs[1] = (R)(ch * F[1] + g1);
+    fs[2] = (R)(ch * F[2] + g2);
+  }
+  collide_store<LAT, ST, COLL, FORC>(P, out, s, cell, f, rs, u, fs);
 }
 
 }  // namespace lbmk

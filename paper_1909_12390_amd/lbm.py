@@ -25,14 +25,14 @@ LATTICES = {"D2Q9": 0, "D3Q19": 1}
 COLLISIONS = {"bgk": 0, "mrt": 1}
 FORCINGS = {"guo": 0, "edm": 1}
 STORAGES = {"f64": 0, "f32": 1, "f16": 2}
-SCHEDULES = {"two_pass": 0, "fused": 1}
+SCHEDULES = {"two_pass": 0, "blocked": 1}
 MAX_NC = 4
 MAX_Q = 19
 Q_OF = {"D2Q9": 9, "D3Q19": 19}
 D_OF = {"D2Q9": 2, "D3Q19": 3}
 
 # every function declared in include/lbm.h
-EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_get_populations",
+EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_moments", "lbm_get_populations",
             "lbm_set_populations", "lbm_check", "lbm_clear_error", "lbm_destroy", "lbm_last_error",
             "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure"]
 
@@ -50,7 +50,7 @@ class LbmMixture(ctypes.Structure):
 
 class LbmParams(ctypes.Structure):
     _fields_ = [("lattice", c_int), ("nx", c_int), ("ny", c_int), ("nz", c_int), ("collision", c_int),
-                ("forcing", c_int), ("storage", c_int), ("schedule", c_int), ("T", c_double),
+                ("forcing", c_int), ("storage", c_int), ("schedule", c_int), ("slab_planes", c_int), ("T", c_double),
                 ("tau", c_double), ("G", c_double), ("beta", c_double), ("gamma", c_double * MAX_NC),
                 ("mrt_s", c_double * MAX_Q), ("accel", c_double * 3)]
 
@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_init.argtypes = [POINTER(LbmMixture), POINTER(LbmParams), c_void_p, c_size_t, c_void_p, c_void_p,
                                c_void_p, POINTER(c_void_p)]
         L.lbm_step.argtypes = [c_void_p, c_int]
+        L.lbm_step_timed.argtypes = [c_void_p, c_int, dp]
         L.lbm_moments.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, dp]
         L.lbm_get_populations.argtypes = [c_void_p, c_void_p]
         L.lbm_set_populations.argtypes = [c_void_p, c_void_p]
@@ -202,7 +203,7 @@ class LibThermo:
 # ---------------------------------------------------------------------------
 
 def params_struct(lattice, shape, T, tau, beta, gamma, collision="bgk", forcing="guo", storage="f64",
-                  schedule="two_pass", mrt_s=None, accel=None, G=-1.0) -> LbmParams:
+                  schedule="two_pass", mrt_s=None, accel=None, G=-1.0, slab_planes=0) -> LbmParams:
     p = LbmParams()
     p.lattice = LATTICES[lattice]
     if lattice == "D2Q9":
@@ -215,6 +216,7 @@ def params_struct(lattice, shape, T, tau, beta, gamma, collision="bgk", forcing=
     p.forcing = FORCINGS[forcing]
     p.storage = STORAGES[storage]
     p.schedule = SCHEDULES[schedule]
+    p.slab_planes = int(slab_planes)
     p.T = float(T)
     p.tau = float(tau)
     p.G = float(G)
@@ -239,7 +241,7 @@ class LbmContext:
 
     def __init__(self, mix: dict, lattice: str, shape, T, tau, beta, gamma, rho0, u0=None,
                  collision="bgk", forcing="guo", storage="f64", schedule="two_pass", mrt_s=None,
-                 accel=None, G=-1.0, device="cuda"):
+                 accel=None, G=-1.0, slab_planes=0, device="cuda"):
         import torch
         self.torch = torch
         self.lattice = lattice
@@ -250,7 +252,7 @@ class LbmContext:
         self.cells = int(np.prod(self.shape))
         self._mix = mixture_struct(mix)
         self._prm = params_struct(lattice, self.shape, T, tau, beta, gamma, collision, forcing, storage,
-                                  schedule, mrt_s, accel, G)
+                                  schedule, mrt_s, accel, G, slab_planes)
         nbytes = c_size_t(0)
         _check(lib().lbm_workspace_bytes(ctypes.byref(self._mix), ctypes.byref(self._prm), ctypes.byref(nbytes)))
         self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=device)
@@ -277,6 +279,13 @@ class LbmContext:
 
     def step(self, n: int = 1):
         _check(lib().lbm_step(self._ctx, int(n)))
+
+    def step_timed(self, n: int):
+        """Run n steps with HIP events around every kernel; returns the summed
+        kernel durations in ms: (psi pass or fused kernel, collide pass)."""
+        ms = np.zeros(2)
+        _check(lib().lbm_step_timed(self._ctx, int(n), _dptr(ms)))
+        return float(ms[0]), float(ms[1])
 
     def check(self):
         _check(lib().lbm_check(self._ctx))

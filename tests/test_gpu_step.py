@@ -145,3 +145,55 @@ def test_set_get_populations_roundtrip():
     g = f * (1 + 1e-3 * rng.uniform(-1, 1, f.shape))
     ctx.set_populations(g)
     assert np.array_equal(ctx.get_populations().cpu().numpy(), g)
+
+
+# Reduced-precision storage.  Error budget relative to max|f| of a component:
+#   f32 offsets: encode rounds f / b and the offset to float32 (~2 eps32 = 1.2e-7 of
+#     f) and the float32 collision adds a few eps32 per step: <= 1e-6 after 1 step,
+#     <= 5e-6 after 10 (errors also propagate through the psi stencil; measured
+#     2.4e-7 / 4.6e-7);
+#   f16 offsets: the stored offset r = f/b - w (|r| <~ 0.05 in these states) is
+#     rounded to 11 bits (2^-11 |r| <~ 2.4e-5 b); relative to max|f| (>= w_0 b_max)
+#     below 1e-4 per step, and the rounding does not accumulate over 10 steps
+#     because every step re-encodes from float32 (measured 4e-5 / 3e-5).
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("storage,tol1,tol10", [("f32", 1e-6, 5e-6), ("f16", 1e-4, 2e-4)])
+@pytest.mark.parametrize("collision,forcing", [("bgk", "guo"), ("mrt", "edm")])
+def test_reduced_precision_step_close_to_oracle(lattice, storage, tol1, tol10, collision, forcing):
+    print(f"case {storage} {lattice} {collision}+{forcing}", flush=True)
+    c = case(lattice, 3, SHAPES[lattice], seed=11, u_amp=0.01)
+    rates = mrt_rates(lattice, 0.8) if collision == "mrt" else None
+    prm = oracle_params(c, collision, forcing, mrt_s=rates, beta=1.16 if forcing == "edm" else 1.945)
+    ref = oracle_run(c, lattice, prm, 10)
+    ctx = gpu_context(c, lattice, collision, forcing, storage=storage, mrt_s=rates,
+                      beta=1.16 if forcing == "edm" else 1.945)
+    e0 = rel_err(ctx.get_populations().cpu().numpy(), ref[0])
+    ctx.step(1)
+    e1 = rel_err(ctx.get_populations().cpu().numpy(), ref[1])
+    ctx.step(9)
+    e10 = rel_err(ctx.get_populations().cpu().numpy(), ref[10])
+    ctx.check()
+    print(f"  {storage}: init {e0:.2e}  1 step {e1:.2e}  10 steps {e10:.2e}", flush=True)
+    assert e1 < tol1 and e10 < tol10, (e0, e1, e10)
+
+
+@pytest.mark.parametrize("lattice,shape,slab", [("D2Q9", (45, 70), 7), ("D3Q19", (13, 14, 15), 4),
+                                                ("D3Q19", (13, 14, 15), 1)])
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_blocked_schedule_equals_two_pass(lattice, shape, slab, storage):
+    # same arithmetic, different launch order: bitwise identical states
+    print(f"case blocked {lattice} slab={slab} {storage}", flush=True)
+    c = case(lattice, 3, shape, seed=9, u_amp=0.01)
+    rates = mrt_rates(lattice, 0.8)
+    a = gpu_context(c, lattice, "mrt", "edm", storage=storage, mrt_s=rates, beta=1.16)
+    lbm = _lbm()
+    b = lbm.LbmContext(c["mix"], lattice, c["shape"], c["T"], 0.8, 1.16, c["gamma"], c["rho0"], c["u0"],
+                       collision="mrt", forcing="edm", storage=storage, schedule="blocked", mrt_s=rates,
+                       slab_planes=slab)
+    a.step(7)
+    b.step(7)
+    fa = a.get_populations().cpu().numpy()
+    fb = b.get_populations().cpu().numpy()
+    a.check()
+    b.check()
+    assert np.array_equal(fa, fb)
