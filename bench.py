@@ -172,7 +172,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f16", choices=list(STORAGE_BYTES))
-    ap.add_argument("--schedule", default="blocked", choices=["two_pass", "blocked"])
+    ap.add_argument("--schedule", default="two_pass", choices=["two_pass", "blocked"])
     ap.add_argument("--slab-planes", type=int, default=0, help="blocked schedule: planes per slab (0 = auto)")
     ap.add_argument("--side", type=int, default=128)
     ap.add_argument("--diag-every", type=int, default=100)

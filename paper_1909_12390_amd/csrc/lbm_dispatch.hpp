@@ -24,7 +24,8 @@ struct Ops {
   void (*imp)(const KParams&, const Bufs&, const double*, const double*, const double*, int, hipStream_t);
 };
 
-inline int nblocks_for(int cells) { return (cells + kBlock - 1) / kBlock; }
+// workgroups for `cells` cells of kBlock threads, rounded to the XCD count
+inline int nblocks_for(int cells) { return (int)xcd_grid((cells + kBlock - 1) / kBlock); }
 
 template <int ST>
 inline Pops<ST> make_pops(const Bufs& b);
@@ -57,7 +58,7 @@ struct OpsImpl {
   }
   static void collide(const KParams& P, const Bufs& in, const Bufs& out, const StepScratch& sc, int plane0,
                       int np, hipStream_t st) {
-    const int nb = (np * P.plane_cells + kCells - 1) / kCells;
+    const int nb = (int)xcd_grid((np * P.plane_cells + kCells - 1) / kCells);
     hipLaunchKernelGGL((k_collide<LAT, NC, ST, COLL, FORC>), dim3(nb), dim3(kCells * NC), 0, st, P,
                        make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
   }

@@ -113,7 +113,8 @@ struct OffsetPops {
     template <int Q, typename W>
     __device__ __forceinline__ void put_all(unsigned idx, const float* v, float b, W w) const {
       bstore(rb, idx * 4u, 0u, b);
-      const float inv = (b != 0.0f) ? 1.0f / b : 0.0f;
+      // hardware reciprocal (1 ulp): below the rounding of the stored offsets
+      const float inv = (b != 0.0f) ? __builtin_amdgcn_rcpf(b) : 0.0f;
 #pragma unroll
       for (int a = 0; a < Q; ++a)
         bstore(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, enc(v[a] * inv - (b != 0.0f ? w(a) : 0.0f)));
@@ -164,10 +165,21 @@ __device__ __forceinline__ Coord make_coord(unsigned cell, const KParams& P) {
   return c;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Launches use a multiple of 8 workgroups and remap workgroup b to the logical
+// block (b mod 8) * (n / 8) + b / 8, so each XCD sweeps one contiguous range of
+// cells and the cache lines shared by neighbouring blocks stay in one L2.
+constexpr unsigned kXcd = 8;
+__device__ __forceinline__ unsigned logical_block() {
+  const unsigned n = gridDim.x, b = blockIdx.x;
+  return (b % kXcd) * (n / kXcd) + b / kXcd;
+}
+inline unsigned xcd_grid(unsigned blocks) { return (blocks + kXcd - 1) / kXcd * kXcd; }
+
 // Linear index of the k-th cell of a launch covering `nplanes` planes starting at
 // plane `plane0` (periodic in the plane index); false past the end.
 __device__ __forceinline__ bool launch_cell(const KParams& P, int plane0, int nplanes, unsigned* cell) {
-  const unsigned lin = blockIdx.x * kBlock + threadIdx.x;
+  const unsigned lin = logical_block() * kBlock + threadIdx.x;
   const unsigned pc = P.plane_cells;
   if (lin >= (unsigned)nplanes * pc) return false;
   const unsigned k = lin / pc;
@@ -495,7 +507,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   const int lane = threadIdx.x & (kCells - 1);
   // uniform per wavefront (wave64): read it from lane 0 so it lives in a scalar register
   const int s = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kCells));
-  const unsigned lin = blockIdx.x * kCells + lane;
+  const unsigned lin = logical_block() * kCells + lane;
   const unsigned pc = P.plane_cells;
   const bool valid = lin < (unsigned)nplanes * pc;
   unsigned cell = 0;
@@ -559,30 +571,31 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   F[1] *= -P.G;
   F[2] *= -P.G;
   if (!(Gam > 0.0)) flag_error(P);
-  const double g0 = P.accel[0], g1 = P.accel[1], g2 = P.accel[2];
-  const double irho = 1.0 / rho;
+  // velocity and split in the collision precision R (float64 storage: double)
+  const R g0 = (R)P.accel[0], g1 = (R)P.accel[1], g2 = (R)P.accel[2];
+  const R rhoR = (R)rho, irho = (R)1 / rhoR;
+  const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
   R u[3];
   if (FORC == LBM_GUO) {
     // u = (j + F_total/2) / rho, F_total = F + rho g
-    u[0] = (R)((j[0] + 0.5 * (F[0] + rho * g0)) * irho);
-    u[1] = (R)((j[1] + 0.5 * (F[1] + rho * g1)) * irho);
-    u[2] = (R)((j[2] + 0.5 * (F[2] + rho * g2)) * irho);
+    u[0] = ((R)j[0] + (R)0.5 * (FR[0] + rhoR * g0)) * irho;
+    u[1] = ((R)j[1] + (R)0.5 * (FR[1] + rhoR * g1)) * irho;
+    u[2] = ((R)j[2] + (R)0.5 * (FR[2] + rhoR * g2)) * irho;
   } else {
-    u[0] = (R)(j[0] * irho);
-    u[1] = (R)(j[1] * irho);
-    u[2] = (R)(j[2] * irho);
+    u[0] = (R)j[0] * irho;
+    u[1] = (R)j[1] * irho;
+    u[2] = (R)j[2] * irho;
   }
-  const double ch = P.gamma[s] / Gam;   // chi_s / rbar_s
+  const R ch = (R)P.gamma[s] / (R)Gam;   // chi_s / rbar_s
   R fs[3];
   if (FORC == LBM_GUO) {                // F_s = chi_s F + rbar_s g
-    const double r = (double)rs;
-    fs[0] = (R)(ch * r * F[0] + r * g0);
-    fs[1] = (R)(ch * r * F[1] + r * g1);
-    fs[2] = (R)(ch * r * F[2] + r * g2);
+    fs[0] = ch * rs * FR[0] + rs * g0;
+    fs[1] = ch * rs * FR[1] + rs * g1;
+    fs[2] = ch * rs * FR[2] + rs * g2;
   } else {                              // du_s = F_s / rbar_s = gamma_s F / Gamma + g
-    fs[0] = (R)(ch * F[0] + g0);
-    fs[1] = (R)(ch * F[1] + g1);
-    fs[2] = (R)(ch * F[2] + g2);
+    fs[0] = ch * FR[0] + g0;
+    fs[1] = ch * FR[1] + g1;
+    fs[2] = ch * FR[2] + g2;
   }
   collide_store<LAT, ST, COLL, FORC>(P, out, s, cell, f, rs, u, fs);
 }
