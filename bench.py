@@ -135,6 +135,12 @@ def cpu_baseline_worker(side: int, steps: int):
         def flash(self, mix, T, p, z):
             return oth.flash(oth.Mixture(**mix), T, p, z)
 
+        def pressure(self, mix, T, n):
+            import numpy as _np
+            m = oth.Mixture(**mix)
+            n = _np.atleast_2d(_np.asarray(n, dtype=_np.float64))
+            return _np.where((n @ m.b) < 1.0, oth.pressure_molar(n.T, T, m), _np.nan)
+
     cfg = inputs.config_c3(_Oracle(), shape=(side, side, side), R0=side / 4.0)
     lat = olat.d3q19()
     prm = olbm.StepParams(T=cfg.T, tau=cfg.tau, gamma=cfg.gamma, beta=cfg.beta, collision=cfg.collision,
@@ -166,6 +172,70 @@ def cpu_baseline(side: int, steps: int):
                       f"({rec['seconds']:.1f} s)"}
 
 
+def batched_section(args, torch, lbm, inputs):
+    """Many independent D2Q9 boxes (sides from {32, 48, 64, 96, 128}, binary or
+    ternary, own T and composition), one launch per pass per step, K steps per HIP
+    graph, workgroup size from the autotuner.  Reports throughput and, after
+    --batch-precision-steps steps, the bulk phase mole-fraction error of the float32
+    and float16 storage against the float64 path, box by box."""
+    from paper_1909_12390_amd import autotune
+    cfgs = inputs.config_c4_boxes(lbm.LibThermo(), nboxes=args.batch_boxes)
+    boxes = [{"mix": c.mix, "shape": c.shape, "T": c.T, "tau": c.tau, "beta": c.beta, "gamma": c.gamma,
+              "rho0": c.rho0, "R0": c.geometry["R0"]} for c in cfgs]
+    cells = sum(c.cells for c in cfgs)
+    comp_cells = sum(c.cells * c.nc for c in cfgs)
+    tune = autotune.tune_batch(boxes, "D2Q9", "bgk", "edm", "f32", steps=20)
+    res = {"workload": f"{len(boxes)} independent D2Q9 boxes, sides from {{32,48,64,96,128}}, binary or ternary, "
+                       f"BGK + exact-difference forcing, own T and composition per box",
+           "boxes": len(boxes), "cells": cells, "component_cells": comp_cells, "autotune": tune}
+    graph_steps = 100
+    for storage in ("f32", "f16", "f64"):
+        b = lbm.LbmBatch(boxes, "D2Q9", collision="bgk", forcing="edm", storage=storage, tile=tune["tile"],
+                         graph_steps=graph_steps)
+        b.step(2 * graph_steps)
+        b.check()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(b.stream)
+        b.step(args.batch_steps)
+        stop.record(b.stream)
+        stop.synchronize()
+        ms = start.elapsed_time(stop) / args.batch_steps
+        b.check()
+        s = STORAGE_BYTES[storage]
+        alg = sum(c.cells * (2 * c.nc * 9 * s + 16 + (8 * c.nc if storage != "f64" else 0)) for c in cfgs)
+        res[storage] = {"ms_per_step": ms, "mlups_x_comp": comp_cells / (ms * 1e-3) / 1e6,
+                        "alg_GBps": alg / (ms * 1e-3) / 1e9}
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+    if args.batch_precision_steps > 0:
+        fr = {}
+        for storage in ("f64", "f32", "f16"):
+            b = lbm.LbmBatch(boxes, "D2Q9", collision="bgk", forcing="edm", storage=storage, tile=tune["tile"],
+                             graph_steps=graph_steps)
+            b.step(args.batch_precision_steps)
+            bad = b.box_errors()
+            if bad.any():
+                raise RuntimeError(f"{storage}: boxes {np.nonzero(bad)[0].tolist()} left the EOS domain")
+            b.check()
+            rho = b.fields()
+            fr[storage] = [phase_mole_fractions(r, bx["mix"]["M"], {"R0": bx["R0"]}, bx["shape"])
+                           for r, bx in zip(rho, boxes)]
+            b.close()
+            del b, rho
+            torch.cuda.empty_cache()
+        for storage in ("f32", "f16"):
+            e = np.array([max(float(np.max(np.abs(a[ph] - c[ph]))) for ph in ("liquid", "vapor"))
+                          for a, c in zip(fr[storage], fr["f64"])])
+            res[f"{storage}_max_abs_molefrac_err_vs_f64"] = float(e.max())
+            res[f"{storage}_median_abs_molefrac_err_vs_f64"] = float(np.median(e))
+            res[f"{storage}_boxes_over_1e-4"] = int((e > 1e-4).sum())
+            res[f"{storage}_worst_box"] = int(np.argmax(e))
+        res["precision_steps"] = args.batch_precision_steps
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +254,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--batch-boxes", type=int, default=512, help="batched section: number of boxes (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--batch-precision-steps", type=int, default=10000)
     args = ap.parse_args()
 
     if args.cpu_baseline_worker:
@@ -311,6 +384,9 @@ def main():
         prec["f64_liquid_x"] = fr["f64"]["liquid"].tolist()
         prec["f64_vapor_y"] = fr["f64"]["vapor"].tolist()
         out["precision"] = prec
+
+    if args.batch_boxes > 0:
+        out["batched"] = batched_section(args, torch, lbm, inputs)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_side, args.cpu_steps)

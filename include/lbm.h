@@ -206,6 +206,63 @@ lbm_status lbm_flash(const lbm_mixture* mix, double T, double p, const double* z
 lbm_status lbm_bubble_pressure(const lbm_mixture* mix, double T, const double* z_host, double* p_out);
 lbm_status lbm_dew_pressure(const lbm_mixture* mix, double T, const double* z_host, double* p_out);
 
+
+/* ---------------------------------------------------------------------------
+ * Batched boxes: many independent periodic boxes, each with its own mixture,
+ * temperature and volatility coefficients (e.g. a sweep of flash states), advanced
+ * together: each pass of a step (density/EOS/psi, then force/split/collide/store)
+ * is one persistent launch over the (box, tile) work list; K steps can be captured
+ * once in a HIP graph and replayed.  The per-box arithmetic is the single-box one.
+ * Concatenated layouts: fields [box][nc_b][cells_b], populations [box][nc_b][Q][cells_b].
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  lbm_mixture mix;           /* the box's components (nc 1..4)                    */
+  int nx, ny, nz;            /* nz = 1 for D2Q9; periodic                         */
+  double T, tau, G, beta;
+  double gamma[LBM_MAX_NC];  /* each in (0, 1]                                    */
+} lbm_box;
+
+typedef struct {
+  int lattice, collision, forcing, storage;   /* shared by every box              */
+  int tile;                  /* cells per workgroup: 64, 128, 256, 512, 1024 (0 = 256) */
+  int graph_steps;           /* steps per captured HIP graph (rounded up to even; 0 = none).
+                                Capture needs a non-default stream.               */
+  int grid;                  /* workgroups of the persistent launch (0 = all resident) */
+  double mrt_s[LBM_MAX_Q];
+  double accel[3];
+} lbm_batch_params;
+
+typedef struct lbm_batch lbm_batch;
+
+/* Workspace bytes and the element counts of the concatenated field and population
+ * layouts (any output may be NULL).  Host validation as for lbm_init, per box. */
+lbm_status lbm_batch_layout(const lbm_box* boxes_host, int nboxes, const lbm_batch_params* prm,
+                            size_t* workspace_bytes, size_t* field_elems, size_t* pop_elems);
+
+/* Bind the caller's workspace (dev, 256-byte aligned), upload the box table and the
+ * work list, and set every box to rest-equilibrium of rho0 (dev, float64, concatenated
+ * [box][nc_b][cells_b]).  Synchronises `stream` once (host tables are uploaded). */
+lbm_status lbm_batch_init(const lbm_box* boxes_host, int nboxes, const lbm_batch_params* prm,
+                          void* workspace_dev, size_t workspace_bytes, const double* rho0_dev,
+                          void* stream, lbm_batch** out);
+
+/* Enqueue nsteps steps of every box (asynchronous; graph replays when configured). */
+lbm_status lbm_batch_step(lbm_batch* b, int nsteps);
+
+/* Export cell-volume densities (dev, concatenated [box][nc_b][cells_b]) and/or the
+ * canonical float64 populations (dev, [box][nc_b][Q][cells_b]); either may be NULL. */
+lbm_status lbm_batch_fields(lbm_batch* b, double* rho_bar_dev, double* f_dev);
+
+/* Synchronise and report the device error flag of the batch. */
+lbm_status lbm_batch_check(lbm_batch* b);
+
+/* Synchronise and copy the per-box error flags (host int [nboxes], 1 = the box left
+ * the EOS domain or produced a non-finite value) so a sweep can tell which states failed. */
+lbm_status lbm_batch_box_errors(lbm_batch* b, int* flags_host);
+
+/* Release the batch (not the caller's workspace); NULL is accepted. */
+void lbm_batch_destroy(lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_import(KParams P, Pops<ST> out, cons
     R vr[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) vr[a] = (R)v[a];
-    out.comp(s, Q, P.cells).template put_all<Q>(cell, vr, (R)sum, [](int a) { return (R)V::w(a); });
+    out.comp(s, Q, P.cells).template put_all<Q>(cell, vr, sum, [](int a) { return (R)V::w(a); });
   }
 }
 

@@ -1,0 +1,311 @@
+// Batched step: many independent periodic boxes, each with its own mixture,
+// temperature, volatility coefficients and component count (1..4), advanced by
+// one launch per pass per step over a (box, tile) work list.
+//
+// Storage: the boxes' population planes are concatenated; box b owns the
+// elements [pop_off, pop_off + nc Q cells) of the population array(s) (and
+// [base_off, base_off + nc cells) of the float32 base in the offset formats),
+// plus [psi_off, psi_off + cells) of the psi scratch.  The per-step arithmetic is
+// the single-box one (lbm_kernels.hpp), with the component count read from the
+// box descriptor instead of a template parameter.
+//
+// Launch: a persistent grid (a multiple of the 8 XCDs, sized to the resident
+// workgroups); XCD x sweeps tiles [x T/8, (x+1) T/8) of the work list in order, so
+// each XCD's L2 sees contiguous cells of the same boxes.  Every workgroup leaves
+// its loop after at most ceil(T / gridDim) tiles.
+#pragma once
+#include "lbm_kernels.hpp"
+
+namespace lbmk {
+
+struct BoxK {
+  int nx, ny, nz, nc;
+  unsigned cells;
+  unsigned first_tile;              // first entry of this box in the work list
+  unsigned long long pop_off;       // element offset of the box's populations
+  unsigned long long base_off;      // element offset of the box's float32 base (offset formats)
+  unsigned long long psi_off;       // element offset of the box's psi
+  double RT, G, beta, omega;
+  double aa[LBM_MAX_NC][LBM_MAX_NC];
+  double b[LBM_MAX_NC], invM[LBM_MAX_NC], gamma[LBM_MAX_NC];
+};
+
+struct BatchK {
+  const BoxK* boxes;
+  const int* tile_box;              // work list: box of each tile
+  unsigned ntiles;
+  int tile;                         // cells per tile (= workgroup size)
+  int collision, forcing;
+  double s_over_n[LBM_MAX_Q];
+  double accel[3];
+  int* err;                         // [0]: any box; [1 + b]: box b
+};
+
+// Storage views over a box's planes (same encodings as Pops<ST>).
+template <int ST>
+struct BatchPops;
+template <>
+struct BatchPops<LBM_F64> {
+  using R = double;
+  double* f;
+  __device__ __forceinline__ Pops<LBM_F64>::View comp(const BoxK& B, int s, int Q) const {
+    const unsigned plane = B.cells * 8u;
+    return Pops<LBM_F64>::View{make_rsrc(f + B.pop_off + (size_t)s * Q * B.cells, (unsigned)Q * plane), plane};
+  }
+};
+template <typename H>
+struct BatchOffsetPops {
+  using R = float;
+  float* base;
+  H* r;
+  __device__ __forceinline__ typename OffsetPops<H>::View comp(const BoxK& B, int s, int Q) const {
+    const unsigned plane = B.cells * (unsigned)sizeof(H);
+    return typename OffsetPops<H>::View{make_rsrc(base + B.base_off + (size_t)s * B.cells, B.cells * 4u),
+                                        make_rsrc(r + B.pop_off + (size_t)s * Q * B.cells, (unsigned)Q * plane),
+                                        plane};
+  }
+};
+template <>
+struct BatchPops<LBM_F32_OFS> : BatchOffsetPops<float> {};
+template <>
+struct BatchPops<LBM_F16_OFS> : BatchOffsetPops<__half> {};
+
+__device__ __forceinline__ void batch_flag(const BatchK& K, int box) {
+  K.err[0] = 1;
+  K.err[1 + box] = 1;
+}
+
+// tiles of this workgroup: XCD-contiguous ranges of the work list
+struct TileRange {
+  unsigned t, end, stride;
+};
+__device__ __forceinline__ TileRange tile_range(unsigned ntiles) {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned per_xcd_blocks = nb / kXcd;
+  const unsigned x = b % kXcd, i = b / kXcd;
+  const unsigned lo = (unsigned)(((unsigned long long)ntiles * x) / kXcd);
+  const unsigned hi = (unsigned)(((unsigned long long)ntiles * (x + 1)) / kXcd);
+  return TileRange{lo + i, hi, per_xcd_blocks};
+}
+
+__device__ __forceinline__ Coord box_coord(unsigned cell, const BoxK& B) {
+  KParams P;
+  P.nx = B.nx;
+  P.ny = B.ny;
+  P.nz = B.nz;
+  return make_coord(cell, P);
+}
+
+// mixture pressure and psi with a runtime component count (rb[i] = 0 for i >= nc)
+__device__ __forceinline__ double box_psi(const BatchK& K, const BoxK& B, int box, const double* rb) {
+  double n[LBM_MAX_NC];
+  double rt = 0.0, Bn = 0.0, rho = 0.0;
+#pragma unroll
+  for (int i = 0; i < LBM_MAX_NC; ++i) {
+    n[i] = i < B.nc ? rb[i] * B.invM[i] : 0.0;
+    rt += n[i];
+    Bn += (i < B.nc ? B.b[i] : 0.0) * n[i];
+    rho += i < B.nc ? rb[i] : 0.0;
+  }
+  double An = 0.0;
+#pragma unroll
+  for (int i = 0; i < LBM_MAX_NC; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < LBM_MAX_NC; ++j)
+      if (i < B.nc && j < B.nc) s += B.aa[i][j] * n[j];
+    An += n[i] * s;
+  }
+  const double p = rt * B.RT / (1.0 - Bn) - An / (1.0 + 2.0 * Bn - Bn * Bn);
+  const double X = 6.0 * (p - rho * (1.0 / 3.0)) / B.G;
+  if (!(Bn < 1.0) || !(X >= 0.0) || !(X <= 1.0e300)) batch_flag(K, box);
+  return sqrt(X);
+}
+
+// pass 1 over every tile: densities -> EOS -> psi
+template <int LAT, int ST>
+__global__ __launch_bounds__(1024) void kb_psi(BatchK K, BatchPops<ST> in, double* __restrict__ psi) {
+  using V = VS<LAT>;
+  using R = typename BatchPops<ST>::R;
+  const TileRange tr = tile_range(K.ntiles);
+  for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
+    const int bx = K.tile_box[t];
+    const BoxK& B = K.boxes[bx];
+    const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
+    if (cell >= B.cells) continue;
+    const Coord c = box_coord(cell, B);
+    double rb[LBM_MAX_NC];
+#pragma unroll
+    for (int s = 0; s < LBM_MAX_NC; ++s) rb[s] = 0.0;
+#pragma unroll 1
+    for (int s = 0; s < B.nc; ++s) {
+      const auto cv = in.comp(B, s, V::Q);
+      R acc = 0;
+#pragma unroll
+      for (int a = 0; a < V::Q; ++a) acc += cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+#pragma unroll
+      for (int u = 0; u < LBM_MAX_NC; ++u)
+        if (u == s) rb[u] = (double)acc;
+    }
+    psi[B.psi_off + cell] = box_psi(K, B, bx, rb);
+  }
+}
+
+// pass 2 over every tile: one thread per cell, components in a rolled loop
+template <int LAT, int ST, int COLL, int FORC>
+__global__ __launch_bounds__(1024) void kb_collide(BatchK K, BatchPops<ST> in, BatchPops<ST> out,
+                                                  const double* __restrict__ psi) {
+  using V = VS<LAT>;
+  using R = typename BatchPops<ST>::R;
+  constexpr int Q = V::Q;
+  const TileRange tr = tile_range(K.ntiles);
+  for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
+    const int bx = K.tile_box[t];
+    const BoxK& B = K.boxes[bx];
+    const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
+    if (cell >= B.cells) continue;
+    const Coord c = box_coord(cell, B);
+    double rho = 0.0, Gam = 0.0;
+    R jx = 0, jy = 0, jz = 0;
+#pragma unroll 1
+    for (int s = 0; s < B.nc; ++s) {
+      const auto cv = in.comp(B, s, Q);
+      R acc = 0;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const R v = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+        acc += v;
+        if (V::cx(a)) jx += (R)V::cx(a) * v;
+        if (V::cy(a)) jy += (R)V::cy(a) * v;
+        if (V::cz(a)) jz += (R)V::cz(a) * v;
+      }
+      rho += (double)acc;
+      Gam += B.gamma[s] * (double)acc;
+    }
+    if (!(Gam > 0.0)) batch_flag(K, bx);
+    const double* ps = psi + B.psi_off;
+    double F[3] = {0.0, 0.0, 0.0};
+    {
+      const double p0 = ps[cell];
+      const double hb = 0.5 * (1.0 - B.beta);
+      static_for<1, Q>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        const double pn = ps[c.at(V::cx(a), V::cy(a), V::cz(a))];
+        const double tt = V::w(a) * pn * (B.beta * p0 + hb * pn);
+        if constexpr (V::cx(a) != 0) F[0] += V::cx(a) * tt;
+        if constexpr (V::cy(a) != 0) F[1] += V::cy(a) * tt;
+        if constexpr (V::cz(a) != 0) F[2] += V::cz(a) * tt;
+      });
+      F[0] *= -B.G;
+      F[1] *= -B.G;
+      F[2] *= -B.G;
+    }
+    const R g0 = (R)K.accel[0], g1 = (R)K.accel[1], g2 = (R)K.accel[2];
+    const R rhoR = (R)rho, irho = (R)1 / rhoR;
+    const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
+    R u[3];
+    if (FORC == LBM_GUO) {
+      u[0] = (jx + (R)0.5 * (FR[0] + rhoR * g0)) * irho;
+      u[1] = (jy + (R)0.5 * (FR[1] + rhoR * g1)) * irho;
+      u[2] = (jz + (R)0.5 * (FR[2] + rhoR * g2)) * irho;
+    } else {
+      u[0] = jx * irho;
+      u[1] = jy * irho;
+      u[2] = jz * irho;
+    }
+    // collision parameters of this box
+    KParams P;
+    P.cells = (int)B.cells;
+    P.omega = B.omega;
+#pragma unroll
+    for (int k = 0; k < LBM_MAX_Q; ++k) P.s_over_n[k] = K.s_over_n[k];
+#pragma unroll 1
+    for (int s = 0; s < B.nc; ++s) {
+      const auto cv = in.comp(B, s, Q);
+      R f[Q];
+      R rs = 0;
+      double mass = 0.0;   // summed exactly for the offset formats' base (put_all)
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        f[a] = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+        rs += f[a];
+        mass += (double)f[a];
+      }
+      const R ch = (R)B.gamma[s] / (R)Gam;
+      R fs[3];
+      if (FORC == LBM_GUO) {
+        fs[0] = ch * rs * FR[0] + rs * g0;
+        fs[1] = ch * rs * FR[1] + rs * g1;
+        fs[2] = ch * rs * FR[2] + rs * g2;
+      } else {
+        fs[0] = ch * FR[0] + g0;
+        fs[1] = ch * FR[1] + g1;
+        fs[2] = ch * FR[2] + g2;
+      }
+      collide_values<LAT, R, COLL, FORC>(P, f, rs, u, fs, [&](const R* fo) {
+        out.comp(B, s, Q).template put_all<Q>(cell, fo, mass, [](int a) { return (R)V::w(a); });
+      });
+    }
+  }
+}
+
+// rbar_s of every cell of every box (concatenated [box][nc_b][cells_b]) and the
+// state in the canonical float64 layout [box][nc_b][Q][cells_b] (either may be null)
+template <int LAT, int ST>
+__global__ __launch_bounds__(1024) void kb_export(BatchK K, BatchPops<ST> in, const unsigned long long* fld_off,
+                                                 double* __restrict__ rho_out, double* __restrict__ f_out) {
+  using V = VS<LAT>;
+  using R = typename BatchPops<ST>::R;
+  const TileRange tr = tile_range(K.ntiles);
+  for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
+    const int bx = K.tile_box[t];
+    const BoxK& B = K.boxes[bx];
+    const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
+    if (cell >= B.cells) continue;
+    const Coord c = box_coord(cell, B);
+#pragma unroll 1
+    for (int s = 0; s < B.nc; ++s) {
+      const auto cv = in.comp(B, s, V::Q);
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < V::Q; ++a) {
+        const double v = (double)cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+        acc += v;
+        if (f_out) f_out[B.pop_off + ((size_t)s * V::Q + a) * B.cells + cell] = v;
+      }
+      if (rho_out) rho_out[fld_off[bx] + (size_t)s * B.cells + cell] = acc;
+    }
+  }
+}
+
+// equilibrium initialisation from rho0 (concatenated [box][nc_b][cells_b]) at rest
+template <int LAT, int ST>
+__global__ __launch_bounds__(1024) void kb_init(BatchK K, BatchPops<ST> out, const unsigned long long* fld_off,
+                                               const double* __restrict__ rho0) {
+  using V = VS<LAT>;
+  using R = typename BatchPops<ST>::R;
+  constexpr int Q = V::Q;
+  const TileRange tr = tile_range(K.ntiles);
+  for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
+    const int bx = K.tile_box[t];
+    const BoxK& B = K.boxes[bx];
+    const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
+    if (cell >= B.cells) continue;
+    const Coord c = box_coord(cell, B);
+#pragma unroll 1
+    for (int s = 0; s < B.nc; ++s) {
+      R v[Q];
+      double sum = 0.0;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const double r = rho0[fld_off[bx] + (size_t)s * B.cells + c.at(V::cx(a), V::cy(a), V::cz(a))];
+        const double fe = feq<LAT, double>(a, r, 0.0, 0.0, 0.0, 0.0);
+        v[a] = (R)fe;
+        sum += fe;
+      }
+      out.comp(B, s, Q).template put_all<Q>(cell, v, sum, [](int a) { return (R)V::w(a); });
+    }
+  }
+}
+
+}  // namespace lbmk

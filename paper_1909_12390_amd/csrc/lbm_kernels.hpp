@@ -72,6 +72,9 @@ __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, _
 //   streams to y + e_a) = base(y) * (w_a + r_a(y)).
 // comp(s) returns a view of component s; get(a, idx) decodes direction a at
 // cell idx, put_all stores the Q post-collision values (and the base) of a cell.
+// Both offset formats rescale the stored base after rounding the offsets so that
+// the cell's decoded mass equals its mass before encoding (put_all); the caller
+// passes that mass summed in float64.
 // ---------------------------------------------------------------------------
 template <int ST>
 struct Pops;
@@ -109,15 +112,37 @@ struct OffsetPops {
     __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
       return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
     }
-    // v: post-collision populations; b: this cell's base (rbar_s); w(a): weights
+    // v: post-collision populations; mass: the cell's mass of this component
+    // (sum of v, summed exactly in float64); w(a): weights.
+    // The offsets are taken against b0 = sum_a |v_a|, which is the mass wherever
+    // every population is positive; where a trace component's populations change
+    // sign (its density near or below zero) b0 stays of the size of the
+    // populations, so the offsets stay bounded and their rounding stays relative
+    // to the populations themselves.  After rounding the offsets the stored base
+    // is set to mass / S with S = sum_a (w_a + r_a), each term formed in float32
+    // exactly as the decoder forms it and the sum taken in float64 (exact); a cell
+    // at rest is then a fixed point of encode/stream/decode, since the decoder's
+    // product roundings total less than half an ulp of the base, which the
+    // rounding of mass / S absorbs.  Float32 sums instead bias the mass by a
+    // fraction of an ulp per step, coherently over a bulk phase, which over
+    // thousands of steps shifts phase compositions by ~1e-4.  Where the
+    // populations are far from all positive (S < 1/2) the base stays b0.
     template <int Q, typename W>
-    __device__ __forceinline__ void put_all(unsigned idx, const float* v, float b, W w) const {
-      bstore(rb, idx * 4u, 0u, b);
-      // hardware reciprocal (1 ulp): below the rounding of the stored offsets
-      const float inv = (b != 0.0f) ? __builtin_amdgcn_rcpf(b) : 0.0f;
+    __device__ __forceinline__ void put_all(unsigned idx, const float* v, double mass, W w) const {
+      float b0 = 0.0f;
 #pragma unroll
-      for (int a = 0; a < Q; ++a)
-        bstore(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, enc(v[a] * inv - (b != 0.0f ? w(a) : 0.0f)));
+      for (int a = 0; a < Q; ++a) b0 += fabsf(v[a]);
+      // hardware reciprocal (1 ulp): its error is absorbed by the rescaled base
+      const float inv = (b0 > 0.0f) ? __builtin_amdgcn_rcpf(b0) : 0.0f;
+      const float wm = (b0 > 0.0f) ? 1.0f : 0.0f;
+      double S = 0.0;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const H r = enc(v[a] * inv - wm * w(a));
+        bstore(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, r);
+        S += (double)(w(a) + (float)r);
+      }
+      bstore(rb, idx * 4u, 0u, S >= 0.5 ? (float)(mass / S) : b0);
     }
   };
   __device__ __forceinline__ View comp(int s, int Q, int cells) const {
@@ -345,12 +370,10 @@ __device__ __forceinline__ void cell_forces(const KParams& P, const double* rb, 
 //         -> even w rs (9/2 (e.du)(2 e.u + e.du) - 3/2 du.(2u + du)), odd 3 w rs e.du;
 // MRT even rows act on f_a + f_opp, odd rows on f_a - f_opp; the density row is
 // skipped because sum_a (f - feq + h src) = 0.
-template <int LAT, int ST, int COLL, int FORC>
-__device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& out, int s, unsigned cell,
-                                              const typename Pops<ST>::R* f, typename Pops<ST>::R rs,
-                                              const typename Pops<ST>::R* u3, const typename Pops<ST>::R* F3) {
+template <int LAT, typename R, int COLL, int FORC, typename Sink>
+__device__ __forceinline__ void collide_values(const KParams& P, const R* f, R rs, const R* u3, const R* F3,
+                                               Sink sink) {
   using V = VS<LAT>;
-  using R = typename Pops<ST>::R;
   constexpr int Q = V::Q;
   constexpr int NP = (Q - 1) / 2;
   const R ux = u3[0], uy = u3[1], uz = u3[2];
@@ -458,7 +481,20 @@ __device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& 
       fo[b] -= E - O;
     });
   }
-  out.comp(s, Q, P.cells).template put_all<Q>(cell, fo, rs, [](int a) { return (R)V::w(a); });
+  sink(fo);
+}
+
+template <int LAT, int ST, int COLL, int FORC>
+__device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& out, int s, unsigned cell,
+                                              const typename Pops<ST>::R* f, typename Pops<ST>::R rs,
+                                              const typename Pops<ST>::R* u3, const typename Pops<ST>::R* F3,
+                                              double mass) {
+  using V = VS<LAT>;
+  using R = typename Pops<ST>::R;
+  constexpr int Q = V::Q;
+  collide_values<LAT, R, COLL, FORC>(P, f, rs, u3, F3, [&](const R* fo) {
+    out.comp(s, Q, P.cells).template put_all<Q>(cell, fo, mass, [](int a) { return (R)V::w(a); });
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -521,12 +557,14 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   const auto cv = in.comp(s, Q, P.cells);
   R f[Q];
   R rs = 0, jx = 0, jy = 0, jz = 0;
+  double mass = 0.0;   // the component's mass, summed exactly (rs in float64 storage)
   double Fp[3] = {0.0, 0.0, 0.0};
   if (valid) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       f[a] = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
       rs += f[a];
+      mass += (double)f[a];
       if (V::cx(a)) jx += (R)V::cx(a) * f[a];
       if (V::cy(a)) jy += (R)V::cy(a) * f[a];
       if (V::cz(a)) jz += (R)V::cz(a) * f[a];
@@ -545,7 +583,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
       }
     });
   }
-  red[s][0][lane] = (double)rs;
+  red[s][0][lane] = mass;
   red[s][1][lane] = (double)jx;
   red[s][2][lane] = (double)jy;
   red[s][3][lane] = (double)jz;
@@ -597,7 +635,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
     fs[1] = ch * FR[1] + g1;
     fs[2] = ch * FR[2] + g2;
   }
-  collide_store<LAT, ST, COLL, FORC>(P, out, s, cell, f, rs, u, fs);
+  collide_store<LAT, ST, COLL, FORC>(P, out, s, cell, f, rs, u, fs, mass);
 }
 
 }  // namespace lbmk

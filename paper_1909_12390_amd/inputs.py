@@ -10,6 +10,8 @@ object passed in by the caller, so each side supplies its own implementation:
     backend.dew_pressure(mix, T, z)             -> p
     backend.flash(mix, T, p, z)                 -> object with .rbar_l, .rbar_v,
                                                    .gamma, .x, .y (raises on one phase)
+    backend.pressure(mix, T, n)                 -> p_EOS of molar-density states n[k, nc]
+                                                   (nan outside the EOS domain)
 
 `mix` is a plain dict {"a", "b", "omega", "M", "k", "R"} of float64 arrays.
 
@@ -175,10 +177,24 @@ def default_mrt_rates(lattice: str, tau: float):
     return np.array([1.0 / tau if k in ("nu", "j") else (0.5 if k in ("e", "eps") else 1.0) for k in kinds])
 
 
+# A drawn liquid state must stay representable under compression: at 1.25 times
+# its cell-volume densities p_EOS must remain below c_s^2 rho, otherwise the square
+# root of Eq. (psicorrected) has no headroom and the first interface transient
+# leaves the EOS domain (observed below ~1.16 on the batched sweep).
+COMPRESSION_MARGIN = 1.25
+
+
+def representable(backend, mix, T, rbar_l, margin=COMPRESSION_MARGIN):
+    n = margin * np.asarray(rbar_l, dtype=np.float64) / np.asarray(mix["M"], dtype=np.float64)
+    p = float(np.asarray(backend.pressure(mix, T, n[None, :]))[0])
+    return np.isfinite(p) and p < margin * float(np.sum(rbar_l)) / 3.0
+
+
 def pick_state(rng, backend, nc, t_lo, t_hi, k_max, comp_kwargs, z=None,
-                exactly_one_supercritical=False, max_draws=200):
+                exactly_one_supercritical=False, max_draws=400):
     """Draw components, T and z until the mixture splits into two phases at
-    p* = (p_bub + p_dew)/2 with every gamma in (0, 1]."""
+    p* = (p_bub + p_dew)/2 with every gamma in (0, 1] and a liquid that keeps the
+    compression margin above."""
     for _ in range(max_draws):
         mix = draw_components(rng, nc, k_max=k_max, **comp_kwargs)
         zz = draw_composition(rng, nc) if z is None else np.asarray(z, dtype=np.float64)
@@ -200,7 +216,9 @@ def pick_state(rng, backend, nc, t_lo, t_hi, k_max, comp_kwargs, z=None,
         except Exception:
             continue
         g = np.asarray(fl.gamma)
-        if np.all(g > 0.0) and np.all(g <= 1.0 + 1e-12) and np.all(np.isfinite(g)):
+        if not (np.all(g > 0.0) and np.all(g <= 1.0 + 1e-12) and np.all(np.isfinite(g))):
+            continue
+        if representable(backend, mix, T, fl.rbar_l):
             return mix, T, zz, p, fl
     raise RuntimeError("no two-phase state found")
 

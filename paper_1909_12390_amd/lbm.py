@@ -34,7 +34,9 @@ D_OF = {"D2Q9": 2, "D3Q19": 3}
 # every function declared in include/lbm.h
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_moments", "lbm_get_populations",
             "lbm_set_populations", "lbm_check", "lbm_clear_error", "lbm_destroy", "lbm_last_error",
-            "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure"]
+            "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure",
+            "lbm_batch_layout", "lbm_batch_init", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_check",
+            "lbm_batch_box_errors", "lbm_batch_destroy"]
 
 
 class LbmError(RuntimeError):
@@ -61,6 +63,17 @@ class LbmFlashResult(ctypes.Structure):
                 ("rbar_l", c_double * MAX_NC), ("rbar_v", c_double * MAX_NC), ("gamma", c_double * MAX_NC),
                 ("fug_l", c_double * MAX_NC), ("fug_v", c_double * MAX_NC), ("residual", c_double),
                 ("iterations", c_int)]
+
+
+class LbmBox(ctypes.Structure):
+    _fields_ = [("mix", LbmMixture), ("nx", c_int), ("ny", c_int), ("nz", c_int), ("T", c_double),
+                ("tau", c_double), ("G", c_double), ("beta", c_double), ("gamma", c_double * MAX_NC)]
+
+
+class LbmBatchParams(ctypes.Structure):
+    _fields_ = [("lattice", c_int), ("collision", c_int), ("forcing", c_int), ("storage", c_int),
+                ("tile", c_int), ("graph_steps", c_int), ("grid", c_int), ("mrt_s", c_double * MAX_Q),
+                ("accel", c_double * 3)]
 
 
 _lib = None
@@ -93,9 +106,19 @@ def lib() -> ctypes.CDLL:
         L.lbm_flash.argtypes = [POINTER(LbmMixture), c_double, c_double, dp, POINTER(LbmFlashResult)]
         L.lbm_bubble_pressure.argtypes = [POINTER(LbmMixture), c_double, dp, dp]
         L.lbm_dew_pressure.argtypes = [POINTER(LbmMixture), c_double, dp, dp]
+        L.lbm_batch_layout.argtypes = [POINTER(LbmBox), c_int, POINTER(LbmBatchParams), POINTER(c_size_t),
+                                       POINTER(c_size_t), POINTER(c_size_t)]
+        L.lbm_batch_init.argtypes = [POINTER(LbmBox), c_int, POINTER(LbmBatchParams), c_void_p, c_size_t, c_void_p,
+                                     c_void_p, POINTER(c_void_p)]
+        L.lbm_batch_step.argtypes = [c_void_p, c_int]
+        L.lbm_batch_fields.argtypes = [c_void_p, c_void_p, c_void_p]
+        L.lbm_batch_check.argtypes = [c_void_p]
+        L.lbm_batch_box_errors.argtypes = [c_void_p, POINTER(c_int)]
+        L.lbm_batch_destroy.argtypes = [c_void_p]
+        L.lbm_batch_destroy.restype = None
         for name in EXPORTED:
             f = getattr(L, name)
-            if name not in ("lbm_destroy", "lbm_last_error"):
+            if name not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy"):
                 f.restype = c_int
         _lib = L
     return _lib
@@ -150,6 +173,22 @@ def lbm_fugacity(mix: dict, T: float, n: np.ndarray):
     return {"p": p, "Z": Z, "lnphi": lp, "fug": fug}
 
 
+def lbm_pressure(mix: dict, T: float, n: np.ndarray) -> np.ndarray:
+    """p_EOS of molar-density states n[nstates, nc]; nan where b_m rho~ >= 1."""
+    m = mixture_struct(mix)
+    n = np.ascontiguousarray(np.atleast_2d(n), dtype=np.float64)
+    out = np.full(n.shape[0], np.nan)
+    p = np.zeros(1)
+    for i in range(n.shape[0]):
+        code = lib().lbm_fugacity(ctypes.byref(m), float(T), 1, _dptr(np.ascontiguousarray(n[i:i + 1])),
+                                  _dptr(p), None, None, None)
+        if code == LBM_OK:
+            out[i] = p[0]
+        elif code != LBM_ERR_DOMAIN:
+            _check(code)
+    return out
+
+
 class FlashResult:
     def __init__(self, r: LbmFlashResult, nc: int):
         for name in ("V", "Zl", "Zv", "rho_l", "rho_v", "residual", "iterations"):
@@ -196,6 +235,9 @@ class LibThermo:
 
     def flash(self, mix, T, p, z):
         return lbm_flash(mix, T, p, z)
+
+    def pressure(self, mix, T, n):
+        return lbm_pressure(mix, T, n)
 
 
 # ---------------------------------------------------------------------------
@@ -326,6 +368,118 @@ class LbmContext:
     def close(self):
         if getattr(self, "_ctx", None) is not None:
             lib().lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LbmBatch:
+    """Many independent boxes advanced together (one lbm_batch).
+
+    boxes: list of dicts {"mix", "shape" (ny, nx) or (nz, ny, nx), "T", "tau", "beta",
+    "gamma", "rho0" (nc, *shape)}.  With graph_steps > 0 the batch runs on its own
+    (default-priority) stream so the steps can be captured in a HIP graph.
+    """
+
+    def __init__(self, boxes, lattice="D2Q9", collision="bgk", forcing="edm", storage="f64", tile=0,
+                 graph_steps=0, grid=0, mrt_s=None, accel=None, G=-1.0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lattice = lattice
+        self.Q = Q_OF[lattice]
+        n = len(boxes)
+        arr = (LbmBox * n)()
+        self.shapes, self.ncs = [], []
+        for i, bx in enumerate(boxes):
+            shape = tuple(int(v) for v in bx["shape"])
+            if lattice == "D2Q9":
+                ny, nx = shape
+                nz = 1
+            else:
+                nz, ny, nx = shape
+            arr[i].mix = mixture_struct(bx["mix"])
+            arr[i].nx, arr[i].ny, arr[i].nz = nx, ny, nz
+            arr[i].T = float(bx["T"])
+            arr[i].tau = float(bx.get("tau", 0.8))
+            arr[i].G = float(bx.get("G", G))
+            arr[i].beta = float(bx["beta"])
+            for k, g in enumerate(bx["gamma"]):
+                arr[i].gamma[k] = float(g)
+            self.shapes.append(shape)
+            self.ncs.append(len(bx["mix"]["a"]))
+        self._boxes = arr
+        prm = LbmBatchParams()
+        prm.lattice = LATTICES[lattice]
+        prm.collision = COLLISIONS[collision]
+        prm.forcing = FORCINGS[forcing]
+        prm.storage = STORAGES[storage]
+        prm.tile = int(tile)
+        prm.graph_steps = int(graph_steps)
+        prm.grid = int(grid)
+        if mrt_s is not None:
+            for k, v in enumerate(mrt_s):
+                prm.mrt_s[k] = float(v)
+        if accel is not None:
+            for d, v in enumerate(accel):
+                prm.accel[d] = float(v)
+        self._prm = prm
+        ws, fe, pe = c_size_t(0), c_size_t(0), c_size_t(0)
+        _check(lib().lbm_batch_layout(arr, n, ctypes.byref(prm), ctypes.byref(ws), ctypes.byref(fe),
+                                      ctypes.byref(pe)))
+        self.field_elems, self.pop_elems = int(fe.value), int(pe.value)
+        self.stream = torch.cuda.Stream(device=device) if graph_steps > 0 else torch.cuda.current_stream(device)
+        cur = torch.cuda.current_stream(device)
+        self.workspace = torch.empty(int(ws.value) + 256, dtype=torch.uint8, device=device)
+        wsp = (self.workspace.data_ptr() + 255) // 256 * 256
+        rho0 = torch.cat([torch.as_tensor(bx["rho0"], dtype=torch.float64).reshape(-1) for bx in boxes]).to(device)
+        assert rho0.numel() == self.field_elems
+        self.stream.wait_stream(cur)
+        ctx = c_void_p()
+        _check(lib().lbm_batch_init(arr, n, ctypes.byref(prm), c_void_p(wsp), c_size_t(int(ws.value)),
+                                    c_void_p(rho0.data_ptr()), c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    def step(self, n=1):
+        _check(lib().lbm_batch_step(self._ctx, int(n)))
+
+    def check(self):
+        _check(lib().lbm_batch_check(self._ctx))
+
+    def box_errors(self):
+        """Per-box error flags (numpy int array, 1 = the box left the EOS domain)."""
+        flags = (c_int * len(self.shapes))()
+        _check(lib().lbm_batch_box_errors(self._ctx, flags))
+        return np.array(flags[:], dtype=np.int64)
+
+    def fields(self, populations=False):
+        """Per-box rbar (list of (nc, *shape) tensors) and optionally populations."""
+        torch = self.torch
+        dev = self.workspace.device
+        rho = torch.empty(self.field_elems, dtype=torch.float64, device=dev)
+        f = torch.empty(self.pop_elems, dtype=torch.float64, device=dev) if populations else None
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        _check(lib().lbm_batch_fields(self._ctx, c_void_p(rho.data_ptr()),
+                                      None if f is None else c_void_p(f.data_ptr())))
+        self.stream.synchronize()
+        out_r, out_f = [], []
+        o, of = 0, 0
+        for shape, nc in zip(self.shapes, self.ncs):
+            cells = int(np.prod(shape))
+            out_r.append(rho[o: o + nc * cells].reshape((nc,) + shape))
+            o += nc * cells
+            if f is not None:
+                out_f.append(f[of: of + nc * self.Q * cells].reshape((nc, self.Q) + shape))
+                of += nc * self.Q * cells
+        return (out_r, out_f) if populations else out_r
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None:
+            lib().lbm_batch_destroy(self._ctx)
             self._ctx = None
 
     def __del__(self):

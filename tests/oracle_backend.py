@@ -23,5 +23,12 @@ class OracleThermo:
     def flash(self, mix, T, p, z):
         return thermo.flash(to_mixture(mix), T, p, z)
 
+    def pressure(self, mix, T, n):
+        m = to_mixture(mix)
+        n = np.atleast_2d(np.asarray(n, dtype=np.float64))
+        p = thermo.pressure_molar(n.T, T, m)
+        inside = (n @ m.b) < 1.0
+        return np.where(inside, p, np.nan)
+
 
 BACKEND = OracleThermo()
