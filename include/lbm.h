@@ -263,6 +263,52 @@ lbm_status lbm_batch_box_errors(lbm_batch* b, int* flags_host);
 /* Release the batch (not the caller's workspace); NULL is accepted. */
 void lbm_batch_destroy(lbm_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint (reverse-mode derivative of the step).  The paper does not
+ * differentiate its model; these calls give the exact derivative of the discrete
+ * step of Sec. 3.4 (the transpose of its Jacobian), evaluated in float64 at the
+ * stored states, for BGK collision with the exact-difference forcing (any storage,
+ * lattice and nc; other collision/forcing choices return LBM_ERR_ARG).
+ * Parameters: the EOS tables aa_ij = sqrt(a_i alpha_i a_j alpha_j)(1 - k_ij) and
+ * b_i of Eq. (randommixingrule) / Eq. (MCPengRobinson), chained to (k_ij, a_i, b_i)
+ * with alpha_i following a_i and b_i through Tc_i (Sec. 3.2).
+ * ------------------------------------------------------------------------- */
+
+/* Device workspace bytes of lbm_adjoint for `nsteps` steps with a checkpoint every
+ * `checkpoint_every` steps: two float64 adjoint population arrays, per-cell scratch,
+ * ceil(nsteps/K) checkpoints and K - 1 recomputed states in the context's storage.
+ * lbm_step_adjoint needs lbm_adjoint_workspace(ctx, 1, 1). */
+lbm_status lbm_adjoint_workspace(const lbm_ctx* ctx, int nsteps, int checkpoint_every, size_t* bytes);
+
+/* One reverse step at the context's current state f(t) (the state is not changed):
+ *   h_next_dev [nc][Q][cells] float64: dL/d(post-streaming populations after the step)
+ *   h_out_dev  [nc][Q][cells] float64: receives dL/d f(t) (must not alias h_next_dev)
+ *   d_aa_host  [nc*nc] += dL/d aa_ij over ordered pairs (i, j) (aa_ij and aa_ji counted
+ *              as separate entries);   d_b_host [nc] += dL/d b_i through the EOS.
+ * Synchronises the stream; LBM_ERR_DOMAIN if the state is outside the EOS domain. */
+lbm_status lbm_step_adjoint(lbm_ctx* ctx, const double* h_next_dev, double* h_out_dev, double* d_aa_host,
+                            double* d_b_host, void* workspace_dev, size_t workspace_bytes);
+
+/* Gradient run.  Advances the context by nsteps (as lbm_step), keeping a checkpoint
+ * every checkpoint_every steps in the workspace; evaluates
+ *   L = sum_i (x_i - x_target_i)^2,  x_i = N_i / sum_j N_j,  N_i = sum_{mask} rbar_i / M_i
+ * over the cells with mask_dev[cell] != 0 (uint8 [cells]) of the final state; then
+ * runs the adjoint back to the starting state, recomputing each segment's states
+ * from its checkpoint.  Outputs (host): *loss_host, x_liq_host [nc] (may be NULL),
+ * d_k_host [nc*nc] (symmetric; entry (i,j) = (j,i) = dL/dk_ij for the symmetric
+ * parameter, diagonal 0), d_a_host [nc], d_b_host [nc].  Synchronises the stream. */
+lbm_status lbm_adjoint(lbm_ctx* ctx, int nsteps, int checkpoint_every, const unsigned char* mask_dev,
+                       const double* x_target_host, void* workspace_dev, size_t workspace_bytes,
+                       double* loss_host, double* x_liq_host, double* d_k_host, double* d_a_host,
+                       double* d_b_host);
+
+/* Host chain rule from the EOS-table derivatives (d_aa over ordered pairs, d_b_direct
+ * through the EOS) to d_k (as in lbm_adjoint), d_a and d_b, with alpha_i following
+ * a_i and b_i through Tc_i (Sec. 3.2).  All arrays host float64. */
+lbm_status lbm_eos_param_grad(const lbm_mixture* mix, double T, const double* d_aa_host,
+                              const double* d_b_direct_host, double* d_k_host, double* d_a_host,
+                              double* d_b_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,7 @@
 #include <new>
 
 #include "lbm.h"
-#include "lbm_dispatch.hpp"
+#include "lbm_ctx.hpp"
 #include "lbm_internal.hpp"
 
 namespace {
@@ -39,8 +39,6 @@ lbm_status lbm_fail(lbm_status code, const char* fmt, ...) {
 extern "C" const char* lbm_last_error(void) { return g_err; }
 
 namespace lbmk {
-
-constexpr int kMaxRed = LBM_MAX_NC + 6;   // reduction width: nc masses + 2 * D
 
 // sum of the per-block partials in a fixed order (one block)
 __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ partials, int nblocks, int K,
@@ -63,24 +61,6 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
 }  // namespace lbmk
 
 using namespace lbmk;
-
-struct lbm_ctx {
-  lbm_mixture mix;
-  lbm_params prm;
-  KParams kp;
-  Ops ops;
-  int Q, D, K;
-  int slab;               // planes per slab (blocked schedule)
-  size_t cells;
-  hipStream_t stream;
-  Bufs pops[2];
-  StepScratch sc;
-  double* psi;
-  double* partials;
-  double* totals;
-  int* err;
-  int cur;
-};
 
 namespace {
 
@@ -269,6 +249,7 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
   kp.err = c->err;
   c->ops = prm->lattice == LBM_D2Q9 ? ops_d2q9(mix->nc, prm->storage, prm->collision, prm->forcing)
                                     : ops_d3q19(mix->nc, prm->storage, prm->collision, prm->forcing);
+  c->adj = prm->lattice == LBM_D2Q9 ? adj_ops_d2q9(mix->nc, prm->storage) : adj_ops_d3q19(mix->nc, prm->storage);
   if (prm->slab_planes > 0) {
     c->slab = prm->slab_planes;
   } else {

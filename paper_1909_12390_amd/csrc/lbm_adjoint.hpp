@@ -1,0 +1,266 @@
+// Discrete adjoint of one step (BGK collision with the exact-difference forcing),
+// i.e. the transpose of the step's Jacobian applied to the adjoint of the
+// post-streaming populations after the step, plus the step's contribution to the
+// derivative with respect to the EOS tables (a alpha)_ij (1 - k_ij) and b_i.
+//
+// Forward step at cell x (post-streaming populations f_sa(x), Sec. 3.4 order):
+//   rbar_s = sum_a f_sa, rho = sum_s rbar_s, j = sum_sa e_a f_sa, u = j / rho
+//   p = p_EOS(rbar / M) (Eq. MCPengRobinson), X = 6 (p - rho/3) / G, psi = sqrt(X)
+//   F(x) = -G sum_a w_a e_a psi(x+e_a) (beta psi(x) + hb psi(x+e_a)),  hb = (1-beta)/2
+//   Gamma = sum_s gamma_s rbar_s, du_s = gamma_s F / Gamma, v_s = u + du_s + g
+//   f*_sa = (1-omega) f_sa + (omega-1) feq_a(rbar_s, u) + feq_a(rbar_s, v_s)
+//   f_sa(x + e_a, t+1) = f*_sa(x)
+// with feq_a(r, v) = w_a r (1 + 3 e.v + 9/2 (e.v)^2 - 3/2 v.v).
+//
+// Reverse, given h_sa(y) = dL/df_sa(y, t+1):
+//   hs_sa(x) = h_sa(x + e_a)                           (adjoint of f*)
+//   per component, moments A0 = sum_a w_a hs_a, A1 = sum_a w_a e_a hs_a,
+//   A2 = sum_a w_a e_a e_a hs_a give
+//     sum_a hs_a feq_a(r, v) = r Phi(v),  Phi(v) = A0 (1 - 3/2 v.v) + 3 A1.v + 9/2 v.A2.v
+//     d/dv = r gPhi(v),                   gPhi(v) = -3 A0 v + 3 A1 + 9 A2 v
+//   rbar^_s   = (omega-1) Phi_s(u) + Phi_s(v_s) + gamma_s Gamma^ - u^.u / rho + [EOS, psi terms]
+//   u^        = sum_s rbar_s ((omega-1) gPhi_s(u) + gPhi_s(v_s)),  j^ = u^ / rho
+//   du^_s     = rbar_s gPhi_s(v_s),  F^ = sum_s gamma_s du^_s / Gamma
+//   Gamma^    = -sum_s (gamma_s F / Gamma) . du^_s / Gamma
+//   psi^(y)   = -G beta sum_a w_a (e_a.F^(y)) psi(y+e_a)
+//               - G sum_a w_a (e_a.F^(y-e_a)) (beta psi(y-e_a) + 2 hb psi(y))
+//   X^ = psi^ / (2 psi), p^ = 6 X^ / G, rho^ += -2 X^ / G
+//   rbar^_s  += p^ dp/dn_s / M_s
+//   dL/df_sa(y, t) = (1-omega) hs_sa(y) + e_a.j^(y) + rbar^_s(y)
+// and, with n_t = sum n, B = sum b n, A = sum n_i n_j aa_ij, D = 1 + 2B - B^2,
+//   dp/dn_i  = RT/(1-B) + n_t RT b_i/(1-B)^2 - 2 (aa n)_i / D + 2 A b_i (1-B) / D^2
+//   dp/daa_ij = -n_i n_j / D            dp/db_i = n_i (n_t RT/(1-B)^2 + 2 A (1-B)/D^2).
+//
+// Two passes per step: ka_cell (everything local to x, writes F^, j^, the local
+// part of rbar^ and rbar) and kb_cell (the transposed psi stencil, the EOS adjoint,
+// the output and the parameter partials).  psi of the state comes from k_psi.
+#pragma once
+#include "lbm_aux.hpp"
+
+namespace lbmk {
+
+// per-cell scratch of the adjoint passes (float64, [k][cells])
+struct AdjScratch {
+  double* Fbar;    // [D]
+  double* jbar;    // [D]
+  double* rbA;     // [NC] local part of rbar^
+  double* rb;      // [NC] rbar of the state
+};
+
+template <int LAT, int NC, int ST>
+__global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, const double* __restrict__ psi,
+                                                 const double* __restrict__ h, AdjScratch S) {
+  using V = VS<LAT>;
+  using R = typename Pops<ST>::R;
+  constexpr int Q = V::Q, D = V::D;
+  unsigned cell;
+  if (!launch_cell(P, 0, P.nplanes, &cell)) return;
+  const Coord c = make_coord(cell, P);
+  const size_t N = (size_t)P.cells;
+  // forward quantities at x
+  double rb[NC], rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    const auto cv = state.comp(s, Q, P.cells);
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const double v = (double)cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+      acc += v;
+      if (V::cx(a)) j[0] += V::cx(a) * v;
+      if (V::cy(a)) j[1] += V::cy(a) * v;
+      if (V::cz(a)) j[2] += V::cz(a) * v;
+    }
+    rb[s] = acc;
+    rho += acc;
+  }
+  const double irho = 1.0 / rho;
+  const double u[3] = {j[0] * irho, j[1] * irho, j[2] * irho};
+  double Gam = 0.0;
+#pragma unroll
+  for (int s = 0; s < NC; ++s) Gam += P.gamma[s] * rb[s];
+  const double iG = 1.0 / Gam;
+  double F[3];
+  force_at<LAT>(P, psi[cell], [&](int a) { return psi[c.at(V::cx(a), V::cy(a), V::cz(a))]; }, F);
+  const double om = P.omega;
+  double ub[3] = {0.0, 0.0, 0.0}, Fb[3] = {0.0, 0.0, 0.0}, Gb = 0.0;
+  double rbA[NC];
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    // moments of the adjoint of f* (gathered from the downstream neighbours)
+    double A0 = 0.0, A1[3] = {0.0, 0.0, 0.0}, A2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // xx yy zz xy xz yz
+    const double* hs = h + (size_t)s * Q * N;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const double g = V::w(a) * hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))];
+      const int ex = V::cx(a), ey = V::cy(a), ez = V::cz(a);
+      A0 += g;
+      if (ex) A1[0] += ex * g;
+      if (ey) A1[1] += ey * g;
+      if (ez) A1[2] += ez * g;
+      if (ex) A2[0] += g;
+      if (ey) A2[1] += g;
+      if (ez) A2[2] += g;
+      if (ex * ey) A2[3] += ex * ey * g;
+      if (ex * ez) A2[4] += ex * ez * g;
+      if (ey * ez) A2[5] += ey * ez * g;
+    }
+    double duF[3], v[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      duF[d] = P.gamma[s] * F[d] * iG;
+      v[d] = u[d] + duF[d] + P.accel[d];
+    }
+    auto phi = [&](const double* w) {
+      const double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+      const double wAw = A2[0] * w[0] * w[0] + A2[1] * w[1] * w[1] + A2[2] * w[2] * w[2] +
+                         2.0 * (A2[3] * w[0] * w[1] + A2[4] * w[0] * w[2] + A2[5] * w[1] * w[2]);
+      return A0 * (1.0 - 1.5 * ww) + 3.0 * (A1[0] * w[0] + A1[1] * w[1] + A1[2] * w[2]) + 4.5 * wAw;
+    };
+    auto gphi = [&](const double* w, double* out) {
+      const double Aw[3] = {A2[0] * w[0] + A2[3] * w[1] + A2[4] * w[2], A2[3] * w[0] + A2[1] * w[1] + A2[5] * w[2],
+                            A2[4] * w[0] + A2[5] * w[1] + A2[2] * w[2]};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) out[d] = -3.0 * A0 * w[d] + 3.0 * A1[d] + 9.0 * Aw[d];
+    };
+    double gu[3], gv[3];
+    gphi(u, gu);
+    gphi(v, gv);
+    rbA[s] = (om - 1.0) * phi(u) + phi(v);
+    double dub[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      ub[d] += rb[s] * ((om - 1.0) * gu[d] + gv[d]);
+      dub[d] = rb[s] * gv[d];
+      Fb[d] += P.gamma[s] * iG * dub[d];
+    }
+    Gb -= (duF[0] * dub[0] + duF[1] * dub[1] + duF[2] * dub[2]) * iG;
+  }
+  const double uub = (ub[0] * u[0] + ub[1] * u[1] + ub[2] * u[2]) * irho;
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    S.rbA[(size_t)s * N + cell] = rbA[s] + P.gamma[s] * Gb - uub;
+    S.rb[(size_t)s * N + cell] = rb[s];
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    S.Fbar[(size_t)d * N + cell] = Fb[d];
+    S.jbar[(size_t)d * N + cell] = ub[d] * irho;
+  }
+}
+
+// Parameter partials per block: [dL/daa_ij (NC*NC, ordered pairs), dL/db_i (NC)].
+template <int LAT, int NC>
+__global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __restrict__ psi,
+                                                 const double* __restrict__ h, AdjScratch S,
+                                                 double* __restrict__ hout, double* __restrict__ partials) {
+  using V = VS<LAT>;
+  constexpr int Q = V::Q, D = V::D, K = NC * NC + NC;
+  double vals[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) vals[k] = 0.0;
+  unsigned cell;
+  if (launch_cell(P, 0, P.nplanes, &cell)) {
+    const Coord c = make_coord(cell, P);
+    const size_t N = (size_t)P.cells;
+    const double hb = 0.5 * (1.0 - P.beta);
+    const double ps = psi[cell];
+    // transposed stencil of Eq. (coupledMCforce)
+    double pb = 0.0;
+    const double Fx = S.Fbar[cell], Fy = S.Fbar[N + cell], Fz = D == 3 ? S.Fbar[2 * N + cell] : 0.0;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const int ex = V::cx(a), ey = V::cy(a), ez = V::cz(a);
+      const double eF = ex * Fx + ey * Fy + ez * Fz;
+      pb += V::w(a) * eF * psi[c.at(ex, ey, ez)] * P.beta;
+      const unsigned up = c.at(-ex, -ey, -ez);
+      double eFn = ex * S.Fbar[up] + ey * S.Fbar[N + up];
+      if (D == 3) eFn += ez * S.Fbar[2 * N + up];
+      pb += V::w(a) * eFn * (P.beta * psi[up] + 2.0 * hb * ps);
+    }
+    pb *= -P.G;
+    const double Xb = pb / (2.0 * ps);
+    const double pbar = 6.0 * Xb / P.G;
+    const double rcommon = -2.0 * Xb / P.G;
+    // EOS adjoint
+    double n[NC], rt = 0.0, Bn = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      n[i] = S.rb[(size_t)i * N + cell] * P.invM[i];
+      rt += n[i];
+      Bn += P.b[i] * n[i];
+    }
+    double an[NC], An = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) s += P.aa[i][k] * n[k];
+      an[i] = s;
+      An += n[i] * s;
+    }
+    const double omB = 1.0 - Bn, iomB = 1.0 / omB;
+    const double Dd = 1.0 + 2.0 * Bn - Bn * Bn, iD = 1.0 / Dd;
+    const double dpdB = rt * P.RT * iomB * iomB + 2.0 * An * omB * iD * iD;
+    double rbar[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const double dpdn = P.RT * iomB + P.b[i] * dpdB - 2.0 * an[i] * iD;
+      rbar[i] = S.rbA[(size_t)i * N + cell] + rcommon + pbar * dpdn * P.invM[i];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) vals[i * NC + k] = -pbar * n[i] * n[k] * iD;
+      vals[NC * NC + i] = pbar * n[i] * dpdB;
+    }
+    const double jb[3] = {S.jbar[cell], S.jbar[N + cell], D == 3 ? S.jbar[2 * N + cell] : 0.0};
+    const double keep = 1.0 - P.omega;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+      const double* hs = h + (size_t)s * Q * N;
+      double* ho = hout + (size_t)s * Q * N;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const double ej = V::cx(a) * jb[0] + V::cy(a) * jb[1] + V::cz(a) * jb[2];
+        ho[(size_t)a * N + cell] = keep * hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))] + ej + rbar[s];
+      }
+    }
+  }
+  block_partials<K>(vals, partials);
+}
+
+// Masked molar sums N_s = sum_{mask} rbar_s / M_s of the post-streaming state
+// (per-block partials, [NC]).
+template <int LAT, int NC, int ST>
+__global__ __launch_bounds__(kBlock) void k_masked_moles(KParams P, Pops<ST> state,
+                                                        const unsigned char* __restrict__ mask,
+                                                        double* __restrict__ partials) {
+  double vals[NC];
+#pragma unroll
+  for (int s = 0; s < NC; ++s) vals[s] = 0.0;
+  unsigned cell;
+  if (launch_cell(P, 0, P.nplanes, &cell) && mask[cell]) {
+    const Coord c = make_coord(cell, P);
+    typename Pops<ST>::R jr[3] = {0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NC; ++s) vals[s] = pull_moments<LAT, ST>(P, state, s, c, jr) * P.invM[s];
+  }
+  block_partials<NC>(vals, partials);
+}
+
+// Adjoint seed of L(N): dL/df_sa(y) = mask(y) * coef_s for every direction.
+template <int LAT, int NC>
+__global__ __launch_bounds__(kBlock) void k_adj_seed(KParams P, const unsigned char* __restrict__ mask,
+                                                    double c0, double c1, double c2, double c3,
+                                                    double* __restrict__ h) {
+  using V = VS<LAT>;
+  unsigned cell;
+  if (!launch_cell(P, 0, P.nplanes, &cell)) return;
+  const double coef[4] = {c0, c1, c2, c3};
+  const size_t N = (size_t)P.cells;
+  const bool in = mask[cell] != 0;
+#pragma unroll
+  for (int s = 0; s < NC; ++s)
+#pragma unroll
+    for (int a = 0; a < V::Q; ++a) h[((size_t)s * V::Q + a) * N + cell] = in ? coef[s] : 0.0;
+}
+
+}  // namespace lbmk

@@ -1,0 +1,32 @@
+// The context behind the opaque lbm_ctx handle of the C ABI (host side), shared by
+// the translation units that implement the step and its adjoint.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lbm.h"
+#include "lbm_dispatch.hpp"
+
+namespace lbmk {
+
+constexpr int kMaxRed = LBM_MAX_NC + 6;   // reduction width: nc masses + 2 * D
+
+}  // namespace lbmk
+
+struct lbm_ctx {
+  lbm_mixture mix;
+  lbm_params prm;
+  lbmk::KParams kp;
+  lbmk::Ops ops;
+  lbmk::AdjOps adj;
+  int Q, D, K;
+  int slab;               // planes per slab (blocked schedule)
+  size_t cells;
+  hipStream_t stream;
+  lbmk::Bufs pops[2];
+  lbmk::StepScratch sc;
+  double* psi;
+  double* partials;
+  double* totals;
+  int* err;
+  int cur;
+};

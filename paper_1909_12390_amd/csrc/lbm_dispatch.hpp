@@ -1,7 +1,7 @@
 // Launchers of the step and auxiliary kernels, instantiated per (lattice, nc,
 // storage, collision, forcing) in the per-lattice translation units.
 #pragma once
-#include "lbm_aux.hpp"
+#include "lbm_adjoint.hpp"
 
 namespace lbmk {
 
@@ -109,8 +109,63 @@ Ops ops_lat(int nc, int st, int coll, int forc) {
   }
 }
 
+// Launchers of the adjoint passes (BGK + exact-difference forcing) and of the loss
+// helpers, per (lattice, nc, storage).
+struct AdjOps {
+  void (*a)(const KParams&, const Bufs& state, const double* psi, const double* h, const AdjScratch&, hipStream_t);
+  void (*b)(const KParams&, const double* psi, const double* h, const AdjScratch&, double* hout, double* partials,
+            hipStream_t);
+  void (*moles)(const KParams&, const Bufs& state, const unsigned char* mask, double* partials, hipStream_t);
+  void (*seed)(const KParams&, const unsigned char* mask, const double* coef, double* h, hipStream_t);
+};
+
+template <int LAT, int NC, int ST>
+struct AdjOpsImpl {
+  static void a(const KParams& P, const Bufs& state, const double* psi, const double* h, const AdjScratch& S,
+                hipStream_t st) {
+    hipLaunchKernelGGL((ka_cell<LAT, NC, ST>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
+                       make_pops<ST>(state), psi, h, S);
+  }
+  static void b(const KParams& P, const double* psi, const double* h, const AdjScratch& S, double* hout,
+                double* partials, hipStream_t st) {
+    hipLaunchKernelGGL((kb_cell<LAT, NC>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P, psi, h, S, hout,
+                       partials);
+  }
+  static void moles(const KParams& P, const Bufs& state, const unsigned char* mask, double* partials,
+                    hipStream_t st) {
+    hipLaunchKernelGGL((k_masked_moles<LAT, NC, ST>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
+                       make_pops<ST>(state), mask, partials);
+  }
+  static void seed(const KParams& P, const unsigned char* mask, const double* coef, double* h, hipStream_t st) {
+    hipLaunchKernelGGL((k_adj_seed<LAT, NC>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P, mask, coef[0],
+                       coef[1], coef[2], coef[3], h);
+  }
+  static AdjOps ops() { return AdjOps{&a, &b, &moles, &seed}; }
+};
+
+template <int LAT, int NC>
+AdjOps adj_ops_st(int st) {
+  switch (st) {
+    case LBM_F64: return AdjOpsImpl<LAT, NC, LBM_F64>::ops();
+    case LBM_F32_OFS: return AdjOpsImpl<LAT, NC, LBM_F32_OFS>::ops();
+    default: return AdjOpsImpl<LAT, NC, LBM_F16_OFS>::ops();
+  }
+}
+
+template <int LAT>
+AdjOps adj_ops_lat(int nc, int st) {
+  switch (nc) {
+    case 1: return adj_ops_st<LAT, 1>(st);
+    case 2: return adj_ops_st<LAT, 2>(st);
+    case 3: return adj_ops_st<LAT, 3>(st);
+    default: return adj_ops_st<LAT, 4>(st);
+  }
+}
+
 // defined in lbm_d2q9.hip / lbm_d3q19.hip
 Ops ops_d2q9(int nc, int st, int coll, int forc);
 Ops ops_d3q19(int nc, int st, int coll, int forc);
+AdjOps adj_ops_d2q9(int nc, int st);
+AdjOps adj_ops_d3q19(int nc, int st);
 
 }  // namespace lbmk

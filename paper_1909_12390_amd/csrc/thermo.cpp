@@ -399,3 +399,42 @@ void lbm_internal_aalpha(const lbm_mixture* mix, double T, double* aa_out) {
   if (!load_mix(mix, &mx)) return;
   aalpha(mx, T, aa_out);
 }
+
+// Chain rule from the EOS tables to the component parameters.  With
+// (a alpha)_l = a_l alpha_l(T / Tc_l), Tc_l = (Omega_b / Omega_a) a_l / (b_l R) and
+// aa_ij = sqrt((a alpha)_i (a alpha)_j) (1 - k_ij) (Sec. 3.2):
+//   d aa_ij / d (a alpha)_l = aa_ij (d_il + d_jl) / (2 (a alpha)_l)
+//   d (a alpha)_l / d a_l = alpha_l + Tc_l alpha'_l,  d (a alpha)_l / d b_l = -a_l Tc_l alpha'_l / b_l
+//   alpha'_l = d alpha_l / d Tc_l = sqrt(alpha_l) m_l sqrt(T / Tc_l) / Tc_l
+//   d aa_ij / d k_ij = -sqrt((a alpha)_i (a alpha)_j) for each ordered pair.
+extern "C" lbm_status lbm_eos_param_grad(const lbm_mixture* mix, double T, const double* d_aa,
+                                         const double* d_b_direct, double* d_k, double* d_a, double* d_b) {
+  Mix mx;
+  if (!load_mix(mix, &mx)) return LBM_ERR_ARG;
+  if (!d_aa || !d_b_direct || !d_k || !d_a || !d_b) return lbm_fail(LBM_ERR_ARG, "NULL argument");
+  if (!(T > 0.0)) return lbm_fail(LBM_ERR_ARG, "T must be positive");
+  const int nc = mx.nc;
+  double al[LBM_MAX_NC], aal[LBM_MAX_NC], dal[LBM_MAX_NC];
+  for (int l = 0; l < nc; ++l) {
+    const double r = std::sqrt(T / mx.Tc[l]);
+    const double s = 1.0 + mx.m[l] * (1.0 - r);
+    al[l] = s * s;
+    aal[l] = mx.a[l] * al[l];
+    dal[l] = s * mx.m[l] * r / mx.Tc[l];
+  }
+  for (int l = 0; l < nc; ++l) {
+    double g = 0.0;
+    for (int j = 0; j < nc; ++j) {
+      const double aa_lj = std::sqrt(aal[l] * aal[j]) * (1.0 - mx.k[l][j]);
+      const double aa_jl = std::sqrt(aal[j] * aal[l]) * (1.0 - mx.k[j][l]);
+      g += d_aa[l * nc + j] * aa_lj + d_aa[j * nc + l] * aa_jl;
+    }
+    g /= 2.0 * aal[l];
+    d_a[l] = g * (al[l] + mx.Tc[l] * dal[l]);
+    d_b[l] = d_b_direct[l] - g * mx.a[l] * mx.Tc[l] * dal[l] / mx.b[l];
+  }
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nc; ++j)
+      d_k[i * nc + j] = (i == j) ? 0.0 : -std::sqrt(aal[i] * aal[j]) * (d_aa[i * nc + j] + d_aa[j * nc + i]);
+  return LBM_OK;
+}

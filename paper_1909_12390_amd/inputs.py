@@ -267,6 +267,23 @@ def config_c5(backend, shape=(128, 128), R0=32.0) -> Config:
                   geometry={"kind": "drop", "R0": R0})
 
 
+def drop_mask(shape, R0):
+    """Cells of a centred drop's bulk: distance to the box centre <= R0/2."""
+    g = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+    r = np.sqrt(sum((x - n / 2.0) ** 2 for x, n in zip(g, shape)))
+    return r <= R0 / 2.0
+
+
+def adjoint_target(cfg: Config, amplitude=0.02, seed=1):
+    """Target liquid composition for the adjoint loss: the flash liquid mole
+    fractions (from rbar_l / M) moved by seeded U[-amplitude, amplitude] and
+    renormalised to sum 1."""
+    x = np.asarray(cfg.rbar_l, dtype=np.float64) / np.asarray(cfg.mix["M"], dtype=np.float64)
+    x = x / x.sum()
+    t = x + rng_for(5, seed).uniform(-amplitude, amplitude, x.shape)
+    return t / t.sum()
+
+
 BOX_SIDES = (32, 48, 64, 96, 128)
 
 

@@ -36,7 +36,8 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "lbm_set_populations", "lbm_check", "lbm_clear_error", "lbm_destroy", "lbm_last_error",
             "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure",
             "lbm_batch_layout", "lbm_batch_init", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_check",
-            "lbm_batch_box_errors", "lbm_batch_destroy"]
+            "lbm_batch_box_errors", "lbm_batch_destroy", "lbm_adjoint_workspace", "lbm_step_adjoint",
+            "lbm_adjoint", "lbm_eos_param_grad"]
 
 
 class LbmError(RuntimeError):
@@ -116,6 +117,10 @@ def lib() -> ctypes.CDLL:
         L.lbm_batch_box_errors.argtypes = [c_void_p, POINTER(c_int)]
         L.lbm_batch_destroy.argtypes = [c_void_p]
         L.lbm_batch_destroy.restype = None
+        L.lbm_adjoint_workspace.argtypes = [c_void_p, c_int, c_int, POINTER(c_size_t)]
+        L.lbm_step_adjoint.argtypes = [c_void_p, c_void_p, c_void_p, dp, dp, c_void_p, c_size_t]
+        L.lbm_adjoint.argtypes = [c_void_p, c_int, c_int, c_void_p, dp, c_void_p, c_size_t, dp, dp, dp, dp, dp]
+        L.lbm_eos_param_grad.argtypes = [POINTER(LbmMixture), c_double, dp, dp, dp, dp, dp]
         for name in EXPORTED:
             f = getattr(L, name)
             if name not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy"):
@@ -365,6 +370,50 @@ class LbmContext:
         _check(lib().lbm_set_populations(self._ctx, c_void_p(t.data_ptr())))
         self.stream.synchronize()
 
+    # -- discrete adjoint ---------------------------------------------------
+    def _adjoint_ws(self, nsteps, checkpoint_every):
+        nbytes = c_size_t(0)
+        _check(lib().lbm_adjoint_workspace(self._ctx, int(nsteps), int(checkpoint_every), ctypes.byref(nbytes)))
+        ws = self.torch.empty(int(nbytes.value) + 256, dtype=self.torch.uint8, device=self.workspace.device)
+        return ws, (ws.data_ptr() + 255) // 256 * 256, int(nbytes.value)
+
+    def step_adjoint(self, h_next):
+        """One reverse step at the current state: returns (dL/df(t) as a float64
+        device tensor [nc, Q, *shape], dL/daa [nc, nc], dL/db [nc] through the EOS)."""
+        torch = self.torch
+        h = self._to_device(h_next, (self.nc, self.Q) + self.shape)
+        out = torch.empty_like(h)
+        daa = np.zeros(self.nc * self.nc)
+        db = np.zeros(self.nc)
+        ws, ptr, nbytes = self._adjoint_ws(1, 1)
+        _check(lib().lbm_step_adjoint(self._ctx, c_void_p(h.data_ptr()), c_void_p(out.data_ptr()), _dptr(daa),
+                                      _dptr(db), c_void_p(ptr), c_size_t(nbytes)))
+        del ws
+        return out, daa.reshape(self.nc, self.nc), db
+
+    def adjoint(self, nsteps, checkpoint_every, mask, x_target):
+        """Advance nsteps with checkpoints, then return {"loss", "x_liq", "d_k" (nc x nc),
+        "d_a", "d_b"} of L = sum (x_liq - x_target)^2 over the cells where mask != 0."""
+        torch = self.torch
+        m = torch.as_tensor(np.asarray(mask), dtype=torch.uint8)
+        if tuple(m.shape) != self.shape:
+            raise ValueError(f"mask must have shape {self.shape}")
+        m = m.to(self.workspace.device).contiguous()
+        xt = np.ascontiguousarray(np.asarray(x_target, dtype=np.float64))
+        if xt.shape != (self.nc,):
+            raise ValueError(f"x_target must have {self.nc} entries")
+        loss = np.zeros(1)
+        x = np.zeros(self.nc)
+        dk = np.zeros(self.nc * self.nc)
+        da = np.zeros(self.nc)
+        db = np.zeros(self.nc)
+        ws, ptr, nbytes = self._adjoint_ws(nsteps, checkpoint_every)
+        _check(lib().lbm_adjoint(self._ctx, int(nsteps), int(checkpoint_every), c_void_p(m.data_ptr()), _dptr(xt),
+                                 c_void_p(ptr), c_size_t(nbytes), _dptr(loss), _dptr(x), _dptr(dk), _dptr(da),
+                                 _dptr(db)))
+        del ws
+        return {"loss": float(loss[0]), "x_liq": x, "d_k": dk.reshape(self.nc, self.nc), "d_a": da, "d_b": db}
+
     def close(self):
         if getattr(self, "_ctx", None) is not None:
             lib().lbm_destroy(self._ctx)
@@ -375,6 +424,20 @@ class LbmContext:
             self.close()
         except Exception:
             pass
+
+
+def eos_param_grad(mix: dict, T: float, d_aa, d_b_direct):
+    """Chain EOS-table derivatives to (d_k [nc, nc], d_a [nc], d_b [nc]) (host)."""
+    m = mixture_struct(mix)
+    nc = m.nc
+    daa = np.ascontiguousarray(np.asarray(d_aa, dtype=np.float64).reshape(nc * nc))
+    dbd = np.ascontiguousarray(np.asarray(d_b_direct, dtype=np.float64).reshape(nc))
+    dk = np.zeros(nc * nc)
+    da = np.zeros(nc)
+    db = np.zeros(nc)
+    _check(lib().lbm_eos_param_grad(ctypes.byref(m), float(T), _dptr(daa), _dptr(dbd), _dptr(dk), _dptr(da),
+                                    _dptr(db)))
+    return dk.reshape(nc, nc), da, db
 
 
 class LbmBatch:
