@@ -236,6 +236,50 @@ def batched_section(args, torch, lbm, inputs):
     return res
 
 
+def adjoint_section(args, torch, lbm, inputs):
+    """Gradient of the liquid-composition loss on the ternary D2Q9 128^2 drop:
+    wall time of a forward-only run and of the checkpointed forward + reverse
+    (lbm_adjoint), float32 and float64 storage, and the float32 gradient's
+    relative difference from the float64 one."""
+    from paper_1909_12390_amd import adjoint as padj
+    cfg = inputs.config_c5(lbm.LibThermo())
+    mask = inputs.drop_mask(cfg.shape, cfg.geometry["R0"])
+    x_tgt = inputs.adjoint_target(cfg)
+    res = {"workload": f"ternary D2Q9 {cfg.shape[0]}x{cfg.shape[1]} drop, BGK + exact-difference forcing, "
+                       f"{args.adjoint_steps} steps, checkpoint every {args.adjoint_every}, "
+                       f"loss = squared liquid mole-fraction mismatch",
+           "steps": args.adjoint_steps, "checkpoint_every": args.adjoint_every}
+    grads = {}
+    for storage in ("f32", "f64"):
+        def ctx():
+            return lbm.LbmContext(cfg.mix, "D2Q9", cfg.shape, cfg.T, cfg.tau, cfg.beta, cfg.gamma, cfg.rho0,
+                                  collision="bgk", forcing="edm", storage=storage)
+        c = ctx()
+        c.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(args.adjoint_steps)
+        c.check()
+        fwd = (time.perf_counter() - t0) * 1e3
+        c.close()
+        c = ctx()
+        c.adjoint(20, 10, mask, x_tgt)            # warm-up (workspace, code objects)
+        c.close()
+        c = ctx()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = c.adjoint(args.adjoint_steps, args.adjoint_every, mask, x_tgt)
+        full = (time.perf_counter() - t0) * 1e3
+        c.close()
+        grads[storage] = padj.pack_gradient(r["d_k"], r["d_a"], r["d_b"])
+        res[storage] = {"forward_ms": fwd, "forward_plus_adjoint_ms": full, "ratio": full / fwd,
+                        "loss": r["loss"], "x_liq": r["x_liq"].tolist()}
+    res["gradient_f64"] = grads["f64"].tolist()
+    res["f32_gradient_max_rel_diff_vs_f64"] = float(np.max(np.abs(grads["f32"] - grads["f64"]))
+                                                    / np.max(np.abs(grads["f64"])))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +301,8 @@ def main():
     ap.add_argument("--batch-boxes", type=int, default=512, help="batched section: number of boxes (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--batch-precision-steps", type=int, default=10000)
+    ap.add_argument("--adjoint-steps", type=int, default=2000, help="adjoint section: steps (0 = skip)")
+    ap.add_argument("--adjoint-every", type=int, default=100, help="adjoint section: checkpoint interval")
     args = ap.parse_args()
 
     if args.cpu_baseline_worker:
@@ -387,6 +433,9 @@ def main():
 
     if args.batch_boxes > 0:
         out["batched"] = batched_section(args, torch, lbm, inputs)
+
+    if args.adjoint_steps > 0:
+        out["adjoint"] = adjoint_section(args, torch, lbm, inputs)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_side, args.cpu_steps)

@@ -224,7 +224,8 @@ typedef struct {
 
 typedef struct {
   int lattice, collision, forcing, storage;   /* shared by every box              */
-  int tile;                  /* cells per workgroup: 64, 128, 256, 512, 1024 (0 = 256) */
+  int tile;                  /* cells per work-list tile: 64, 128 or 256 (0 = 256); the
+                                collide pass runs nc_max x tile threads per workgroup */
   int graph_steps;           /* steps per captured HIP graph (rounded up to even; 0 = none).
                                 Capture needs a non-default stream.               */
   int grid;                  /* workgroups of the persistent launch (0 = all resident) */

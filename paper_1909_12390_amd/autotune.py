@@ -11,7 +11,7 @@ import json
 import os
 import time
 
-CANDIDATE_TILES = (64, 128, 256, 512, 1024)
+CANDIDATE_TILES = (64, 128, 256)
 
 
 def _key(boxes, lattice, collision, forcing, storage):

@@ -147,15 +147,24 @@ AdjScratch scratch_of(char* ws, const AdjLayout& L) {
   return S;
 }
 
-// one reverse step at `state`: h (after the step) -> hout (before it); partials
-// accumulated into acc
+// one reverse step at `state`: h (after the step) -> hout (before it); the
+// parameter partials are added to the per-block accumulator `partials`
 void enqueue_reverse(lbm_ctx* c, const Bufs& state, const double* h, double* hout, const AdjScratch& S,
-                     double* partials, double* acc, int ktheta) {
+                     double* partials) {
   c->ops.psi(c->kp, state, c->sc, 0, c->kp.nplanes, c->stream);
   c->adj.a(c->kp, state, c->psi, h, S, c->stream);
   c->adj.b(c->kp, c->psi, h, S, hout, partials, c->stream);
-  hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(kBlock), 0, c->stream, (const double*)partials,
-                     nblocks_for((int)c->cells), ktheta, acc);
+}
+
+void zero(double* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, p, n);
+}
+
+// acc[0..K) = sum over blocks of the per-block accumulator
+void finish_partials(const lbm_ctx* c, const double* partials, int K, double* acc) {
+  zero(acc, 32, c->stream);
+  hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(kBlock), 0, c->stream, partials, nblocks_for((int)c->cells), K,
+                     acc);
 }
 
 lbm_status read_flag(lbm_ctx* c) {
@@ -190,8 +199,11 @@ extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* h_next, double*
   if (ws_bytes < L.total) return lbm_fail(LBM_ERR_ARG, "workspace too small: %zu < %zu", ws_bytes, L.total);
   char* w = (char*)ws;
   double* acc = (double*)(w + L.acc);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, c->stream, acc, 32);
-  enqueue_reverse(c, c->pops[c->cur], h_next, h_out, scratch_of(w, L), (double*)(w + L.partials), acc, L.ktheta);
+  double* partials = (double*)(w + L.partials);
+  const int nb = nblocks_for((int)c->cells);
+  zero(partials, nb * L.ktheta, c->stream);
+  enqueue_reverse(c, c->pops[c->cur], h_next, h_out, scratch_of(w, L), partials);
+  finish_partials(c, partials, L.ktheta, acc);
   st = hip_check(hipGetLastError(), "adjoint launch");
   if (st != LBM_OK) return st;
   double host[LBM_MAX_NC * LBM_MAX_NC + LBM_MAX_NC];
@@ -235,9 +247,8 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, int nsteps, int checkpoint_every, 
   if (st != LBM_OK) return st;
 
   // loss over the mask: N_i = sum rbar_i / M_i, x = N / sum N, L = sum (x - x_tgt)^2
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, c->stream, acc, 32);
   c->adj.moles(c->kp, c->pops[c->cur], mask, partials, c->stream);
-  hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(kBlock), 0, c->stream, (const double*)partials, nb, nc, acc);
+  finish_partials(c, partials, nc, acc);
   double Nm[LBM_MAX_NC];
   st = hip_check(hipMemcpyAsync(Nm, acc, sizeof(double) * nc, hipMemcpyDeviceToHost, c->stream), "read moles");
   if (st == LBM_OK) st = hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
@@ -260,7 +271,7 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, int nsteps, int checkpoint_every, 
     coef[k] = g / c->mix.M[k];
   }
   c->adj.seed(c->kp, mask, coef, hb[0], c->stream);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, c->stream, acc, 32);
+  zero(partials, nb * L.ktheta, c->stream);
 
   // reverse, segment by segment
   int cur = 0;
@@ -276,12 +287,13 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, int nsteps, int checkpoint_every, 
       c->ops.collide(c->kp, in, out, c->sc, 0, c->kp.nplanes, c->stream);
     }
     for (int i = n - 1; i >= 0; --i) {
-      enqueue_reverse(c, slot(i), hb[cur], hb[1 - cur], S, partials, acc, L.ktheta);
+      enqueue_reverse(c, slot(i), hb[cur], hb[1 - cur], S, partials);
       cur = 1 - cur;
     }
     st = hip_check(hipGetLastError(), "adjoint launch");
   }
   if (st != LBM_OK) return st;
+  finish_partials(c, partials, L.ktheta, acc);
   double host[LBM_MAX_NC * LBM_MAX_NC + LBM_MAX_NC];
   st = hip_check(hipMemcpyAsync(host, acc, sizeof(double) * L.ktheta, hipMemcpyDeviceToHost, c->stream),
                  "read parameter adjoint");

@@ -149,7 +149,8 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
   }
 }
 
-// Parameter partials per block: [dL/daa_ij (NC*NC, ordered pairs), dL/db_i (NC)].
+// Parameter partials per block, added to a running per-block accumulator:
+// [dL/daa_ij (NC*NC, ordered pairs), dL/db_i (NC)].
 template <int LAT, int NC>
 __global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __restrict__ psi,
                                                  const double* __restrict__ h, AdjScratch S,
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __res
       }
     }
   }
-  block_partials<K>(vals, partials);
+  block_partials_add<K>(vals, partials);
 }
 
 // Masked molar sums N_s = sum_{mask} rbar_s / M_s of the post-streaming state

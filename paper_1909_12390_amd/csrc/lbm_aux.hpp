@@ -31,6 +31,26 @@ __device__ __forceinline__ void block_partials(double* vals, double* partials) {
   }
 }
 
+// as block_partials, but adds the block's sums to partials[block][k] (a running
+// per-block accumulator across launches on one stream; each block owns its row)
+template <int K>
+__device__ __forceinline__ void block_partials_add(double* vals, double* partials) {
+  __shared__ double red[kBlock / 64][K];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double s = wave_sum(vals[k]);
+    if (lane == 0) red[wv][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+    partials[(size_t)blockIdx.x * K + threadIdx.x] += s;
+  }
+}
+
 // rbar_s, u = (j + F_total/2)/rho, p_EOS and psi of every cell; per-block partial
 // sums of [mass_s (nc), momentum (D), force (D)] in a fixed order.
 template <int LAT, int NC, int ST>

@@ -12,96 +12,12 @@
 #include <vector>
 
 #include "lbm.h"
-#include "lbm_batch.hpp"
+#include "lbm_batch_dispatch.hpp"
 #include "lbm_internal.hpp"
 
 using namespace lbmk;
 
 namespace {
-
-struct BBufs {
-  void* p0;   // F64: f; offset formats: base
-  void* p1;   // offset formats: r
-};
-
-template <int ST>
-BatchPops<ST> bpops(const BBufs& b);
-template <>
-BatchPops<LBM_F64> bpops<LBM_F64>(const BBufs& b) {
-  BatchPops<LBM_F64> p;
-  p.f = (double*)b.p0;
-  return p;
-}
-template <>
-BatchPops<LBM_F32_OFS> bpops<LBM_F32_OFS>(const BBufs& b) {
-  BatchPops<LBM_F32_OFS> p;
-  p.base = (float*)b.p0;
-  p.r = (float*)b.p1;
-  return p;
-}
-template <>
-BatchPops<LBM_F16_OFS> bpops<LBM_F16_OFS>(const BBufs& b) {
-  BatchPops<LBM_F16_OFS> p;
-  p.base = (float*)b.p0;
-  p.r = (__half*)b.p1;
-  return p;
-}
-
-struct BOps {
-  void (*psi)(const BatchK&, int, const BBufs&, double*, hipStream_t);
-  void (*collide)(const BatchK&, int, const BBufs&, const BBufs&, const double*, hipStream_t);
-  void (*exp)(const BatchK&, int, const BBufs&, const unsigned long long*, double*, double*, hipStream_t);
-  void (*init)(const BatchK&, int, const BBufs&, const unsigned long long*, const double*, hipStream_t);
-  int (*occupancy)(int tile);
-};
-
-template <int LAT, int ST, int COLL, int FORC>
-struct BOpsImpl {
-  static void psi(const BatchK& K, int grid, const BBufs& in, double* psi, hipStream_t st) {
-    hipLaunchKernelGGL((kb_psi<LAT, ST>), dim3(grid), dim3(K.tile), 0, st, K, bpops<ST>(in), psi);
-  }
-  static void collide(const BatchK& K, int grid, const BBufs& in, const BBufs& out, const double* psi,
-                      hipStream_t st) {
-    hipLaunchKernelGGL((kb_collide<LAT, ST, COLL, FORC>), dim3(grid), dim3(K.tile), 0, st, K, bpops<ST>(in),
-                       bpops<ST>(out), psi);
-  }
-  static void exp(const BatchK& K, int grid, const BBufs& in, const unsigned long long* off, double* rho,
-                  double* f, hipStream_t st) {
-    hipLaunchKernelGGL((kb_export<LAT, ST>), dim3(grid), dim3(K.tile), 0, st, K, bpops<ST>(in), off, rho, f);
-  }
-  static void init(const BatchK& K, int grid, const BBufs& out, const unsigned long long* off, const double* rho0,
-                   hipStream_t st) {
-    hipLaunchKernelGGL((kb_init<LAT, ST>), dim3(grid), dim3(K.tile), 0, st, K, bpops<ST>(out), off, rho0);
-  }
-  static int occupancy(int tile) {
-    int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kb_collide<LAT, ST, COLL, FORC>, tile, 0) != hipSuccess)
-      a = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb_psi<LAT, ST>, tile, 0) != hipSuccess) b = 1;
-    return std::max(1, std::min(a, b));
-  }
-  static BOps ops() { return BOps{&psi, &collide, &exp, &init, &occupancy}; }
-};
-
-template <int LAT, int ST>
-BOps bops_cf(int coll, int forc) {
-  if (coll == LBM_BGK)
-    return forc == LBM_GUO ? BOpsImpl<LAT, ST, LBM_BGK, LBM_GUO>::ops() : BOpsImpl<LAT, ST, LBM_BGK, LBM_EDM>::ops();
-  return forc == LBM_GUO ? BOpsImpl<LAT, ST, LBM_MRT, LBM_GUO>::ops() : BOpsImpl<LAT, ST, LBM_MRT, LBM_EDM>::ops();
-}
-
-template <int LAT>
-BOps bops_st(int st, int coll, int forc) {
-  switch (st) {
-    case LBM_F64: return bops_cf<LAT, LBM_F64>(coll, forc);
-    case LBM_F32_OFS: return bops_cf<LAT, LBM_F32_OFS>(coll, forc);
-    default: return bops_cf<LAT, LBM_F16_OFS>(coll, forc);
-  }
-}
-
-BOps bops_for(int lat, int st, int coll, int forc) {
-  return lat == LBM_D2Q9 ? bops_st<LBM_D2Q9>(st, coll, forc) : bops_st<LBM_D3Q19>(st, coll, forc);
-}
 
 lbm_status hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) return lbm_fail(LBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
@@ -125,8 +41,7 @@ lbm_status batch_validate(const lbm_box* boxes, int nboxes, const lbm_batch_para
   if (prm->forcing != LBM_GUO && prm->forcing != LBM_EDM) return lbm_fail(LBM_ERR_ARG, "unknown forcing");
   if (prm->storage < LBM_F64 || prm->storage > LBM_F16_OFS) return lbm_fail(LBM_ERR_ARG, "unknown storage");
   const int t = prm->tile;
-  if (!(t == 0 || t == 64 || t == 128 || t == 256 || t == 512 || t == 1024))
-    return lbm_fail(LBM_ERR_ARG, "tile must be 0, 64, 128, 256, 512 or 1024");
+  if (!(t == 0 || t == 64 || t == 128 || t == 256)) return lbm_fail(LBM_ERR_ARG, "tile must be 0, 64, 128 or 256");
   if (prm->graph_steps < 0 || prm->grid < 0) return lbm_fail(LBM_ERR_ARG, "graph_steps and grid must be >= 0");
   const int Q = prm->lattice == LBM_D2Q9 ? 9 : 19;
   if (prm->collision == LBM_MRT)
@@ -194,7 +109,7 @@ void batch_layout(const lbm_box* boxes, int nboxes, const lbm_batch_params* prm,
 
 template <int LAT>
 void fill_mrt_b(const lbm_batch_params* prm, BatchK* K) {
-  for (int k = 0; k < VS<LAT>::Q; ++k) K->s_over_n[k] = prm->mrt_s[k] / mrow_norm2<LAT>(k);
+  for (int k = 0; k < VS<LAT>::Q; ++k) K->mrt_c[k] = (1.0 - prm->mrt_s[k]) / mrow_norm2<LAT>(k);
 }
 
 }  // namespace
@@ -204,7 +119,8 @@ struct lbm_batch {
   lbm_batch_params prm;
   BatchK K;
   BOps ops;
-  int grid;
+  int grid;           // persistent grid of the one-thread-per-cell kernels
+  int grid_collide;   // persistent grid of kb_collide
   hipStream_t stream;
   BBufs pops[2];
   double* psi;
@@ -220,7 +136,7 @@ void enqueue_batch_step(lbm_batch* b) {
   const BBufs& in = b->pops[b->cur];
   const BBufs& out = b->pops[1 - b->cur];
   b->ops.psi(b->K, b->grid, in, b->psi, b->stream);
-  b->ops.collide(b->K, b->grid, in, out, b->psi, b->stream);
+  b->ops.collide(b->K, b->grid_collide, in, out, b->psi, b->stream);
   b->cur = 1 - b->cur;
 }
 }  // namespace
@@ -320,22 +236,28 @@ extern "C" lbm_status lbm_batch_init(const lbm_box* boxes, int nboxes, const lbm
   const int D = prm->lattice == LBM_D2Q9 ? 2 : 3;
   for (int d = 0; d < 3; ++d) b->K.accel[d] = d < D ? prm->accel[d] : 0.0;
   b->K.err = b->err;
-  b->ops = bops_for(prm->lattice, prm->storage, prm->collision, prm->forcing);
+  int ncmax = 1;
+  for (int i = 0; i < nboxes; ++i) ncmax = std::max(ncmax, boxes[i].mix.nc);
+  b->ops = prm->lattice == LBM_D2Q9 ? bops_d2q9(prm->storage, prm->collision, prm->forcing, ncmax)
+                                    : bops_d3q19(prm->storage, prm->collision, prm->forcing, ncmax);
 
-  // persistent grid: resident workgroups (or the caller's choice), a multiple of the XCD count
-  int grid = prm->grid;
-  if (grid <= 0) {
-    int dev = 0, cus = 0;
+  // persistent grids: resident workgroups (or the caller's choice), a multiple of the XCD count
+  int grids[2] = {prm->grid, prm->grid};
+  if (prm->grid <= 0) {
+    int dev = 0, cus = 0, per_cu[2] = {1, 1};
     st = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (st == LBM_OK) st = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "cus");
     if (st != LBM_OK) {
       delete b;
       return st;
     }
-    grid = cus * b->ops.occupancy(tile);
+    b->ops.occupancy(tile, per_cu);
+    grids[0] = cus * per_cu[0];
+    grids[1] = cus * per_cu[1];
   }
-  grid = std::min<int>(grid, (int)L.ntiles);
-  b->grid = (int)xcd_grid((unsigned)std::max(grid, 1));
+  for (int k = 0; k < 2; ++k) grids[k] = (int)xcd_grid((unsigned)std::max(1, std::min<int>(grids[k], (int)L.ntiles)));
+  b->grid = grids[0];
+  b->grid_collide = grids[1];
 
   st = hip_check(hipMemcpyAsync((void*)b->K.boxes, hb.data(), hb.size() * sizeof(BoxK), hipMemcpyHostToDevice,
                                 b->stream), "upload boxes");

@@ -30,13 +30,16 @@ struct BoxK {
   double b[LBM_MAX_NC], invM[LBM_MAX_NC], gamma[LBM_MAX_NC];
 };
 
+// Scalars of a batch; the box table and the work list (box of each tile) are
+// passed to the kernels as separate restrict pointers, so that their loads,
+// uniform per tile, go through the scalar cache.
 struct BatchK {
   const BoxK* boxes;
-  const int* tile_box;              // work list: box of each tile
+  const int* tile_box;
   unsigned ntiles;
   int tile;                         // cells per tile (= workgroup size)
   int collision, forcing;
-  double s_over_n[LBM_MAX_Q];
+  double mrt_c[LBM_MAX_Q];
   double accel[3];
   int* err;                         // [0]: any box; [1 + b]: box b
 };
@@ -124,13 +127,14 @@ __device__ __forceinline__ double box_psi(const BatchK& K, const BoxK& B, int bo
 
 // pass 1 over every tile: densities -> EOS -> psi
 template <int LAT, int ST>
-__global__ __launch_bounds__(1024) void kb_psi(BatchK K, BatchPops<ST> in, double* __restrict__ psi) {
+__global__ __launch_bounds__(1024) void kb_psi(BatchK K, const BoxK* __restrict__ boxes, const int* __restrict__ tile_box,
+                                              BatchPops<ST> in, double* __restrict__ psi) {
   using V = VS<LAT>;
   using R = typename BatchPops<ST>::R;
   const TileRange tr = tile_range(K.ntiles);
   for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
-    const int bx = K.tile_box[t];
-    const BoxK& B = K.boxes[bx];
+    const int bx = __builtin_amdgcn_readfirstlane(tile_box[t]);
+    const BoxK& B = boxes[bx];
     const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
     if (cell >= B.cells) continue;
     const Coord c = box_coord(cell, B);
@@ -151,86 +155,112 @@ __global__ __launch_bounds__(1024) void kb_psi(BatchK K, BatchPops<ST> in, doubl
   }
 }
 
-// pass 2 over every tile: one thread per cell, components in a rolled loop
-template <int LAT, int ST, int COLL, int FORC>
-__global__ __launch_bounds__(1024) void kb_collide(BatchK K, BatchPops<ST> in, BatchPops<ST> out,
-                                                  const double* __restrict__ psi) {
+// pass 2 over every tile.  A workgroup is NCMAX groups of `tile` threads (the
+// largest component count of the batch); group s owns component s of the tile's
+// cells, as in the single-box k_collide: it pulls and decodes that component,
+// adds a share of the psi stencil (directions a with (a - 1) mod NCMAX = s, also
+// in groups with s >= nc of a box with fewer components), and the groups combine
+// densities, momenta and force through LDS in a fixed order before each collides
+// its own component.  Dynamic LDS: NCMAX x 7 x tile doubles.
+template <int LAT, int NCMAX, int ST, int COLL, int FORC>
+__global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restrict__ boxes,
+                                                  const int* __restrict__ tile_box, BatchPops<ST> in,
+                                                  BatchPops<ST> out, const double* __restrict__ psi) {
   using V = VS<LAT>;
   using R = typename BatchPops<ST>::R;
   constexpr int Q = V::Q;
+  extern __shared__ double kb_red[];   // [NCMAX][7][tile]
+  const int tile = K.tile;
+  // uniform per wavefront (tile is a multiple of 64)
+  const int s = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / (unsigned)tile));
+  const int lane = (int)threadIdx.x - s * tile;
+  KParams P;
+  P.mrt_c[0] = 0.0;
+#pragma unroll
+  for (int k = 0; k < LBM_MAX_Q; ++k) P.mrt_c[k] = K.mrt_c[k];
   const TileRange tr = tile_range(K.ntiles);
   for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
-    const int bx = K.tile_box[t];
-    const BoxK& B = K.boxes[bx];
-    const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
-    if (cell >= B.cells) continue;
-    const Coord c = box_coord(cell, B);
-    double rho = 0.0, Gam = 0.0;
+    const int bx = __builtin_amdgcn_readfirstlane(tile_box[t]);
+    const BoxK& B = boxes[bx];
+    const int nc = B.nc;
+    const unsigned cell = (t - B.first_tile) * (unsigned)tile + (unsigned)lane;
+    const bool in_box = cell < B.cells;
+    const bool active = in_box && s < nc;
+    const Coord c = box_coord(in_box ? cell : 0u, B);
+    R f[Q];
     R jx = 0, jy = 0, jz = 0;
-#pragma unroll 1
-    for (int s = 0; s < B.nc; ++s) {
+    double mass = 0.0;   // summed exactly for the offset formats' base (put_all)
+    double Fp[3] = {0.0, 0.0, 0.0};
+    if (active) {
       const auto cv = in.comp(B, s, Q);
-      R acc = 0;
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
-        const R v = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
-        acc += v;
-        if (V::cx(a)) jx += (R)V::cx(a) * v;
-        if (V::cy(a)) jy += (R)V::cy(a) * v;
-        if (V::cz(a)) jz += (R)V::cz(a) * v;
+        f[a] = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+        mass += (double)f[a];
+        if (V::cx(a)) jx += (R)V::cx(a) * f[a];
+        if (V::cy(a)) jy += (R)V::cy(a) * f[a];
+        if (V::cz(a)) jz += (R)V::cz(a) * f[a];
       }
-      rho += (double)acc;
-      Gam += B.gamma[s] * (double)acc;
     }
-    if (!(Gam > 0.0)) batch_flag(K, bx);
-    const double* ps = psi + B.psi_off;
-    double F[3] = {0.0, 0.0, 0.0};
-    {
+    if (in_box) {
+      const double* ps = psi + B.psi_off;
       const double p0 = ps[cell];
       const double hb = 0.5 * (1.0 - B.beta);
       static_for<1, Q>([&](auto A) {
         constexpr int a = decltype(A)::value;
-        const double pn = ps[c.at(V::cx(a), V::cy(a), V::cz(a))];
-        const double tt = V::w(a) * pn * (B.beta * p0 + hb * pn);
-        if constexpr (V::cx(a) != 0) F[0] += V::cx(a) * tt;
-        if constexpr (V::cy(a) != 0) F[1] += V::cy(a) * tt;
-        if constexpr (V::cz(a) != 0) F[2] += V::cz(a) * tt;
+        if ((a - 1) % NCMAX == s) {
+          const double pn = ps[c.at(V::cx(a), V::cy(a), V::cz(a))];
+          const double tt = V::w(a) * pn * (B.beta * p0 + hb * pn);
+          if constexpr (V::cx(a) != 0) Fp[0] += V::cx(a) * tt;
+          if constexpr (V::cy(a) != 0) Fp[1] += V::cy(a) * tt;
+          if constexpr (V::cz(a) != 0) Fp[2] += V::cz(a) * tt;
+        }
       });
+    }
+    double* red = kb_red + (size_t)s * 7 * tile;
+    red[0 * tile + lane] = mass;
+    red[1 * tile + lane] = (double)jx;
+    red[2 * tile + lane] = (double)jy;
+    red[3 * tile + lane] = (double)jz;
+    red[4 * tile + lane] = Fp[0];
+    red[5 * tile + lane] = Fp[1];
+    red[6 * tile + lane] = Fp[2];
+    __syncthreads();
+    if (active) {
+      double rho = 0.0, Gam = 0.0, j[3] = {0.0, 0.0, 0.0}, F[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < NCMAX; ++q) {
+        const double* rq = kb_red + (size_t)q * 7 * tile;
+        if (q < nc) {
+          const double r = rq[lane];
+          rho += r;
+          Gam += B.gamma[q] * r;
+          j[0] += rq[1 * tile + lane];
+          j[1] += rq[2 * tile + lane];
+          j[2] += rq[3 * tile + lane];
+        }
+        F[0] += rq[4 * tile + lane];
+        F[1] += rq[5 * tile + lane];
+        F[2] += rq[6 * tile + lane];
+      }
       F[0] *= -B.G;
       F[1] *= -B.G;
       F[2] *= -B.G;
-    }
-    const R g0 = (R)K.accel[0], g1 = (R)K.accel[1], g2 = (R)K.accel[2];
-    const R rhoR = (R)rho, irho = (R)1 / rhoR;
-    const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
-    R u[3];
-    if (FORC == LBM_GUO) {
-      u[0] = (jx + (R)0.5 * (FR[0] + rhoR * g0)) * irho;
-      u[1] = (jy + (R)0.5 * (FR[1] + rhoR * g1)) * irho;
-      u[2] = (jz + (R)0.5 * (FR[2] + rhoR * g2)) * irho;
-    } else {
-      u[0] = jx * irho;
-      u[1] = jy * irho;
-      u[2] = jz * irho;
-    }
-    // collision parameters of this box
-    KParams P;
-    P.cells = (int)B.cells;
-    P.omega = B.omega;
-#pragma unroll
-    for (int k = 0; k < LBM_MAX_Q; ++k) P.s_over_n[k] = K.s_over_n[k];
-#pragma unroll 1
-    for (int s = 0; s < B.nc; ++s) {
-      const auto cv = in.comp(B, s, Q);
-      R f[Q];
-      R rs = 0;
-      double mass = 0.0;   // summed exactly for the offset formats' base (put_all)
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        f[a] = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
-        rs += f[a];
-        mass += (double)f[a];
+      if (!(Gam > 0.0)) batch_flag(K, bx);
+      const R g0 = (R)K.accel[0], g1 = (R)K.accel[1], g2 = (R)K.accel[2];
+      const R rhoR = (R)rho, irho = (R)1 / rhoR;
+      const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
+      R u[3];
+      if (FORC == LBM_GUO) {
+        u[0] = ((R)j[0] + (R)0.5 * (FR[0] + rhoR * g0)) * irho;
+        u[1] = ((R)j[1] + (R)0.5 * (FR[1] + rhoR * g1)) * irho;
+        u[2] = ((R)j[2] + (R)0.5 * (FR[2] + rhoR * g2)) * irho;
+      } else {
+        u[0] = (R)j[0] * irho;
+        u[1] = (R)j[1] * irho;
+        u[2] = (R)j[2] * irho;
       }
+      const R rs = (R)mass;
       const R ch = (R)B.gamma[s] / (R)Gam;
       R fs[3];
       if (FORC == LBM_GUO) {
@@ -242,24 +272,29 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, BatchPops<ST> in, B
         fs[1] = ch * FR[1] + g1;
         fs[2] = ch * FR[2] + g2;
       }
+      P.cells = (int)B.cells;
+      P.omega = B.omega;
       collide_values<LAT, R, COLL, FORC>(P, f, rs, u, fs, [&](const R* fo) {
         out.comp(B, s, Q).template put_all<Q>(cell, fo, mass, [](int a) { return (R)V::w(a); });
       });
     }
+    __syncthreads();   // the LDS rows are reused by the next tile
   }
 }
 
 // rbar_s of every cell of every box (concatenated [box][nc_b][cells_b]) and the
 // state in the canonical float64 layout [box][nc_b][Q][cells_b] (either may be null)
 template <int LAT, int ST>
-__global__ __launch_bounds__(1024) void kb_export(BatchK K, BatchPops<ST> in, const unsigned long long* fld_off,
+__global__ __launch_bounds__(1024) void kb_export(BatchK K, const BoxK* __restrict__ boxes,
+                                                 const int* __restrict__ tile_box, BatchPops<ST> in,
+                                                 const unsigned long long* __restrict__ fld_off,
                                                  double* __restrict__ rho_out, double* __restrict__ f_out) {
   using V = VS<LAT>;
   using R = typename BatchPops<ST>::R;
   const TileRange tr = tile_range(K.ntiles);
   for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
-    const int bx = K.tile_box[t];
-    const BoxK& B = K.boxes[bx];
+    const int bx = __builtin_amdgcn_readfirstlane(tile_box[t]);
+    const BoxK& B = boxes[bx];
     const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
     if (cell >= B.cells) continue;
     const Coord c = box_coord(cell, B);
@@ -280,15 +315,17 @@ __global__ __launch_bounds__(1024) void kb_export(BatchK K, BatchPops<ST> in, co
 
 // equilibrium initialisation from rho0 (concatenated [box][nc_b][cells_b]) at rest
 template <int LAT, int ST>
-__global__ __launch_bounds__(1024) void kb_init(BatchK K, BatchPops<ST> out, const unsigned long long* fld_off,
+__global__ __launch_bounds__(1024) void kb_init(BatchK K, const BoxK* __restrict__ boxes,
+                                               const int* __restrict__ tile_box, BatchPops<ST> out,
+                                               const unsigned long long* __restrict__ fld_off,
                                                const double* __restrict__ rho0) {
   using V = VS<LAT>;
   using R = typename BatchPops<ST>::R;
   constexpr int Q = V::Q;
   const TileRange tr = tile_range(K.ntiles);
   for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
-    const int bx = K.tile_box[t];
-    const BoxK& B = K.boxes[bx];
+    const int bx = __builtin_amdgcn_readfirstlane(tile_box[t]);
+    const BoxK& B = boxes[bx];
     const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
     if (cell >= B.cells) continue;
     const Coord c = box_coord(cell, B);

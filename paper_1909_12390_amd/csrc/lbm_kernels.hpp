@@ -24,7 +24,7 @@ struct KParams {
   double b[LBM_MAX_NC];
   double invM[LBM_MAX_NC];
   double gamma[LBM_MAX_NC];
-  double s_over_n[LBM_MAX_Q];      // MRT rate / squared norm of each moment row
+  double mrt_c[LBM_MAX_Q];         // MRT: (1 - rate) / squared norm of each moment row
   double accel[3];
   int* err;                        // device error flag (set to 1 on a domain violation)
 };
@@ -361,15 +361,20 @@ __device__ __forceinline__ void cell_forces(const KParams& P, const double* rb, 
 //   f   : populations of component s at this cell (time t, post-streaming)
 //   rs  : rbar_s;  u: shared velocity;  Fs: F_s (Guo) or du_s (EDM)
 // BGK : f* = f - omega (f - feq) + (1 - omega/2) S_guo        | + [feq(u + du) - feq(u)]
-// MRT : f* = f + src - M^T diag(s_k/|M_k|^2) M (f - feq + h src),  h = 1/2 (Guo), 0 (EDM)
+// MRT : f* = f + src - M^-1 S M (f - feq + h src), h = 1/2 (Guo), 0 (EDM), which
+//       with d = f - feq + h src is the same as
+//       f* = feq + (1 - h) src + M^-1 (I - S) M d
+//       (M^-1 = M^T diag(1/|M_k|^2) for the orthogonal basis).  Rows relaxed at
+//       rate 1 drop out of the second form, so only the rows with rate != 1 are
+//       transformed (a uniform branch per row; the density row always drops out
+//       because sum_a d_a = 0).
 // Everything is evaluated on opposite pairs (a, opp(a)): the equilibrium and the
 // sources split into a part even under e -> -e and an odd part,
 //   feq_a = E + O, feq_opp = E - O,  E = w rs (1 + 9/2 (e.u)^2 - 3/2 u.u), O = 3 w rs e.u,
 //   Guo : w[3(e - u).F + 9 (e.u)(e.F)]  -> even w(9 (e.u)(e.F) - 3 u.F), odd 3 w e.F,
 //   EDM : feq(u + du) - feq(u) = w rs [3 e.du + 9/2 (e.du)(2 e.u + e.du) - 3/2 du.(2u + du)]
 //         -> even w rs (9/2 (e.du)(2 e.u + e.du) - 3/2 du.(2u + du)), odd 3 w rs e.du;
-// MRT even rows act on f_a + f_opp, odd rows on f_a - f_opp; the density row is
-// skipped because sum_a (f - feq + h src) = 0.
+// MRT even rows act on d_a + d_opp, odd rows on d_a - d_opp.
 template <int LAT, typename R, int COLL, int FORC, typename Sink>
 __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R rs, const R* u3, const R* F3,
                                                Sink sink) {
@@ -419,14 +424,15 @@ __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R r
     });
   } else {
     const R h = (FORC == LBM_GUO) ? (R)0.5 : (R)0;
-    R d0;
+    const R g1 = (R)1 - h;
+    R d0, acc0 = 0;
+    R S[NP], D[NP], accE[NP], accO[NP];
     {
       R Ev, Od, sE, sO;
       parts(std::integral_constant<int, 0>{}, Ev, Od, sE, sO);
       d0 = f[0] - Ev + h * sE;
-      fo[0] = f[0] + sE;
+      fo[0] = Ev + g1 * sE;
     }
-    R S[NP], D[NP];
     static_for<0, NP>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value;
       constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
@@ -434,51 +440,50 @@ __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R r
       parts(std::integral_constant<int, a>{}, Ev, Od, sE, sO);
       S[p] = (f[a] + f[b]) - (R)2 * Ev + (R)2 * h * sE;   // d_a + d_b
       D[p] = (f[a] - f[b]) - (R)2 * Od + (R)2 * h * sO;   // d_a - d_b
-      fo[a] = f[a] + (sE + sO);
-      fo[b] = f[b] + (sE - sO);
+      fo[a] = (Ev + g1 * sE) + (Od + g1 * sO);            // feq + (1 - h) src
+      fo[b] = (Ev + g1 * sE) - (Od + g1 * sO);
+      accE[p] = 0;
+      accO[p] = 0;
     });
-    R m[Q];
     static_for<1, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      R acc = 0;
-      if constexpr (!row_odd<LAT>(k)) {
-        if constexpr (V::mrow(k, 0) != 0.0) acc += (R)V::mrow(k, 0) * d0;
+      const double ck = P.mrt_c[k];
+      // skip rows relaxed at rate 1 (a uniform branch); in float64 the kernel
+      // streams at HBM speed and the branches cost more than the skipped rows
+      if (std::is_same<R, double>::value || ck != 0.0) {
+        R m = 0;
+        if constexpr (!row_odd<LAT>(k)) {
+          if constexpr (V::mrow(k, 0) != 0.0) m += (R)V::mrow(k, 0) * d0;
+          static_for<0, NP>([&](auto Pp) {
+            constexpr int p = decltype(Pp)::value;
+            constexpr double mk = V::mrow(k, V::pair_first(p));
+            if constexpr (mk != 0.0) m += (R)mk * S[p];
+          });
+        } else {
+          static_for<0, NP>([&](auto Pp) {
+            constexpr int p = decltype(Pp)::value;
+            constexpr double mk = V::mrow(k, V::pair_first(p));
+            if constexpr (mk != 0.0) m += (R)mk * D[p];
+          });
+        }
+        m *= (R)ck;
+        if constexpr (!row_odd<LAT>(k) && V::mrow(k, 0) != 0.0) acc0 += (R)V::mrow(k, 0) * m;
         static_for<0, NP>([&](auto Pp) {
           constexpr int p = decltype(Pp)::value;
           constexpr double mk = V::mrow(k, V::pair_first(p));
-          if constexpr (mk != 0.0) acc += (R)mk * S[p];
-        });
-      } else {
-        static_for<0, NP>([&](auto Pp) {
-          constexpr int p = decltype(Pp)::value;
-          constexpr double mk = V::mrow(k, V::pair_first(p));
-          if constexpr (mk != 0.0) acc += (R)mk * D[p];
+          if constexpr (mk != 0.0) {
+            if constexpr (row_odd<LAT>(k)) accO[p] += (R)mk * m;
+            else accE[p] += (R)mk * m;
+          }
         });
       }
-      m[k] = acc * (R)P.s_over_n[k];
     });
-    {
-      R acc = 0;
-      static_for<1, Q>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        if constexpr (!row_odd<LAT>(k) && V::mrow(k, 0) != 0.0) acc += (R)V::mrow(k, 0) * m[k];
-      });
-      fo[0] -= acc;
-    }
+    fo[0] += acc0;
     static_for<0, NP>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value;
       constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
-      R E = 0, O = 0;
-      static_for<1, Q>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        constexpr double mk = V::mrow(k, a);
-        if constexpr (mk != 0.0) {
-          if constexpr (row_odd<LAT>(k)) O += (R)mk * m[k];
-          else E += (R)mk * m[k];
-        }
-      });
-      fo[a] -= E + O;
-      fo[b] -= E - O;
+      fo[a] += accE[p] + accO[p];
+      fo[b] += accE[p] - accO[p];
     });
   }
   sink(fo);
@@ -563,12 +568,12 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       f[a] = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
-      rs += f[a];
       mass += (double)f[a];
       if (V::cx(a)) jx += (R)V::cx(a) * f[a];
       if (V::cy(a)) jy += (R)V::cy(a) * f[a];
       if (V::cz(a)) jz += (R)V::cz(a) * f[a];
     }
+    rs = (R)mass;
     // partial stencil of Eq. (coupledMCforce) over this wavefront's directions
     const double ps = ldb(psi, cell * 8u);
     const double hb = 0.5 * (1.0 - P.beta);

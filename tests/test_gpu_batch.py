@@ -75,8 +75,8 @@ def test_each_box_matches_oracle(collision, forcing):
 def test_tiles_grid_and_graph_are_bitwise_identical():
     print("case batch tiles/grid/graph", flush=True)
     boxes = make_boxes(9, 2)
-    runs = [dict(tile=64), dict(tile=256), dict(tile=1024), dict(tile=128, grid=8),
-            dict(tile=256, graph_steps=4), dict(tile=512, graph_steps=3)]
+    runs = [dict(tile=64), dict(tile=256), dict(tile=128), dict(tile=128, grid=8),
+            dict(tile=256, graph_steps=4), dict(tile=64, graph_steps=3, grid=16)]
     out = []
     for kw in runs:
         b = batch(boxes, collision="bgk", forcing="edm", storage="f16", **kw)
