@@ -309,8 +309,8 @@ def main():
         cpu_baseline_worker(args.cpu_side, args.cpu_steps)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
-              f"described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the multi-GPU sharding "
+              f"(boxes across GPUs, z-slabs with halo exchange) is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
