@@ -144,9 +144,12 @@ __global__ __launch_bounds__(1024) void kb_psi(BatchK K, const BoxK* __restrict_
 #pragma unroll 1
     for (int s = 0; s < B.nc; ++s) {
       const auto cv = in.comp(B, s, V::Q);
+      R v[V::Q];
+      cv.template get_all<V::Q>([&](int a) { return c.at(-V::cx(a), -V::cy(a), -V::cz(a)); }, v,
+                                [](int a) { return (R)V::w(a); });
       R acc = 0;
 #pragma unroll
-      for (int a = 0; a < V::Q; ++a) acc += cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+      for (int a = 0; a < V::Q; ++a) acc += v[a];
 #pragma unroll
       for (int u = 0; u < LBM_MAX_NC; ++u)
         if (u == s) rb[u] = (double)acc;

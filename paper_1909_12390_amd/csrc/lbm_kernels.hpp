@@ -89,6 +89,12 @@ struct Pops<LBM_F64> {
     __device__ __forceinline__ double get(int a, unsigned idx, double) const {
       return bload(rf, idx * 8u, (unsigned)a * plane, 0.0);
     }
+    // all Q directions, direction a from cell src(a): loads first, then decode
+    template <int Q, typename Src, typename W>
+    __device__ __forceinline__ void get_all(Src src, double* out, W) const {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) out[a] = bload(rf, src(a) * 8u, (unsigned)a * plane, 0.0);
+    }
     template <int Q, typename W>
     __device__ __forceinline__ void put_all(unsigned idx, const double* v, double, W) const {
 #pragma unroll
@@ -111,6 +117,21 @@ struct OffsetPops {
     unsigned plane;   // bytes per direction plane of r
     __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
       return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
+    }
+    // all Q directions, direction a from cell src(a): every load is issued before
+    // the first decode, so the wavefront keeps 2Q loads in flight
+    template <int Q, typename Src, typename W>
+    __device__ __forceinline__ void get_all(Src src, float* out, W w) const {
+      float bq[Q], rq[Q];   // rq: offsets already widened to float32
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const unsigned idx = src(a);
+        bq[a] = bload(rb, idx * 4u, 0u, 0.0f);
+        rq[a] = bload(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H());
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the decode
+#pragma unroll
+      for (int a = 0; a < Q; ++a) out[a] = bq[a] * (w(a) + rq[a]);
     }
     // v: post-collision populations; mass: the cell's mass of this component
     // (sum of v, summed exactly in float64); w(a): weights.
@@ -521,9 +542,12 @@ __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* 
 #pragma unroll 1
   for (int s = 0; s < NC; ++s) {
     const auto cv = in.comp(s, V::Q, P.cells);
+    R v[V::Q];
+    cv.template get_all<V::Q>([&](int a) { return c.at(-V::cx(a), -V::cy(a), -V::cz(a)); }, v,
+                              [](int a) { return (R)V::w(a); });
     R acc = 0;
 #pragma unroll
-    for (int a = 0; a < V::Q; ++a) acc += cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+    for (int a = 0; a < V::Q; ++a) acc += v[a];
 #pragma unroll
     for (int t = 0; t < NC; ++t)
       if (t == s) rb[t] = (double)acc;
