@@ -84,6 +84,9 @@ def lib() -> ctypes.CDLL:
     """Load libpaper_lbm.so (raises if it is missing: there is no fallback)."""
     global _lib
     if _lib is None:
+        # torch first: the library and torch must share one HIP runtime in the
+        # process, and the first one loaded is the one both use
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise LbmError(LBM_ERR_UNSUPPORTED,
                            f"{LIB_PATH} is not built (python -m paper_1909_12390_amd.build)")

@@ -1,0 +1,61 @@
+"""Host side of the flat-interface validation (Sec. 4.2): lattice-unit scaling,
+slab position and initial profile (no device call)."""
+import numpy as np
+import pytest
+
+from golden_io import table1, table2
+from paper_1909_12390_amd import lbm, validation
+
+
+def test_table1_copy_matches_fixture():
+    t = table1()
+    for name, (pc, Tc, om, M) in validation.TABLE1.items():
+        assert (pc, Tc, om, M) == (t[name]["pc"], t[name]["Tc"], t[name]["omega"], t[name]["M"])
+
+
+def test_lattice_units_fix_component_one():
+    u = validation.LatticeUnits(validation.field_mixture())
+    m = u.mixture()
+    assert m["a"][0] == pytest.approx(2.0 / 49.0, rel=1e-15)
+    assert m["b"][0] == pytest.approx(2.0 / 21.0, rel=1e-15)
+    assert m["M"][0] == 1.0 and m["R"] == 1.0
+    # ratios to component 1 are unit-free
+    f = validation.field_mixture()
+    assert m["a"][1] / m["a"][0] == pytest.approx(f["a"][1] / f["a"][0], rel=1e-14)
+    assert m["b"][1] / m["b"][0] == pytest.approx(f["b"][1] / f["b"][0], rel=1e-14)
+
+
+def test_lattice_flash_reproduces_table2():
+    """The rescaled mixture flashed in lattice units at the rescaled pressures gives
+    Table 2's compositions, gamma_1 and (rescaled) densities."""
+    case = validation.flat_case(240.0, nx=64)
+    u, mix, T = case["units"], case["mix"], case["T"]
+    for r in table2():
+        if not np.isfinite(r["gamma1"]):
+            continue
+        fl = lbm.lbm_flash(mix, T, u.p(r["p"]), np.array([0.4, 0.6]))
+        assert fl.x[0] == pytest.approx(r["x1"], abs=2e-4)
+        assert fl.y[0] == pytest.approx(r["y1"], abs=2e-4)
+        assert fl.gamma[0] == pytest.approx(r["gamma1"], abs=5e-5)
+        printed = np.array([r["r1l"], r["r2l"], r["r1v"], r["r2v"]])
+        ours = np.array([fl.rbar_l[0], fl.rbar_l[1], fl.rbar_v[0], fl.rbar_v[1]])
+        assert np.allclose(ours, u.mass_density(printed), rtol=1.5e-3)
+
+
+def test_slab_start_gives_overall_composition_for_sharp_profile():
+    l, v = np.array([1.398, 5.3997]), np.array([0.2159, 0.1948])
+    M = np.array([1.0, 1.636])
+    z1, L = 0.4, 1600.0
+    L0 = validation.slab_start(l, v, z1, M[0] / M[1], L)
+    N = ((L - 2 * L0) * l + 2 * L0 * v) / M
+    assert N[0] / N.sum() == pytest.approx(z1, abs=1e-12)
+    assert 0.0 < L0 < L / 2
+
+
+def test_flat_profile_limits_and_symmetry():
+    l, v = np.array([2.0, 5.0]), np.array([0.3, 0.2])
+    prof = validation.flat_profile(400, 2, 120.0, 8.0, l, v)
+    assert prof.shape == (2, 2, 400)
+    assert np.allclose(prof[:, :, 200], l[:, None], atol=1e-12)
+    assert np.allclose(prof[:, :, 0], v[:, None], atol=1e-12)
+    assert np.allclose(prof[:, 0, 1:], prof[:, 0, 1:][:, ::-1], atol=1e-12)
