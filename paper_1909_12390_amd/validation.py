@@ -209,6 +209,94 @@ def calibrate_beta(p_list=(200.0, 240.0), forcing="edm", collision="bgk", betas=
             "best_beta": best, "best_err": score[best], "reports": reps}
 
 
+# ---------------------------------------------------------------------------
+# Laplace's law for a drop (Sec. 4.3)
+# ---------------------------------------------------------------------------
+
+def drop_case(p_psia, n, beta=1.915, tau=0.8, W=4.0, z1=0.4, names=("C3", "nC5")):
+    """A drop of initial radius R0 = n/5 at the centre of an n x n periodic box,
+    Eq. (initialdensity_droplet) with the liquid inside (the sign of
+    Eq. (initialden)), phase densities from the flash at p_psia."""
+    fmix = field_mixture(names)
+    u = LatticeUnits(fmix)
+    mix = u.mixture()
+    T = u.T(TABLE1[names[0]][1])
+    fl = lbm.lbm_flash(mix, T, u.p(p_psia), np.array([z1, 1.0 - z1]))
+    y, x = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64), indexing="ij")
+    r = np.sqrt((x - n / 2.0) ** 2 + (y - n / 2.0) ** 2)
+    t = np.tanh(2.0 * (r - n / 5.0) / W)
+    l = np.asarray(fl.rbar_l)[:, None, None]
+    v = np.asarray(fl.rbar_v)[:, None, None]
+    rho0 = 0.5 * (l + v) - 0.5 * (l - v) * t[None]
+    return {"mix": mix, "shape": (n, n), "T": T, "tau": tau, "beta": beta, "gamma": np.asarray(fl.gamma),
+            "rho0": rho0, "p_psia": p_psia, "flash": fl, "units": u, "n": n}
+
+
+def drop_measure(rho_s, mix, T):
+    """Radius at the level 0.5 (rho_l + rho_v) of the total density along the four
+    axis rays from the centre (linear interpolation, averaged), and the pressures
+    p_EOS at the centre and at the box corner."""
+    r = np.asarray(rho_s)
+    rho = r.sum(axis=0)
+    n = rho.shape[0]
+    c = n // 2
+    rl, rv = rho[c, c], rho[0, 0]
+    level = 0.5 * (rl + rv)
+    radii = []
+    for prof in (rho[c, c:], rho[c, c::-1], rho[c:, c], rho[c::-1, c]):
+        k = int(np.argmax(prof < level))
+        a, b = prof[k - 1], prof[k]
+        radii.append(k - 1 + (a - level) / (a - b))
+    M = np.asarray(mix["M"], dtype=np.float64)
+    n_l, n_v = r[:, c, c] / M, r[:, 0, 0] / M
+    p = lbm.lbm_pressure(mix, T, np.stack([n_l, n_v]))
+    return {"R": float(np.mean(radii)), "p_l": float(p[0]), "p_v": float(p[1]), "dp": float(p[0] - p[1]),
+            "x": (n_l / n_l.sum()).tolist(), "y": (n_v / n_v.sum()).tolist()}
+
+
+def run_laplace(p_list=(200.0, 240.0), sizes=(50, 100, 200, 400, 800), beta=1.915, forcing="guo",
+                collision="bgk", max_steps=400_000, check_every=20_000, tol=1e-8, progress=None):
+    """All (pressure, size) drops as one batch to steady state; per pressure the
+    surface tension is the least-squares slope of dp against 1/R (with intercept)."""
+    cases = [drop_case(p, n, beta=beta) for p in p_list for n in sizes]
+    boxes = [{"mix": c["mix"], "shape": c["shape"], "T": c["T"], "tau": c["tau"], "beta": c["beta"],
+              "gamma": c["gamma"], "rho0": c["rho0"]} for c in cases]
+    b = lbm.LbmBatch(boxes, "D2Q9", collision=collision, forcing=forcing, storage="f64",
+                     graph_steps=min(1000, check_every))
+    steps, prev, change = 0, None, float("inf")
+    try:
+        while steps < max_steps:
+            b.step(check_every)
+            steps += check_every
+            bad = b.box_errors()
+            if bad.any():
+                raise lbm.LbmError(lbm.LBM_ERR_DOMAIN, f"boxes {np.nonzero(bad)[0].tolist()} left the EOS domain")
+            meas = [drop_measure(r.cpu().numpy(), c["mix"], c["T"]) for r, c in zip(b.fields(), cases)]
+            cur = np.array([[m["R"], m["dp"]] for m in meas])
+            if prev is not None:
+                change = float(np.max(np.abs(cur - prev) / np.abs(prev)))
+            if progress is not None:
+                progress(steps, change)
+            if change < tol:
+                break
+            prev = cur
+        b.check()
+    finally:
+        b.close()
+    out = {"steps": steps, "last_change": change, "beta": beta, "forcing": forcing, "pressures": {}}
+    for p in p_list:
+        rows = [(c["n"], m) for c, m in zip(cases, meas) if c["p_psia"] == p]
+        invR = np.array([1.0 / m["R"] for _, m in rows])
+        dp = np.array([m["dp"] for _, m in rows])
+        A = np.stack([invR, np.ones_like(invR)], axis=1)
+        (sigma, icpt), *_ = np.linalg.lstsq(A, dp, rcond=None)
+        fit = A @ np.array([sigma, icpt])
+        r2 = 1.0 - float(np.sum((dp - fit) ** 2) / np.sum((dp - dp.mean()) ** 2)) if len(dp) > 2 else 1.0
+        out["pressures"][str(p)] = {"sigma": float(sigma), "intercept": float(icpt), "r2": r2,
+                                    "drops": [{"n": n, **m} for n, m in rows]}
+    return out
+
+
 def main():
     import argparse
     import json
@@ -223,6 +311,8 @@ def main():
     ap.add_argument("--check-every", type=int, default=50_000)
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--calibrate", action="store_true", help="sweep beta instead")
+    ap.add_argument("--laplace", action="store_true", help="Laplace's law on drops instead (Sec. 4.3)")
+    ap.add_argument("--sizes", default="50,100,200,400,800")
     ap.add_argument("--betas", default="", help="comma list for --calibrate (default 1.0..2.0 step 0.1)")
     args = ap.parse_args()
     ps = [float(p) for p in args.pressures.split(",")]
@@ -232,7 +322,10 @@ def main():
         print(f"steps {steps} max relative change of the bulk densities {change:.3e}", file=sys.stderr, flush=True)
 
     kw = dict(max_steps=args.max_steps, check_every=args.check_every, tol=args.tol, progress=progress)
-    if args.calibrate:
+    if args.laplace:
+        out = run_laplace(ps, sizes=[int(n) for n in args.sizes.split(",")], beta=args.beta, forcing=args.forcing,
+                          collision=args.collision, **kw)
+    elif args.calibrate:
         betas = [float(b) for b in args.betas.split(",")] if args.betas else None
         out = calibrate_beta(ps, forcing=args.forcing, collision=args.collision, nx=args.nx, betas=betas, **kw)
     else:

@@ -24,3 +24,19 @@ def test_flat_interface_matches_flash():
         assert abs(r["p_l"] - r["p_v"]) < 1e-6 * r["p_l"]
         assert r["y"][0] > r["x"][0]
         assert r["p_lb_psia"] == pytest.approx(r["p_psia"], rel=0.02)
+
+
+def test_laplace_law_on_drops():
+    """Sec. 4.3: drops of initial radius n/5 in n x n boxes (n = 50, 100, 200),
+    200 psia, Guo forcing, beta = 1.915: dp = p_l - p_v is linear in 1/R and its
+    slope is the paper's surface tension 0.1289 (lattice units) within 10 %."""
+    from paper_1909_12390_amd import validation as V
+    print("case Laplace drops 50/100/200, 200 psia", flush=True)
+    out = V.run_laplace(p_list=(200.0,), sizes=(50, 100, 200), beta=1.915, max_steps=400_000,
+                        check_every=50_000, tol=1e-6)
+    r = out["pressures"]["200.0"]
+    print(f"  sigma {r['sigma']:.4f} (paper 0.1289), r2 {r['r2']:.5f}, steps {out['steps']}", flush=True)
+    assert r["r2"] > 0.999
+    assert r["sigma"] == pytest.approx(0.1289, rel=0.10)
+    for d in r["drops"]:
+        assert d["dp"] > 0.0 and d["y"][0] > d["x"][0]
