@@ -297,6 +297,106 @@ def run_laplace(p_list=(200.0, 240.0), sizes=(50, 100, 200, 400, 800), beta=1.91
     return out
 
 
+# ---------------------------------------------------------------------------
+# Oscillating elliptical drop (Sec. 4.3, Table 3)
+# ---------------------------------------------------------------------------
+
+def ellipse_case(n, p_psia=70.0, T_degR=580.0, beta=1.815, tau=0.8, W=4.0, h=0.9, z1=0.4, names=("C3", "nC5")):
+    """Elliptical drop, Eq. (ellipsedroplet) with the liquid inside: semi-axes R0
+    along x and R0 h along y, R0 = 0.15 n, in an n x n periodic box; phase
+    densities from the flash at (T_degR, p_psia)."""
+    fmix = field_mixture(names)
+    u = LatticeUnits(fmix)
+    mix = u.mixture()
+    T = u.T(T_degR)
+    fl = lbm.lbm_flash(mix, T, u.p(p_psia), np.array([z1, 1.0 - z1]))
+    R0 = 0.15 * n
+    y, x = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64), indexing="ij")
+    r = np.sqrt((x - n / 2.0) ** 2 + ((y - n / 2.0) / h) ** 2)
+    t = np.tanh(2.0 * (r - R0) / W)
+    l = np.asarray(fl.rbar_l)[:, None, None]
+    v = np.asarray(fl.rbar_v)[:, None, None]
+    rho0 = 0.5 * (l + v) - 0.5 * (l - v) * t[None]
+    return {"mix": mix, "shape": (n, n), "T": T, "tau": tau, "beta": beta, "gamma": np.asarray(fl.gamma),
+            "rho0": rho0, "n": n, "R0": R0, "h": h, "flash": fl, "units": u}
+
+
+def _axis_radius(line, level):
+    """Distance from the centre (index 0 of `line`) to where `line` drops below level."""
+    k = int(np.argmax(line < level))
+    a, b = line[k - 1], line[k]
+    return k - 1 + (a - level) / (a - b)
+
+
+def axes_of(rho_s):
+    """Semi-axes along x and y of a centred drop: where the total density crosses
+    the mean of its centre and corner values on the axis rays (averaged over the
+    two rays of each axis)."""
+    import torch
+    rho = rho_s.sum(dim=0)
+    n = rho.shape[0]
+    c = n // 2
+    m = n - c
+    rows = torch.stack([rho[c, c:], torch.flip(rho[c, c - m + 1:c + 1], [0]), rho[c:, c],
+                        torch.flip(rho[c - m + 1:c + 1, c], [0])]).cpu().numpy()
+    level = 0.5 * (float(rows[0, 0]) + float(rho[0, 0]))
+    rx = 0.5 * (_axis_radius(rows[0], level) + _axis_radius(rows[1], level))
+    ry = 0.5 * (_axis_radius(rows[2], level) + _axis_radius(rows[3], level))
+    return rx, ry
+
+
+def oscillation_period(t, d):
+    """Period from the zero crossings of d(t) = Rx - Ry (linear interpolation);
+    consecutive crossings are half a period apart."""
+    t = np.asarray(t, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    z = []
+    for k in range(1, len(d)):
+        if d[k - 1] == 0.0 or d[k - 1] * d[k] < 0.0:
+            z.append(t[k - 1] + (t[k] - t[k - 1]) * d[k - 1] / (d[k - 1] - d[k]))
+    if len(z) < 3:
+        return float("nan"), z
+    return float(2.0 * np.mean(np.diff(z))), z
+
+
+def run_oscillation(sizes=(200, 300, 400, 600, 800), steps=None, sample_every=50, periods=3.0, beta=1.815,
+                    forcing="guo", progress=None):
+    """All sizes as one batch; the semi-axes are sampled every sample_every steps
+    (computed on the device from the density field); returns the periods."""
+    cases = [ellipse_case(n, beta=beta) for n in sizes]
+    if steps is None:
+        # enough for `periods` periods of the largest drop, from the paper's Table 3 scale (T ~ n^1.5)
+        steps = int(periods * 18112.0 * (max(sizes) / 800.0) ** 1.5) + 2000
+    boxes = [{"mix": c["mix"], "shape": c["shape"], "T": c["T"], "tau": c["tau"], "beta": c["beta"],
+              "gamma": c["gamma"], "rho0": c["rho0"]} for c in cases]
+    b = lbm.LbmBatch(boxes, "D2Q9", collision="bgk", forcing=forcing, storage="f64", graph_steps=sample_every)
+    series = [[] for _ in cases]
+    t = []
+    try:
+        done = 0
+        while done < steps:
+            b.step(sample_every)
+            done += sample_every
+            t.append(done)
+            for k, r in enumerate(b.fields()):
+                series[k].append(axes_of(r))
+            if progress is not None and len(t) % 200 == 0:
+                progress(done, float("nan"))
+        bad = b.box_errors()
+        if bad.any():
+            raise lbm.LbmError(lbm.LBM_ERR_DOMAIN, f"boxes {np.nonzero(bad)[0].tolist()} left the EOS domain")
+        b.check()
+    finally:
+        b.close()
+    out = []
+    for c, ser in zip(cases, series):
+        ser = np.asarray(ser)
+        period, crossings = oscillation_period(t, ser[:, 0] - ser[:, 1])
+        out.append({"n": c["n"], "period": period, "crossings": crossings[:12],
+                    "rx_final": float(ser[-1, 0]), "ry_final": float(ser[-1, 1])})
+    return {"steps": steps, "sample_every": sample_every, "beta": beta, "drops": out}
+
+
 def main():
     import argparse
     import json
@@ -313,6 +413,7 @@ def main():
     ap.add_argument("--calibrate", action="store_true", help="sweep beta instead")
     ap.add_argument("--laplace", action="store_true", help="Laplace's law on drops instead (Sec. 4.3)")
     ap.add_argument("--sizes", default="50,100,200,400,800")
+    ap.add_argument("--oscillation", action="store_true", help="oscillating elliptical drop instead (Table 3)")
     ap.add_argument("--betas", default="", help="comma list for --calibrate (default 1.0..2.0 step 0.1)")
     args = ap.parse_args()
     ps = [float(p) for p in args.pressures.split(",")]
@@ -322,7 +423,10 @@ def main():
         print(f"steps {steps} max relative change of the bulk densities {change:.3e}", file=sys.stderr, flush=True)
 
     kw = dict(max_steps=args.max_steps, check_every=args.check_every, tol=args.tol, progress=progress)
-    if args.laplace:
+    if args.oscillation:
+        out = run_oscillation(sizes=[int(n) for n in args.sizes.split(",")], beta=args.beta, forcing=args.forcing,
+                              progress=progress)
+    elif args.laplace:
         out = run_laplace(ps, sizes=[int(n) for n in args.sizes.split(",")], beta=args.beta, forcing=args.forcing,
                           collision=args.collision, **kw)
     elif args.calibrate:

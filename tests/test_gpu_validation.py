@@ -40,3 +40,25 @@ def test_laplace_law_on_drops():
     assert r["sigma"] == pytest.approx(0.1289, rel=0.10)
     for d in r["drops"]:
         assert d["dp"] > 0.0 and d["y"][0] > d["x"][0]
+
+
+def test_oscillating_drop_period():
+    """Sec. 4.3 / Table 3: elliptical drop (h = 0.9, R0 = 0.15 n) at 580 degR and
+    70 psia (density ratio ~58), Guo forcing, beta = 1.815, n = 200.  The period
+    of the axis oscillation must agree with the model period of Table 3 (2407)
+    within 6 % and with Lamb's period (2129) within 10 %."""
+    import os
+    from paper_1909_12390_amd import validation as V
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table3_periods.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                n, th, mo = line.split()
+                rows[int(n)] = (float(th), float(mo))
+    print("case oscillating drop n=200", flush=True)
+    out = V.run_oscillation(sizes=(200,), steps=7500, sample_every=25)
+    period = out["drops"][0]["period"]
+    theory, model = rows[200]
+    print(f"  period {period:.0f} (paper model {model:.0f}, theory {theory:.0f})", flush=True)
+    assert period == pytest.approx(model, rel=0.06)
+    assert period == pytest.approx(theory, rel=0.10)
