@@ -268,8 +268,8 @@ void lbm_batch_destroy(lbm_batch* b);
  * Discrete adjoint (reverse-mode derivative of the step).  The paper does not
  * differentiate its model; these calls give the exact derivative of the discrete
  * step of Sec. 3.4 (the transpose of its Jacobian), evaluated in float64 at the
- * stored states, for BGK collision with the exact-difference forcing (any storage,
- * lattice and nc; other collision/forcing choices return LBM_ERR_ARG).
+ * stored states, for BGK collision with the exact-difference or Guo forcing (any
+ * storage, lattice and nc; MRT collision returns LBM_ERR_ARG).
  * Parameters: the EOS tables aa_ij = sqrt(a_i alpha_i a_j alpha_j)(1 - k_ij) and
  * b_i of Eq. (randommixingrule) / Eq. (MCPengRobinson), chained to (k_ij, a_i, b_i)
  * with alpha_i following a_i and b_i through Tc_i (Sec. 3.2).

@@ -249,7 +249,8 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
   kp.err = c->err;
   c->ops = prm->lattice == LBM_D2Q9 ? ops_d2q9(mix->nc, prm->storage, prm->collision, prm->forcing)
                                     : ops_d3q19(mix->nc, prm->storage, prm->collision, prm->forcing);
-  c->adj = prm->lattice == LBM_D2Q9 ? adj_ops_d2q9(mix->nc, prm->storage) : adj_ops_d3q19(mix->nc, prm->storage);
+  c->adj = prm->lattice == LBM_D2Q9 ? adj_ops_d2q9(mix->nc, prm->storage, prm->forcing)
+                                    : adj_ops_d3q19(mix->nc, prm->storage, prm->forcing);
   if (prm->slab_planes > 0) {
     c->slab = prm->slab_planes;
   } else {

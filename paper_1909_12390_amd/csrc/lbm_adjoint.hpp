@@ -1,4 +1,4 @@
-// Discrete adjoint of one step (BGK collision with the exact-difference forcing),
+// Discrete adjoint of one step (BGK collision with the exact-difference or Guo forcing),
 // i.e. the transpose of the step's Jacobian applied to the adjoint of the
 // post-streaming populations after the step, plus the step's contribution to the
 // derivative with respect to the EOS tables (a alpha)_ij (1 - k_ij) and b_i.
@@ -31,6 +31,15 @@
 //   dp/dn_i  = RT/(1-B) + n_t RT b_i/(1-B)^2 - 2 (aa n)_i / D + 2 A b_i (1-B) / D^2
 //   dp/daa_ij = -n_i n_j / D            dp/db_i = n_i (n_t RT/(1-B)^2 + 2 A (1-B)/D^2).
 //
+// With Guo forcing (u = (j + F_tot/2)/rho, F_s = gamma_s rbar_s F / Gamma + rbar_s g,
+// f*_sa = (1-omega) f_sa + omega feq_a(rbar_s, u) + (1 - omega/2) S_sa,
+// S_sa = w_a [3 (e_a - u).F_s + 9 (e_a.u)(e_a.F_s)]) the local part becomes
+//   F^_s      = (1 - omega/2) gPhi_s(u)       (sum_a hs_a S_a is linear in F_s)
+//   u^        = sum_s [omega rbar_s gPhi_s(u) + (1 - omega/2)(9 A2 F_s - 3 A0 F_s)]
+//   F^        = sum_s (gamma_s rbar_s / Gamma) F^_s + u^ / (2 rho)
+//   rbar^_s   = omega Phi_s(u) + gamma_s (F^_s.F)/Gamma - gamma_s (sum_t chi_t F^_t.F)/Gamma
+//               + F^_s.g - u^.(u - g/2)/rho + [EOS, psi terms]
+//
 // Two passes per step: ka_cell (everything local to x, writes F^, j^, the local
 // part of rbar^ and rbar) and kb_cell (the transposed psi stencil, the EOS adjoint,
 // the output and the parameter partials).  psi of the state comes from k_psi.
@@ -47,7 +56,7 @@ struct AdjScratch {
   double* rb;      // [NC] rbar of the state
 };
 
-template <int LAT, int NC, int ST>
+template <int LAT, int NC, int ST, int FORC>
 __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, const double* __restrict__ psi,
                                                  const double* __restrict__ h, AdjScratch S) {
   using V = VS<LAT>;
@@ -75,16 +84,21 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
     rho += acc;
   }
   const double irho = 1.0 / rho;
-  const double u[3] = {j[0] * irho, j[1] * irho, j[2] * irho};
   double Gam = 0.0;
 #pragma unroll
   for (int s = 0; s < NC; ++s) Gam += P.gamma[s] * rb[s];
   const double iG = 1.0 / Gam;
   double F[3];
   force_at<LAT>(P, psi[cell], [&](int a) { return psi[c.at(V::cx(a), V::cy(a), V::cz(a))]; }, F);
+  const double* g = P.accel;
+  double u[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    u[d] = (FORC == LBM_GUO) ? (j[d] + 0.5 * (F[d] + rho * g[d])) * irho : j[d] * irho;
   const double om = P.omega;
+  const double gk = 1.0 - 0.5 * om;   // Guo source prefactor
   double ub[3] = {0.0, 0.0, 0.0}, Fb[3] = {0.0, 0.0, 0.0}, Gb = 0.0;
-  double rbA[NC];
+  double rbA[NC], FbF[NC];
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
     // moments of the adjoint of f* (gathered from the downstream neighbours)
@@ -92,51 +106,90 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
     const double* hs = h + (size_t)s * Q * N;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      const double g = V::w(a) * hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))];
+      const double w = V::w(a) * hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))];
       const int ex = V::cx(a), ey = V::cy(a), ez = V::cz(a);
-      A0 += g;
-      if (ex) A1[0] += ex * g;
-      if (ey) A1[1] += ey * g;
-      if (ez) A1[2] += ez * g;
-      if (ex) A2[0] += g;
-      if (ey) A2[1] += g;
-      if (ez) A2[2] += g;
-      if (ex * ey) A2[3] += ex * ey * g;
-      if (ex * ez) A2[4] += ex * ez * g;
-      if (ey * ez) A2[5] += ey * ez * g;
+      A0 += w;
+      if (ex) A1[0] += ex * w;
+      if (ey) A1[1] += ey * w;
+      if (ez) A1[2] += ez * w;
+      if (ex) A2[0] += w;
+      if (ey) A2[1] += w;
+      if (ez) A2[2] += w;
+      if (ex * ey) A2[3] += ex * ey * w;
+      if (ex * ez) A2[4] += ex * ez * w;
+      if (ey * ez) A2[5] += ey * ez * w;
     }
-    double duF[3], v[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      duF[d] = P.gamma[s] * F[d] * iG;
-      v[d] = u[d] + duF[d] + P.accel[d];
-    }
+    auto A2v = [&](const double* v, double* out) {
+      out[0] = A2[0] * v[0] + A2[3] * v[1] + A2[4] * v[2];
+      out[1] = A2[3] * v[0] + A2[1] * v[1] + A2[5] * v[2];
+      out[2] = A2[4] * v[0] + A2[5] * v[1] + A2[2] * v[2];
+    };
     auto phi = [&](const double* w) {
+      double Aw[3];
+      A2v(w, Aw);
       const double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-      const double wAw = A2[0] * w[0] * w[0] + A2[1] * w[1] * w[1] + A2[2] * w[2] * w[2] +
-                         2.0 * (A2[3] * w[0] * w[1] + A2[4] * w[0] * w[2] + A2[5] * w[1] * w[2]);
-      return A0 * (1.0 - 1.5 * ww) + 3.0 * (A1[0] * w[0] + A1[1] * w[1] + A1[2] * w[2]) + 4.5 * wAw;
+      return A0 * (1.0 - 1.5 * ww) + 3.0 * (A1[0] * w[0] + A1[1] * w[1] + A1[2] * w[2]) +
+             4.5 * (w[0] * Aw[0] + w[1] * Aw[1] + w[2] * Aw[2]);
     };
     auto gphi = [&](const double* w, double* out) {
-      const double Aw[3] = {A2[0] * w[0] + A2[3] * w[1] + A2[4] * w[2], A2[3] * w[0] + A2[1] * w[1] + A2[5] * w[2],
-                            A2[4] * w[0] + A2[5] * w[1] + A2[2] * w[2]};
+      double Aw[3];
+      A2v(w, Aw);
 #pragma unroll
       for (int d = 0; d < 3; ++d) out[d] = -3.0 * A0 * w[d] + 3.0 * A1[d] + 9.0 * Aw[d];
     };
-    double gu[3], gv[3];
+    double gu[3];
     gphi(u, gu);
-    gphi(v, gv);
-    rbA[s] = (om - 1.0) * phi(u) + phi(v);
-    double dub[3];
+    if constexpr (FORC == LBM_EDM) {
+      double duF[3], v[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      ub[d] += rb[s] * ((om - 1.0) * gu[d] + gv[d]);
-      dub[d] = rb[s] * gv[d];
-      Fb[d] += P.gamma[s] * iG * dub[d];
+      for (int d = 0; d < 3; ++d) {
+        duF[d] = P.gamma[s] * F[d] * iG;
+        v[d] = u[d] + duF[d] + g[d];
+      }
+      double gv[3];
+      gphi(v, gv);
+      rbA[s] = (om - 1.0) * phi(u) + phi(v);
+      double dub[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        ub[d] += rb[s] * ((om - 1.0) * gu[d] + gv[d]);
+        dub[d] = rb[s] * gv[d];
+        Fb[d] += P.gamma[s] * iG * dub[d];
+      }
+      Gb -= (duF[0] * dub[0] + duF[1] * dub[1] + duF[2] * dub[2]) * iG;
+      FbF[s] = 0.0;
+    } else {
+      const double chi = P.gamma[s] * rb[s] * iG;
+      double Fs[3], AF[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Fs[d] = chi * F[d] + rb[s] * g[d];
+      A2v(Fs, AF);
+      rbA[s] = om * phi(u);
+      double fbs_F = 0.0, fbs_g = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double Fbs = gk * gu[d];               // adjoint of F_s
+        ub[d] += om * rb[s] * gu[d] + gk * (9.0 * AF[d] - 3.0 * A0 * Fs[d]);
+        Fb[d] += chi * Fbs;
+        fbs_F += Fbs * F[d];
+        fbs_g += Fbs * g[d];
+      }
+      rbA[s] += P.gamma[s] * fbs_F * iG + fbs_g;
+      FbF[s] = chi * fbs_F;                          // chi_s F^_s . F
     }
-    Gb -= (duF[0] * dub[0] + duF[1] * dub[1] + duF[2] * dub[2]) * iG;
   }
-  const double uub = (ub[0] * u[0] + ub[1] * u[1] + ub[2] * u[2]) * irho;
+  if constexpr (FORC == LBM_GUO) {
+    double cs = 0.0;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) cs += FbF[s];
+    Gb = -cs * iG;                                   // d/d Gamma through chi_s = gamma_s rbar_s / Gamma
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Fb[d] += 0.5 * ub[d] * irho;
+  }
+  double uub = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) uub += ub[d] * ((FORC == LBM_GUO) ? (u[d] - 0.5 * g[d]) : u[d]);
+  uub *= irho;
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
     S.rbA[(size_t)s * N + cell] = rbA[s] + P.gamma[s] * Gb - uub;

@@ -109,8 +109,8 @@ Ops ops_lat(int nc, int st, int coll, int forc) {
   }
 }
 
-// Launchers of the adjoint passes (BGK + exact-difference forcing) and of the loss
-// helpers, per (lattice, nc, storage).
+// Launchers of the adjoint passes (BGK collision; exact-difference or Guo forcing)
+// and of the loss helpers, per (lattice, nc, storage, forcing).
 struct AdjOps {
   void (*a)(const KParams&, const Bufs& state, const double* psi, const double* h, const AdjScratch&, hipStream_t);
   void (*b)(const KParams&, const double* psi, const double* h, const AdjScratch&, double* hout, double* partials,
@@ -119,11 +119,11 @@ struct AdjOps {
   void (*seed)(const KParams&, const unsigned char* mask, const double* coef, double* h, hipStream_t);
 };
 
-template <int LAT, int NC, int ST>
+template <int LAT, int NC, int ST, int FORC>
 struct AdjOpsImpl {
   static void a(const KParams& P, const Bufs& state, const double* psi, const double* h, const AdjScratch& S,
                 hipStream_t st) {
-    hipLaunchKernelGGL((ka_cell<LAT, NC, ST>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
+    hipLaunchKernelGGL((ka_cell<LAT, NC, ST, FORC>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
                        make_pops<ST>(state), psi, h, S);
   }
   static void b(const KParams& P, const double* psi, const double* h, const AdjScratch& S, double* hout,
@@ -143,29 +143,34 @@ struct AdjOpsImpl {
   static AdjOps ops() { return AdjOps{&a, &b, &moles, &seed}; }
 };
 
+template <int LAT, int NC, int ST>
+AdjOps adj_ops_f(int forc) {
+  return forc == LBM_GUO ? AdjOpsImpl<LAT, NC, ST, LBM_GUO>::ops() : AdjOpsImpl<LAT, NC, ST, LBM_EDM>::ops();
+}
+
 template <int LAT, int NC>
-AdjOps adj_ops_st(int st) {
+AdjOps adj_ops_st(int st, int forc) {
   switch (st) {
-    case LBM_F64: return AdjOpsImpl<LAT, NC, LBM_F64>::ops();
-    case LBM_F32_OFS: return AdjOpsImpl<LAT, NC, LBM_F32_OFS>::ops();
-    default: return AdjOpsImpl<LAT, NC, LBM_F16_OFS>::ops();
+    case LBM_F64: return adj_ops_f<LAT, NC, LBM_F64>(forc);
+    case LBM_F32_OFS: return adj_ops_f<LAT, NC, LBM_F32_OFS>(forc);
+    default: return adj_ops_f<LAT, NC, LBM_F16_OFS>(forc);
   }
 }
 
 template <int LAT>
-AdjOps adj_ops_lat(int nc, int st) {
+AdjOps adj_ops_lat(int nc, int st, int forc) {
   switch (nc) {
-    case 1: return adj_ops_st<LAT, 1>(st);
-    case 2: return adj_ops_st<LAT, 2>(st);
-    case 3: return adj_ops_st<LAT, 3>(st);
-    default: return adj_ops_st<LAT, 4>(st);
+    case 1: return adj_ops_st<LAT, 1>(st, forc);
+    case 2: return adj_ops_st<LAT, 2>(st, forc);
+    case 3: return adj_ops_st<LAT, 3>(st, forc);
+    default: return adj_ops_st<LAT, 4>(st, forc);
   }
 }
 
 // defined in lbm_d2q9.hip / lbm_d3q19.hip
 Ops ops_d2q9(int nc, int st, int coll, int forc);
 Ops ops_d3q19(int nc, int st, int coll, int forc);
-AdjOps adj_ops_d2q9(int nc, int st);
-AdjOps adj_ops_d3q19(int nc, int st);
+AdjOps adj_ops_d2q9(int nc, int st, int forc);
+AdjOps adj_ops_d3q19(int nc, int st, int forc);
 
 }  // namespace lbmk

@@ -30,18 +30,22 @@ def _lbm():
     return lbm
 
 
-def context(c, lattice, storage="f64", beta=1.16, tau=0.8):
+def context(c, lattice, storage="f64", beta=1.16, tau=0.8, forcing="edm", accel=None):
     return _lbm().LbmContext(c["mix"], lattice, c["shape"], c["T"], tau, beta, c["gamma"], c["rho0"],
-                             collision="bgk", forcing="edm", storage=storage)
+                             collision="bgk", forcing=forcing, storage=storage, accel=accel)
 
 
+@pytest.mark.parametrize("forcing,accel", [("edm", None), ("guo", None), ("guo", (2e-5, -1e-5, 3e-6))])
 @pytest.mark.parametrize("lattice,nc,shape", [("D2Q9", 3, (12, 14)), ("D2Q9", 1, (10, 9)), ("D2Q9", 4, (9, 11)),
                                               ("D3Q19", 2, (5, 6, 7))])
-def test_step_adjoint_matches_oracle(lattice, nc, shape):
-    print(f"case step adjoint {lattice} nc={nc} {shape}", flush=True)
+def test_step_adjoint_matches_oracle(lattice, nc, shape, forcing, accel):
+    print(f"case step adjoint {lattice} nc={nc} {shape} {forcing} accel={accel}", flush=True)
     c = case(lattice, nc, shape, seed=1, u_amp=0.01)
     c["u0"] = None
-    ctx = context(c, lattice)
+    D = 2 if lattice == "D2Q9" else 3
+    acc = None if accel is None else np.asarray(accel[:D])
+    beta = 1.16 if forcing == "edm" else 1.7
+    ctx = context(c, lattice, forcing=forcing, beta=beta, accel=acc)
     ctx.step(3)
     f = ctx.get_populations().cpu().numpy()
     h = np.random.default_rng(5).standard_normal(f.shape)
@@ -49,7 +53,7 @@ def test_step_adjoint_matches_oracle(lattice, nc, shape):
     ctx.check()
     assert np.array_equal(ctx.get_populations().cpu().numpy(), f)   # state untouched
     base = to_mixture(c["mix"])
-    prm = oracle_params(c, "bgk", "edm", tau=0.8, beta=1.16)
+    prm = oracle_params(c, "bgk", forcing, tau=0.8, beta=beta, accel=acc)
     aa, b = oadj.eos_tables(torch.as_tensor(oadj.theta_of(base), dtype=oadj.DT), base, c["T"])
     gf, gaa, gb = oadj.step_vjp_tables(f, h, aa.numpy(), b.numpy(), base, prm, LAT[lattice])
     assert np.max(np.abs(hout.cpu().numpy() - gf)) <= 1e-11 * np.max(np.abs(gf))
@@ -67,24 +71,25 @@ def small_problem(seed=2, shape=(12, 14), nsteps=12):
     return c, mask, base, f0, x_tgt, nsteps
 
 
-def gpu_gradient(c, mask, x_tgt, nsteps, K, storage="f64"):
+def gpu_gradient(c, mask, x_tgt, nsteps, K, storage="f64", forcing="edm"):
     from paper_1909_12390_amd import adjoint as padj
-    ctx = context(c, "D2Q9", storage)
+    ctx = context(c, "D2Q9", storage, forcing=forcing, beta=1.16 if forcing == "edm" else 1.7)
     r = ctx.adjoint(nsteps, K, mask, x_tgt)
     ctx.close()
     return r, padj.pack_gradient(r["d_k"], r["d_a"], r["d_b"])
 
 
-def test_gradient_run_matches_oracle_gradient():
-    print("case adjoint run vs oracle", flush=True)
+@pytest.mark.parametrize("forcing", ["edm", "guo"])
+def test_gradient_run_matches_oracle_gradient(forcing):
+    print(f"case adjoint run vs oracle {forcing}", flush=True)
     c, mask, base, f0, x_tgt, nsteps = small_problem()
-    prm = oracle_params(c, "bgk", "edm", tau=0.8, beta=1.16)
+    prm = oracle_params(c, "bgk", forcing, tau=0.8, beta=1.16 if forcing == "edm" else 1.7)
     L, g = oadj.gradient(oadj.theta_of(base), f0, base, prm, LAT["D2Q9"], nsteps, mask, x_tgt)
-    r, gg = gpu_gradient(c, mask, x_tgt, nsteps, K=5)
+    r, gg = gpu_gradient(c, mask, x_tgt, nsteps, K=5, forcing=forcing)
     assert abs(r["loss"] - L) <= 1e-11 * L
     assert np.max(np.abs(gg - g)) <= 1e-9 * np.max(np.abs(g))
     # float32 storage: same gradient to the precision of the stored states
-    r32, g32 = gpu_gradient(c, mask, x_tgt, nsteps, K=5, storage="f32")
+    r32, g32 = gpu_gradient(c, mask, x_tgt, nsteps, K=5, storage="f32", forcing=forcing)
     assert np.max(np.abs(g32 - g)) <= 1e-4 * np.max(np.abs(g))
 
 
