@@ -171,6 +171,12 @@ lbm_status lbm_step_timed(lbm_ctx* ctx, int nsteps, double* kernel_ms_host);
 /* Synchronise the stream and report the device error flag (LBM_OK / LBM_ERR_DOMAIN). */
 lbm_status lbm_check(lbm_ctx* ctx);
 
+/* Replace the volatility coefficients gamma_i of Eq. (gamma) used by the force split
+ * (host, nc values in (0, 1]); the next enqueued step uses them.  The paper's gamma
+ * depends on (T, p, z) (Sec. 3.1); this lets a caller re-flash at the evolving bulk
+ * state and update it during a run. */
+lbm_status lbm_set_gamma(lbm_ctx* ctx, const double* gamma_host);
+
 /* Clear the device error flag. */
 lbm_status lbm_clear_error(lbm_ctx* ctx);
 
@@ -260,6 +266,11 @@ lbm_status lbm_batch_check(lbm_batch* b);
 /* Synchronise and copy the per-box error flags (host int [nboxes], 1 = the box left
  * the EOS domain or produced a non-finite value) so a sweep can tell which states failed. */
 lbm_status lbm_batch_box_errors(lbm_batch* b, int* flags_host);
+
+/* Replace gamma of one box (host, nc_b values in (0, 1]); written to the device box
+ * table in stream order; synchronises the stream.  Captured graphs read the table,
+ * so later replays use the new values. */
+lbm_status lbm_batch_set_gamma(lbm_batch* b, int box, const double* gamma_host);
 
 /* Release the batch (not the caller's workspace); NULL is accepted. */
 void lbm_batch_destroy(lbm_batch* b);

@@ -334,6 +334,17 @@ extern "C" lbm_status lbm_check(lbm_ctx* c) {
   return LBM_OK;
 }
 
+extern "C" lbm_status lbm_set_gamma(lbm_ctx* c, const double* gamma) {
+  if (!c || !gamma) return lbm_fail(LBM_ERR_ARG, "bad lbm_set_gamma arguments");
+  for (int i = 0; i < c->mix.nc; ++i)
+    if (!(gamma[i] > 0.0 && gamma[i] <= 1.0)) return lbm_fail(LBM_ERR_ARG, "gamma_%d outside (0, 1]", i);
+  for (int i = 0; i < c->mix.nc; ++i) {
+    c->prm.gamma[i] = gamma[i];
+    c->kp.gamma[i] = gamma[i];   // kernel arguments: the next launch uses the new values
+  }
+  return LBM_OK;
+}
+
 extern "C" lbm_status lbm_clear_error(lbm_ctx* c) {
   if (!c) return lbm_fail(LBM_ERR_ARG, "ctx is NULL");
   return hip_check(hipMemsetAsync(c->err, 0, sizeof(int), c->stream), "hipMemsetAsync(err)");

@@ -116,6 +116,7 @@ void fill_mrt_b(const lbm_batch_params* prm, BatchK* K) {
 
 struct lbm_batch {
   int nboxes;
+  std::vector<int> box_nc;
   lbm_batch_params prm;
   BatchK K;
   BOps ops;
@@ -210,6 +211,8 @@ extern "C" lbm_status lbm_batch_init(const lbm_box* boxes, int nboxes, const lbm
   if (!b) return lbm_fail(LBM_ERR_ARG, "out of host memory");
   b->prm = *prm;
   b->nboxes = nboxes;
+  b->box_nc.resize(nboxes);
+  for (int i = 0; i < nboxes; ++i) b->box_nc[i] = boxes[i].mix.nc;
   b->stream = (hipStream_t)stream;
   char* base = (char*)ws;
   for (int k = 0; k < 2; ++k) {
@@ -327,6 +330,23 @@ extern "C" lbm_status lbm_batch_check(lbm_batch* b) {
   if (st != LBM_OK) return st;
   if (flag) return lbm_fail(LBM_ERR_DOMAIN, "EOS/psi domain violation or non-finite value in a box");
   return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_set_gamma(lbm_batch* b, int box, const double* gamma) {
+  if (!b || !gamma || box < 0 || box >= b->nboxes) return lbm_fail(LBM_ERR_ARG, "bad lbm_batch_set_gamma arguments");
+  const int nc = b->box_nc[box];
+  double g[LBM_MAX_NC] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < nc; ++i) {
+    if (!(gamma[i] > 0.0 && gamma[i] <= 1.0)) return lbm_fail(LBM_ERR_ARG, "gamma_%d outside (0, 1]", i);
+    g[i] = gamma[i];
+  }
+  // the box table lives on the device and is read by every launch (graph replays too):
+  // write it in stream order, then wait so the host buffer may go
+  BoxK* dst = const_cast<BoxK*>(b->K.boxes) + box;
+  lbm_status st = hip_check(hipMemcpyAsync(dst->gamma, g, sizeof(double) * LBM_MAX_NC, hipMemcpyHostToDevice,
+                                           b->stream), "update gamma");
+  if (st == LBM_OK) st = hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  return st;
 }
 
 extern "C" lbm_status lbm_batch_box_errors(lbm_batch* b, int* flags) {

@@ -37,7 +37,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure",
             "lbm_batch_layout", "lbm_batch_init", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_check",
             "lbm_batch_box_errors", "lbm_batch_destroy", "lbm_adjoint_workspace", "lbm_step_adjoint",
-            "lbm_adjoint", "lbm_eos_param_grad"]
+            "lbm_adjoint", "lbm_eos_param_grad", "lbm_set_gamma", "lbm_batch_set_gamma"]
 
 
 class LbmError(RuntimeError):
@@ -124,6 +124,8 @@ def lib() -> ctypes.CDLL:
         L.lbm_step_adjoint.argtypes = [c_void_p, c_void_p, c_void_p, dp, dp, c_void_p, c_size_t]
         L.lbm_adjoint.argtypes = [c_void_p, c_int, c_int, c_void_p, dp, c_void_p, c_size_t, dp, dp, dp, dp, dp]
         L.lbm_eos_param_grad.argtypes = [POINTER(LbmMixture), c_double, dp, dp, dp, dp, dp]
+        L.lbm_set_gamma.argtypes = [c_void_p, dp]
+        L.lbm_batch_set_gamma.argtypes = [c_void_p, c_int, dp]
         for name in EXPORTED:
             f = getattr(L, name)
             if name not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy"):
@@ -343,6 +345,12 @@ class LbmContext:
     def clear_error(self):
         _check(lib().lbm_clear_error(self._ctx))
 
+    def set_gamma(self, gamma):
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+        if g.shape != (self.nc,):
+            raise ValueError(f"gamma must have {self.nc} entries")
+        _check(lib().lbm_set_gamma(self._ctx, _dptr(g)))
+
     def moments(self, fields=True, totals=True):
         torch = self.torch
         dev = self.workspace.device
@@ -515,6 +523,10 @@ class LbmBatch:
 
     def check(self):
         _check(lib().lbm_batch_check(self._ctx))
+
+    def set_gamma(self, box, gamma):
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+        _check(lib().lbm_batch_set_gamma(self._ctx, int(box), _dptr(g)))
 
     def box_errors(self):
         """Per-box error flags (numpy int array, 1 = the box left the EOS domain)."""

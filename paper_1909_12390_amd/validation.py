@@ -146,11 +146,39 @@ def phase_report(mix, T, rbar_l, rbar_v, flash):
     return out
 
 
+def overall_composition(rho_s, M):
+    """Mole fractions of the whole box (conserved by the step)."""
+    n = np.asarray(rho_s).reshape(len(M), -1).sum(axis=1) / np.asarray(M, dtype=np.float64)
+    return n / n.sum()
+
+
+def reflash_gamma(case, rho_s):
+    """State-dependent gamma: flash at the box's LB bulk pressure (p_EOS of the bulk
+    liquid and vapour, averaged) and its overall composition; returns the new
+    gamma and the pressure, or (None, p) if the flash finds one phase or a gamma
+    outside (0, 1]."""
+    mix, T = case["mix"], case["T"]
+    rl, rv = bulk_state(rho_s, mix)
+    M = np.asarray(mix["M"], dtype=np.float64)
+    p = lbm.lbm_pressure(mix, T, np.stack([rl / M, rv / M]))
+    p_lb = 0.5 * float(p[0] + p[1])
+    try:
+        fl = lbm.lbm_flash(mix, T, p_lb, overall_composition(rho_s, M))
+    except lbm.LbmError:
+        return None, p_lb
+    g = np.asarray(fl.gamma)
+    if not np.all((g > 0.0) & (g <= 1.0)):     # outside the model's range: keep the old gamma
+        return None, p_lb
+    return g, p_lb
+
+
 def run_flat(cases, collision="bgk", forcing="guo", storage="f64", max_steps=2_000_000, check_every=20_000,
-             tol=1e-9, graph_steps=1000, progress=None):
+             tol=1e-9, graph_steps=1000, progress=None, gamma_update=False):
     """Advance the boxes together until the bulk densities of every box change by
     less than tol (relative) over check_every steps.  Returns the reports;
-    progress(steps, change) is called after every check."""
+    progress(steps, change) is called after every check.  With gamma_update, every
+    check re-flashes each box at its current bulk pressure and overall composition
+    and replaces its gamma (state-dependent gamma, Sec. 3.1)."""
     boxes = [{"mix": c["mix"], "shape": c["shape"], "T": c["T"], "tau": c["tau"], "beta": c["beta"],
               "gamma": c["gamma"], "rho0": c["rho0"]} for c in cases]
     rates = None
@@ -171,6 +199,12 @@ def run_flat(cases, collision="bgk", forcing="guo", storage="f64", max_steps=2_0
                 raise lbm.LbmError(lbm.LBM_ERR_DOMAIN, f"boxes {np.nonzero(bad)[0].tolist()} left the EOS domain")
             rho = [r.cpu().numpy() for r in b.fields()]
             bulk = [np.concatenate(bulk_state(r, c["mix"])) for r, c in zip(rho, cases)]
+            if gamma_update:
+                for k, (r, c) in enumerate(zip(rho, cases)):
+                    g, _ = reflash_gamma(c, r)
+                    if g is not None:
+                        b.set_gamma(k, g)
+                        c["gamma"] = g
             if prev is not None:
                 change = max(float(np.max(np.abs(u - v) / np.abs(v))) for u, v in zip(bulk, prev))
             if progress is not None:
@@ -186,7 +220,14 @@ def run_flat(cases, collision="bgk", forcing="guo", storage="f64", max_steps=2_0
         rl, rv = bulk_state(r, c["mix"])
         rep = phase_report(c["mix"], c["T"], rl, rv, c["flash"])
         rep.update({"p_psia": c["p_psia"], "beta": c["beta"], "steps": steps, "last_change": change,
-                    "p_lb_psia": 0.5 * (rep["p_l"] + rep["p_v"]) * c["units"].sp})
+                    "p_lb_psia": 0.5 * (rep["p_l"] + rep["p_v"]) * c["units"].sp,
+                    "gamma": np.asarray(c["gamma"]).tolist()})
+        # the same bulk states against the flash at the LB pressure and overall composition
+        fl_lb = lbm.lbm_flash(c["mix"], c["T"], 0.5 * (rep["p_l"] + rep["p_v"]),
+                              overall_composition(r, c["mix"]["M"]))
+        lb = phase_report(c["mix"], c["T"], rl, rv, fl_lb)
+        rep["err_composition_at_lb_pressure"] = lb["err_composition"]
+        rep["err_density_at_lb_pressure"] = lb["err_density"]
         reports.append(rep)
     return reports
 
@@ -410,6 +451,7 @@ def main():
     ap.add_argument("--max-steps", type=int, default=2_000_000)
     ap.add_argument("--check-every", type=int, default=50_000)
     ap.add_argument("--tol", type=float, default=1e-9)
+    ap.add_argument("--gamma-update", action="store_true", help="re-flash gamma at every check")
     ap.add_argument("--calibrate", action="store_true", help="sweep beta instead")
     ap.add_argument("--laplace", action="store_true", help="Laplace's law on drops instead (Sec. 4.3)")
     ap.add_argument("--sizes", default="50,100,200,400,800")
@@ -434,7 +476,7 @@ def main():
         out = calibrate_beta(ps, forcing=args.forcing, collision=args.collision, nx=args.nx, betas=betas, **kw)
     else:
         cases = [flat_case(p, nx=args.nx, beta=args.beta) for p in ps]
-        reps = run_flat(cases, collision=args.collision, forcing=args.forcing, **kw)
+        reps = run_flat(cases, collision=args.collision, forcing=args.forcing, gamma_update=args.gamma_update, **kw)
         out = {"reports": reps, "worst_composition_err": max(r["err_composition"] for r in reps),
                "worst_density_err": max(r["err_density"] for r in reps)}
     print(json.dumps(out, default=float))
