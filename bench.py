@@ -286,7 +286,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f16", choices=list(STORAGE_BYTES))
-    ap.add_argument("--schedule", default="two_pass", choices=["two_pass", "blocked"])
+    ap.add_argument("--schedule", default="two_pass", choices=["two_pass", "blocked", "overlap"])
     ap.add_argument("--slab-planes", type=int, default=0, help="blocked schedule: planes per slab (0 = auto)")
     ap.add_argument("--side", type=int, default=128)
     ap.add_argument("--diag-every", type=int, default=100)
@@ -398,7 +398,7 @@ def main():
     if modes:
         res = {}
         for m in modes:
-            for sched in ("two_pass", "blocked"):
+            for sched in ("two_pass", "blocked", "overlap"):
                 c = make(m, sched)
                 w, k = timed(c, args.steps, args.warmup, args.diag_every)
                 res[f"{m}/{sched}"] = {

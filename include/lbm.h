@@ -53,9 +53,11 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
 enum { LBM_BGK = 0, LBM_MRT = 1 };
 enum { LBM_GUO = 0, LBM_EDM = 1 };
 /* Population storage.  F64: plain float64 populations, float64 collision.
- * F32_OFS / F16_OFS: per cell and component a float32 base b = rbar_sigma and Q
- * offsets r_a = f_a / b - w_a stored in float32 / float16 (round to nearest even);
- * collision in float32; EOS, psi and the force stencil stay float64. */
+ * F32_OFS / F16_OFS: per cell and component a float32 base b and Q offsets
+ * r_a = f_a / b0 - w_a stored in float32 / float16 (round to nearest even), with
+ * b0 = sum_a |f_a| and b rescaled after rounding so that the decoded populations
+ * sum to the component's mass; decode f_a = b (w_a + r_a).  Collision in float32;
+ * EOS, psi, the force stencil and the masses stay float64. */
 enum { LBM_F64 = 0, LBM_F32_OFS = 1, LBM_F16_OFS = 2 };
 /* Kernel schedule of one step (identical results).
  * TWO_PASS: a density/EOS/psi pass over the whole box, then a collide pass.
@@ -63,8 +65,14 @@ enum { LBM_F64 = 0, LBM_F32_OFS = 1, LBM_F16_OFS = 2 };
  *           3-D): psi on the slab plus one plane each side, then the collide pass of
  *           the slab, so the collide pass re-reads populations the psi pass has just
  *           brought into the last-level cache.  Slab height lbm_params.slab_planes
- *           (0 = sized for about 64 MiB of population input per slab). */
-enum { LBM_SCHED_TWO_PASS = 0, LBM_SCHED_BLOCKED = 1 };
+ *           (0 = sized for about 64 MiB of population input per slab).
+ * OVERLAP : the density/EOS/psi pass slab by slab on a second stream the library
+ *           creates (default priority), each slab's collide pass on the context's
+ *           stream as soon as the psi of its slab and of the two neighbouring slabs
+ *           is done, so the memory-bound psi pass of later slabs runs beside the
+ *           arithmetic-bound collide pass of earlier ones.  Slab height as BLOCKED
+ *           (0 = one eighth of the planes). */
+enum { LBM_SCHED_TWO_PASS = 0, LBM_SCHED_BLOCKED = 1, LBM_SCHED_OVERLAP = 2 };
 
 #define LBM_MAX_NC 4
 #define LBM_MAX_Q 19
@@ -85,7 +93,7 @@ typedef struct {
   int collision;             /* LBM_BGK | LBM_MRT                               */
   int forcing;               /* LBM_GUO | LBM_EDM                               */
   int storage;               /* LBM_F64 | LBM_F32_OFS | LBM_F16_OFS             */
-  int schedule;              /* LBM_SCHED_TWO_PASS | LBM_SCHED_BLOCKED          */
+  int schedule;              /* LBM_SCHED_TWO_PASS | LBM_SCHED_BLOCKED | LBM_SCHED_OVERLAP */
   int slab_planes;           /* BLOCKED: planes per slab (0 = automatic)        */
   double T;                  /* temperature                                     */
   double tau;                /* relaxation time, > 0.5 (Sec. 2.1)               */
@@ -279,8 +287,8 @@ void lbm_batch_destroy(lbm_batch* b);
  * Discrete adjoint (reverse-mode derivative of the step).  The paper does not
  * differentiate its model; these calls give the exact derivative of the discrete
  * step of Sec. 3.4 (the transpose of its Jacobian), evaluated in float64 at the
- * stored states, for BGK collision with the exact-difference or Guo forcing (any
- * storage, lattice and nc; MRT collision returns LBM_ERR_ARG).
+ * stored states, for every collision (BGK, MRT), forcing (exact difference, Guo),
+ * storage, lattice and nc.
  * Parameters: the EOS tables aa_ij = sqrt(a_i alpha_i a_j alpha_j)(1 - k_ij) and
  * b_i of Eq. (randommixingrule) / Eq. (MCPengRobinson), chained to (k_ij, a_i, b_i)
  * with alpha_i following a_i and b_i through Tc_i (Sec. 3.2).

@@ -63,13 +63,16 @@ class AdjointSpec:
     nsteps: int
     checkpoint_every: int = 100
     storage: str = "f32"
-    forcing: str = "edm"       # "edm" or "guo" (BGK collision)
+    forcing: str = "edm"       # "edm" or "guo"
+    collision: str = "bgk"     # "bgk" or "mrt"
+    mrt_s: np.ndarray = None   # MRT relaxation rate per moment row
 
 
 def run(theta, spec: AdjointSpec):
     """(loss, x_liq, dL/dtheta) for the parameter vector theta."""
     ctx = lbm.LbmContext(mixture_with(theta, spec.mix), spec.lattice, spec.shape, spec.T, spec.tau, spec.beta,
-                         spec.gamma, spec.rho0, collision="bgk", forcing=spec.forcing, storage=spec.storage)
+                         spec.gamma, spec.rho0, collision=spec.collision, forcing=spec.forcing, storage=spec.storage,
+                         mrt_s=spec.mrt_s)
     try:
         r = ctx.adjoint(spec.nsteps, spec.checkpoint_every, spec.mask, spec.x_target)
     finally:

@@ -108,7 +108,8 @@ lbm_status validate(const lbm_mixture* mix, const lbm_params* prm) {
   if (prm->collision != LBM_BGK && prm->collision != LBM_MRT) return lbm_fail(LBM_ERR_ARG, "unknown collision");
   if (prm->forcing != LBM_GUO && prm->forcing != LBM_EDM) return lbm_fail(LBM_ERR_ARG, "unknown forcing");
   if (prm->storage < LBM_F64 || prm->storage > LBM_F16_OFS) return lbm_fail(LBM_ERR_ARG, "unknown storage");
-  if (prm->schedule != LBM_SCHED_TWO_PASS && prm->schedule != LBM_SCHED_BLOCKED)
+  if (prm->schedule != LBM_SCHED_TWO_PASS && prm->schedule != LBM_SCHED_BLOCKED &&
+      prm->schedule != LBM_SCHED_OVERLAP)
     return lbm_fail(LBM_ERR_ARG, "unknown schedule");
   if (prm->slab_planes < 0) return lbm_fail(LBM_ERR_ARG, "slab_planes must be >= 0");
   if (prm->nx < 1 || prm->ny < 1 || prm->nz < 1) return lbm_fail(LBM_ERR_ARG, "box sides must be >= 1");
@@ -147,12 +148,40 @@ lbm_status hip_check(hipError_t e, const char* what) {
 }
 
 // Enqueue one step; mark(k) runs after every psi (k = 0) / collide (k = 1) launch.
+// OVERLAP: psi slabs on the aux stream (in the order last, 0, 1, ...), each collide
+// slab on the context's stream after the psi events of slabs k-1, k, k+1; the aux
+// stream first waits for the previous step's work on the context's stream.
+void enqueue_overlap(lbm_ctx* c, const Bufs& in, const Bufs& out) {
+  const int np = c->kp.nplanes, sl = c->slab;
+  const int ns = (np + sl - 1) / sl;
+  hipEvent_t* done = c->ev;            // [ns] psi of slab k done
+  hipEvent_t boundary = c->ev[ns];
+  hipEventRecord(boundary, c->stream);
+  hipStreamWaitEvent(c->aux, boundary, 0);
+  for (int i = 0; i < ns; ++i) {
+    const int k = (i == 0) ? ns - 1 : i - 1;
+    const int p0 = k * sl, n = std::min(sl, np - p0);
+    c->ops.psi(c->kp, in, c->sc, p0, n, c->aux);
+    hipEventRecord(done[k], c->aux);
+  }
+  for (int k = 0; k < ns; ++k) {
+    hipStreamWaitEvent(c->stream, done[(k + ns - 1) % ns], 0);
+    hipStreamWaitEvent(c->stream, done[k], 0);
+    hipStreamWaitEvent(c->stream, done[(k + 1) % ns], 0);
+    const int p0 = k * sl, n = std::min(sl, np - p0);
+    c->ops.collide(c->kp, in, out, c->sc, p0, n, c->stream);
+  }
+}
+
 template <typename Mark>
 void enqueue_step(lbm_ctx* c, Mark mark) {
   const Bufs& in = c->pops[c->cur];
   const Bufs& out = c->pops[1 - c->cur];
   const int np = c->kp.nplanes;
-  if (c->prm.schedule == LBM_SCHED_TWO_PASS || c->slab >= np) {
+  if (c->prm.schedule == LBM_SCHED_OVERLAP && c->aux) {
+    enqueue_overlap(c, in, out);
+    mark(1);
+  } else if (c->prm.schedule == LBM_SCHED_TWO_PASS || c->slab >= np) {
     c->ops.psi(c->kp, in, c->sc, 0, np, c->stream);
     mark(0);
     c->ops.collide(c->kp, in, out, c->sc, 0, np, c->stream);
@@ -172,6 +201,7 @@ void enqueue_step(lbm_ctx* c, Mark mark) {
 
 int launches_per_step(const lbm_ctx* c) {
   const int np = c->kp.nplanes;
+  if (c->prm.schedule == LBM_SCHED_OVERLAP && c->aux) return 1;
   if (c->prm.schedule == LBM_SCHED_TWO_PASS || c->slab >= np) return 2;
   return 2 * ((np + c->slab - 1) / c->slab);
 }
@@ -249,10 +279,12 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
   kp.err = c->err;
   c->ops = prm->lattice == LBM_D2Q9 ? ops_d2q9(mix->nc, prm->storage, prm->collision, prm->forcing)
                                     : ops_d3q19(mix->nc, prm->storage, prm->collision, prm->forcing);
-  c->adj = prm->lattice == LBM_D2Q9 ? adj_ops_d2q9(mix->nc, prm->storage, prm->forcing)
-                                    : adj_ops_d3q19(mix->nc, prm->storage, prm->forcing);
+  c->adj = prm->lattice == LBM_D2Q9 ? adj_ops_d2q9(mix->nc, prm->storage, prm->collision, prm->forcing)
+                                    : adj_ops_d3q19(mix->nc, prm->storage, prm->collision, prm->forcing);
   if (prm->slab_planes > 0) {
     c->slab = prm->slab_planes;
+  } else if (prm->schedule == LBM_SCHED_OVERLAP) {
+    c->slab = std::max(1, (kp.nplanes + 7) / 8);
   } else {
     // about 64 MiB of population input (+ base) per slab
     const double plane_bytes = (double)kp.plane_cells * mix->nc *
@@ -260,6 +292,22 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
     c->slab = std::max(1, (int)((64.0 * 1048576.0) / plane_bytes));
   }
 
+  if (prm->schedule == LBM_SCHED_OVERLAP) {
+    const int ns = (kp.nplanes + c->slab - 1) / c->slab;
+    st = hip_check(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking), "create overlap stream");
+    if (st == LBM_OK) {
+      c->ev = new (std::nothrow) hipEvent_t[ns + 1];
+      if (!c->ev) st = lbm_fail(LBM_ERR_ARG, "out of host memory");
+    }
+    for (int k = 0; st == LBM_OK && k <= ns; ++k) {
+      st = hip_check(hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming), "create overlap event");
+      if (st == LBM_OK) c->nev = k + 1;
+    }
+    if (st != LBM_OK) {
+      delete c;
+      return st;
+    }
+  }
   st = hip_check(hipMemsetAsync(c->err, 0, sizeof(int), c->stream), "hipMemsetAsync(err)");
   if (st != LBM_OK) {
     delete c;

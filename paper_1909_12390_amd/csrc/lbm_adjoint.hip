@@ -133,8 +133,6 @@ lbm_status copy_state(const lbm_ctx* c, const Bufs& dst, const Bufs& src, const 
 
 lbm_status supported(const lbm_ctx* c) {
   if (!c) return lbm_fail(LBM_ERR_ARG, "ctx is NULL");
-  if (c->prm.collision != LBM_BGK)
-    return lbm_fail(LBM_ERR_ARG, "the adjoint supports BGK collision (exact-difference or Guo forcing)");
   return LBM_OK;
 }
 

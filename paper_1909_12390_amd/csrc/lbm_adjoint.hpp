@@ -1,4 +1,4 @@
-// Discrete adjoint of one step (BGK collision with the exact-difference or Guo forcing),
+// Discrete adjoint of one step (BGK or MRT collision, exact-difference or Guo forcing),
 // i.e. the transpose of the step's Jacobian applied to the adjoint of the
 // post-streaming populations after the step, plus the step's contribution to the
 // derivative with respect to the EOS tables (a alpha)_ij (1 - k_ij) and b_i.
@@ -40,6 +40,12 @@
 //   rbar^_s   = omega Phi_s(u) + gamma_s (F^_s.F)/Gamma - gamma_s (sum_t chi_t F^_t.F)/Gamma
 //               + F^_s.g - u^.(u - g/2)/rho + [EOS, psi terms]
 //
+// MRT: f* = feq(u) + (1 - h) src + K (f - feq(u) + h src) with the symmetric
+// K = M^-1 (I - S) M = sum_k (1 - s_k)/|M_k|^2 M_k M_k^T (BGK: K = (1 - omega) I).
+// With g = K hs the adjoint of f is g (instead of (1 - omega) hs), and every
+// equilibrium / source term above takes the moments of the vector that multiplies
+// it: EDM  feq(u): -g, feq(v): hs;   Guo  feq(u): hs - g, src: (hs + g)/2.
+//
 // Two passes per step: ka_cell (everything local to x, writes F^, j^, the local
 // part of rbar^ and rbar) and kb_cell (the transposed psi stencil, the EOS adjoint,
 // the output and the parameter partials).  psi of the state comes from k_psi.
@@ -56,7 +62,125 @@ struct AdjScratch {
   double* rb;      // [NC] rbar of the state
 };
 
-template <int LAT, int NC, int ST, int FORC>
+// out = K in for the collision operator (BGK: (1 - omega) in; MRT: pair-based
+// transform over the rows with (1 - s_k) != 0, as in collide_values)
+template <int LAT, int COLL>
+__device__ __forceinline__ void apply_K(const KParams& P, const double* in, double* out) {
+  using V = VS<LAT>;
+  constexpr int Q = V::Q;
+  constexpr int NP = (Q - 1) / 2;
+  if constexpr (COLL == LBM_BGK) {
+    const double k = 1.0 - P.omega;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) out[a] = k * in[a];
+  } else {
+    double Sp[NP], Dp[NP], accE[NP], accO[NP], acc0 = 0.0;
+    static_for<0, NP>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
+      Sp[p] = in[a] + in[b];
+      Dp[p] = in[a] - in[b];
+      accE[p] = 0.0;
+      accO[p] = 0.0;
+    });
+    // the density row is left out, as in the forward collision (its term vanishes
+    // there because sum_a d_a = 0; here its two contributions would cancel)
+    static_for<1, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      const double ck = P.mrt_c[k];
+      double m = 0.0;
+      if constexpr (!row_odd<LAT>(k)) {
+        if constexpr (V::mrow(k, 0) != 0.0) m += V::mrow(k, 0) * in[0];
+        static_for<0, NP>([&](auto Pp) {
+          constexpr int p = decltype(Pp)::value;
+          constexpr double mk = V::mrow(k, V::pair_first(p));
+          if constexpr (mk != 0.0) m += mk * Sp[p];
+        });
+      } else {
+        static_for<0, NP>([&](auto Pp) {
+          constexpr int p = decltype(Pp)::value;
+          constexpr double mk = V::mrow(k, V::pair_first(p));
+          if constexpr (mk != 0.0) m += mk * Dp[p];
+        });
+      }
+      m *= ck;
+      if constexpr (!row_odd<LAT>(k) && V::mrow(k, 0) != 0.0) acc0 += V::mrow(k, 0) * m;
+      static_for<0, NP>([&](auto Pp) {
+        constexpr int p = decltype(Pp)::value;
+        constexpr double mk = V::mrow(k, V::pair_first(p));
+        if constexpr (mk != 0.0) {
+          if constexpr (row_odd<LAT>(k)) accO[p] += mk * m;
+          else accE[p] += mk * m;
+        }
+      });
+    });
+    out[0] = acc0;
+    static_for<0, NP>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
+      out[a] = accE[p] + accO[p];
+      out[b] = accE[p] - accO[p];
+    });
+  }
+}
+
+// w-weighted moments of a population-shaped vector: A0 = sum w v, A1 = sum w e v,
+// A2 = sum w e e v (xx yy zz xy xz yz)
+struct WMom {
+  double A0, A1[3], A2[6];
+};
+template <int LAT>
+__device__ __forceinline__ WMom wmoments(const double* v) {
+  using V = VS<LAT>;
+  WMom m = {0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+  for (int a = 0; a < V::Q; ++a) {
+    const double w = V::w(a) * v[a];
+    const int ex = V::cx(a), ey = V::cy(a), ez = V::cz(a);
+    m.A0 += w;
+    if (ex) m.A1[0] += ex * w;
+    if (ey) m.A1[1] += ey * w;
+    if (ez) m.A1[2] += ez * w;
+    if (ex) m.A2[0] += w;
+    if (ey) m.A2[1] += w;
+    if (ez) m.A2[2] += w;
+    if (ex * ey) m.A2[3] += ex * ey * w;
+    if (ex * ez) m.A2[4] += ex * ez * w;
+    if (ey * ez) m.A2[5] += ey * ez * w;
+  }
+  return m;
+}
+__device__ __forceinline__ WMom wcomb(const WMom& a, double ca, const WMom& b, double cb) {
+  WMom m;
+  m.A0 = ca * a.A0 + cb * b.A0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) m.A1[d] = ca * a.A1[d] + cb * b.A1[d];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) m.A2[d] = ca * a.A2[d] + cb * b.A2[d];
+  return m;
+}
+__device__ __forceinline__ void wA2v(const WMom& m, const double* v, double* out) {
+  out[0] = m.A2[0] * v[0] + m.A2[3] * v[1] + m.A2[4] * v[2];
+  out[1] = m.A2[3] * v[0] + m.A2[1] * v[1] + m.A2[5] * v[2];
+  out[2] = m.A2[4] * v[0] + m.A2[5] * v[1] + m.A2[2] * v[2];
+}
+// Phi(v) = A0 (1 - 3/2 v.v) + 3 A1.v + 9/2 v.A2.v   (sum_a x_a feq_a(r, v) = r Phi(v))
+__device__ __forceinline__ double wphi(const WMom& m, const double* v) {
+  double Av[3];
+  wA2v(m, v, Av);
+  const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  return m.A0 * (1.0 - 1.5 * vv) + 3.0 * (m.A1[0] * v[0] + m.A1[1] * v[1] + m.A1[2] * v[2]) +
+         4.5 * (v[0] * Av[0] + v[1] * Av[1] + v[2] * Av[2]);
+}
+// gPhi(v) = d Phi / d v = -3 A0 v + 3 A1 + 9 A2 v
+__device__ __forceinline__ void wgphi(const WMom& m, const double* v, double* out) {
+  double Av[3];
+  wA2v(m, v, Av);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) out[d] = -3.0 * m.A0 * v[d] + 3.0 * m.A1[d] + 9.0 * Av[d];
+}
+
+template <int LAT, int NC, int ST, int COLL, int FORC>
 __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, const double* __restrict__ psi,
                                                  const double* __restrict__ h, AdjScratch S) {
   using V = VS<LAT>;
@@ -95,50 +219,17 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
 #pragma unroll
   for (int d = 0; d < 3; ++d)
     u[d] = (FORC == LBM_GUO) ? (j[d] + 0.5 * (F[d] + rho * g[d])) * irho : j[d] * irho;
-  const double om = P.omega;
-  const double gk = 1.0 - 0.5 * om;   // Guo source prefactor
   double ub[3] = {0.0, 0.0, 0.0}, Fb[3] = {0.0, 0.0, 0.0}, Gb = 0.0;
   double rbA[NC], FbF[NC];
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
-    // moments of the adjoint of f* (gathered from the downstream neighbours)
-    double A0 = 0.0, A1[3] = {0.0, 0.0, 0.0}, A2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // xx yy zz xy xz yz
+    // the adjoint of f* (gathered from the downstream neighbours) and K applied to it
+    double hv[Q], kv[Q];
     const double* hs = h + (size_t)s * Q * N;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const double w = V::w(a) * hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))];
-      const int ex = V::cx(a), ey = V::cy(a), ez = V::cz(a);
-      A0 += w;
-      if (ex) A1[0] += ex * w;
-      if (ey) A1[1] += ey * w;
-      if (ez) A1[2] += ez * w;
-      if (ex) A2[0] += w;
-      if (ey) A2[1] += w;
-      if (ez) A2[2] += w;
-      if (ex * ey) A2[3] += ex * ey * w;
-      if (ex * ez) A2[4] += ex * ez * w;
-      if (ey * ez) A2[5] += ey * ez * w;
-    }
-    auto A2v = [&](const double* v, double* out) {
-      out[0] = A2[0] * v[0] + A2[3] * v[1] + A2[4] * v[2];
-      out[1] = A2[3] * v[0] + A2[1] * v[1] + A2[5] * v[2];
-      out[2] = A2[4] * v[0] + A2[5] * v[1] + A2[2] * v[2];
-    };
-    auto phi = [&](const double* w) {
-      double Aw[3];
-      A2v(w, Aw);
-      const double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-      return A0 * (1.0 - 1.5 * ww) + 3.0 * (A1[0] * w[0] + A1[1] * w[1] + A1[2] * w[2]) +
-             4.5 * (w[0] * Aw[0] + w[1] * Aw[1] + w[2] * Aw[2]);
-    };
-    auto gphi = [&](const double* w, double* out) {
-      double Aw[3];
-      A2v(w, Aw);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) out[d] = -3.0 * A0 * w[d] + 3.0 * A1[d] + 9.0 * Aw[d];
-    };
-    double gu[3];
-    gphi(u, gu);
+    for (int a = 0; a < Q; ++a) hv[a] = hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))];
+    apply_K<LAT, COLL>(P, hv, kv);
+    const WMom A = wmoments<LAT>(hv), B = wmoments<LAT>(kv);
     if constexpr (FORC == LBM_EDM) {
       double duF[3], v[3];
 #pragma unroll
@@ -146,43 +237,48 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
         duF[d] = P.gamma[s] * F[d] * iG;
         v[d] = u[d] + duF[d] + g[d];
       }
-      double gv[3];
-      gphi(v, gv);
-      rbA[s] = (om - 1.0) * phi(u) + phi(v);
+      double gAv[3], gBu[3];
+      wgphi(A, v, gAv);
+      wgphi(B, u, gBu);
+      rbA[s] = wphi(A, v) - wphi(B, u);
       double dub[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        ub[d] += rb[s] * ((om - 1.0) * gu[d] + gv[d]);
-        dub[d] = rb[s] * gv[d];
+        ub[d] += rb[s] * (gAv[d] - gBu[d]);
+        dub[d] = rb[s] * gAv[d];
         Fb[d] += P.gamma[s] * iG * dub[d];
       }
       Gb -= (duF[0] * dub[0] + duF[1] * dub[1] + duF[2] * dub[2]) * iG;
       FbF[s] = 0.0;
     } else {
+      const WMom E = wcomb(A, 1.0, B, -1.0);     // multiplies feq(u)
+      const WMom C = wcomb(A, 0.5, B, 0.5);      // multiplies the source
       const double chi = P.gamma[s] * rb[s] * iG;
-      double Fs[3], AF[3];
+      double Fs[3], CF[3], gE[3], gC[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) Fs[d] = chi * F[d] + rb[s] * g[d];
-      A2v(Fs, AF);
-      rbA[s] = om * phi(u);
+      wA2v(C, Fs, CF);
+      wgphi(E, u, gE);
+      wgphi(C, u, gC);
+      rbA[s] = wphi(E, u);
       double fbs_F = 0.0, fbs_g = 0.0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double Fbs = gk * gu[d];               // adjoint of F_s
-        ub[d] += om * rb[s] * gu[d] + gk * (9.0 * AF[d] - 3.0 * A0 * Fs[d]);
+        const double Fbs = gC[d];                  // adjoint of F_s
+        ub[d] += rb[s] * gE[d] + (9.0 * CF[d] - 3.0 * C.A0 * Fs[d]);
         Fb[d] += chi * Fbs;
         fbs_F += Fbs * F[d];
         fbs_g += Fbs * g[d];
       }
       rbA[s] += P.gamma[s] * fbs_F * iG + fbs_g;
-      FbF[s] = chi * fbs_F;                          // chi_s F^_s . F
+      FbF[s] = chi * fbs_F;                        // chi_s F^_s . F
     }
   }
   if constexpr (FORC == LBM_GUO) {
     double cs = 0.0;
 #pragma unroll
     for (int s = 0; s < NC; ++s) cs += FbF[s];
-    Gb = -cs * iG;                                   // d/d Gamma through chi_s = gamma_s rbar_s / Gamma
+    Gb = -cs * iG;                                 // d/d Gamma through chi_s = gamma_s rbar_s / Gamma
 #pragma unroll
     for (int d = 0; d < 3; ++d) Fb[d] += 0.5 * ub[d] * irho;
   }
@@ -204,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
 
 // Parameter partials per block, added to a running per-block accumulator:
 // [dL/daa_ij (NC*NC, ordered pairs), dL/db_i (NC)].
-template <int LAT, int NC>
+template <int LAT, int NC, int COLL>
 __global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __restrict__ psi,
                                                  const double* __restrict__ h, AdjScratch S,
                                                  double* __restrict__ hout, double* __restrict__ partials) {
@@ -266,15 +362,18 @@ __global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __res
       vals[NC * NC + i] = pbar * n[i] * dpdB;
     }
     const double jb[3] = {S.jbar[cell], S.jbar[N + cell], D == 3 ? S.jbar[2 * N + cell] : 0.0};
-    const double keep = 1.0 - P.omega;
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
       const double* hs = h + (size_t)s * Q * N;
       double* ho = hout + (size_t)s * Q * N;
+      double hv[Q], kv[Q];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) hv[a] = hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))];
+      apply_K<LAT, COLL>(P, hv, kv);
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const double ej = V::cx(a) * jb[0] + V::cy(a) * jb[1] + V::cz(a) * jb[2];
-        ho[(size_t)a * N + cell] = keep * hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))] + ej + rbar[s];
+        ho[(size_t)a * N + cell] = kv[a] + ej + rbar[s];
       }
     }
   }

@@ -29,4 +29,13 @@ struct lbm_ctx {
   double* totals;
   int* err;
   int cur;
+  // OVERLAP schedule: second stream and one event per slab (+ the step boundary)
+  hipStream_t aux;
+  hipEvent_t* ev;
+  int nev;
+  ~lbm_ctx() {
+    for (int k = 0; k < nev; ++k) hipEventDestroy(ev[k]);
+    delete[] ev;
+    if (aux) hipStreamDestroy(aux);
+  }
 };

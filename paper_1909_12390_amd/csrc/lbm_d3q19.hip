@@ -3,5 +3,5 @@
 
 namespace lbmk {
 Ops ops_d3q19(int nc, int st, int coll, int forc) { return ops_lat<LBM_D3Q19>(nc, st, coll, forc); }
-AdjOps adj_ops_d3q19(int nc, int st, int forc) { return adj_ops_lat<LBM_D3Q19>(nc, st, forc); }
+AdjOps adj_ops_d3q19(int nc, int st, int coll, int forc) { return adj_ops_lat<LBM_D3Q19>(nc, st, coll, forc); }
 }  // namespace lbmk

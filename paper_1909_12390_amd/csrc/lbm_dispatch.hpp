@@ -109,8 +109,8 @@ Ops ops_lat(int nc, int st, int coll, int forc) {
   }
 }
 
-// Launchers of the adjoint passes (BGK collision; exact-difference or Guo forcing)
-// and of the loss helpers, per (lattice, nc, storage, forcing).
+// Launchers of the adjoint passes and of the loss helpers, per (lattice, nc,
+// storage, collision, forcing).
 struct AdjOps {
   void (*a)(const KParams&, const Bufs& state, const double* psi, const double* h, const AdjScratch&, hipStream_t);
   void (*b)(const KParams&, const double* psi, const double* h, const AdjScratch&, double* hout, double* partials,
@@ -119,16 +119,16 @@ struct AdjOps {
   void (*seed)(const KParams&, const unsigned char* mask, const double* coef, double* h, hipStream_t);
 };
 
-template <int LAT, int NC, int ST, int FORC>
+template <int LAT, int NC, int ST, int COLL, int FORC>
 struct AdjOpsImpl {
   static void a(const KParams& P, const Bufs& state, const double* psi, const double* h, const AdjScratch& S,
                 hipStream_t st) {
-    hipLaunchKernelGGL((ka_cell<LAT, NC, ST, FORC>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
+    hipLaunchKernelGGL((ka_cell<LAT, NC, ST, COLL, FORC>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
                        make_pops<ST>(state), psi, h, S);
   }
   static void b(const KParams& P, const double* psi, const double* h, const AdjScratch& S, double* hout,
                 double* partials, hipStream_t st) {
-    hipLaunchKernelGGL((kb_cell<LAT, NC>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P, psi, h, S, hout,
+    hipLaunchKernelGGL((kb_cell<LAT, NC, COLL>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P, psi, h, S, hout,
                        partials);
   }
   static void moles(const KParams& P, const Bufs& state, const unsigned char* mask, double* partials,
@@ -144,33 +144,37 @@ struct AdjOpsImpl {
 };
 
 template <int LAT, int NC, int ST>
-AdjOps adj_ops_f(int forc) {
-  return forc == LBM_GUO ? AdjOpsImpl<LAT, NC, ST, LBM_GUO>::ops() : AdjOpsImpl<LAT, NC, ST, LBM_EDM>::ops();
+AdjOps adj_ops_cf(int coll, int forc) {
+  if (coll == LBM_BGK)
+    return forc == LBM_GUO ? AdjOpsImpl<LAT, NC, ST, LBM_BGK, LBM_GUO>::ops()
+                           : AdjOpsImpl<LAT, NC, ST, LBM_BGK, LBM_EDM>::ops();
+  return forc == LBM_GUO ? AdjOpsImpl<LAT, NC, ST, LBM_MRT, LBM_GUO>::ops()
+                         : AdjOpsImpl<LAT, NC, ST, LBM_MRT, LBM_EDM>::ops();
 }
 
 template <int LAT, int NC>
-AdjOps adj_ops_st(int st, int forc) {
+AdjOps adj_ops_st(int st, int coll, int forc) {
   switch (st) {
-    case LBM_F64: return adj_ops_f<LAT, NC, LBM_F64>(forc);
-    case LBM_F32_OFS: return adj_ops_f<LAT, NC, LBM_F32_OFS>(forc);
-    default: return adj_ops_f<LAT, NC, LBM_F16_OFS>(forc);
+    case LBM_F64: return adj_ops_cf<LAT, NC, LBM_F64>(coll, forc);
+    case LBM_F32_OFS: return adj_ops_cf<LAT, NC, LBM_F32_OFS>(coll, forc);
+    default: return adj_ops_cf<LAT, NC, LBM_F16_OFS>(coll, forc);
   }
 }
 
 template <int LAT>
-AdjOps adj_ops_lat(int nc, int st, int forc) {
+AdjOps adj_ops_lat(int nc, int st, int coll, int forc) {
   switch (nc) {
-    case 1: return adj_ops_st<LAT, 1>(st, forc);
-    case 2: return adj_ops_st<LAT, 2>(st, forc);
-    case 3: return adj_ops_st<LAT, 3>(st, forc);
-    default: return adj_ops_st<LAT, 4>(st, forc);
+    case 1: return adj_ops_st<LAT, 1>(st, coll, forc);
+    case 2: return adj_ops_st<LAT, 2>(st, coll, forc);
+    case 3: return adj_ops_st<LAT, 3>(st, coll, forc);
+    default: return adj_ops_st<LAT, 4>(st, coll, forc);
   }
 }
 
 // defined in lbm_d2q9.hip / lbm_d3q19.hip
 Ops ops_d2q9(int nc, int st, int coll, int forc);
 Ops ops_d3q19(int nc, int st, int coll, int forc);
-AdjOps adj_ops_d2q9(int nc, int st, int forc);
-AdjOps adj_ops_d3q19(int nc, int st, int forc);
+AdjOps adj_ops_d2q9(int nc, int st, int coll, int forc);
+AdjOps adj_ops_d3q19(int nc, int st, int coll, int forc);
 
 }  // namespace lbmk

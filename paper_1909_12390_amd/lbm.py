@@ -25,7 +25,7 @@ LATTICES = {"D2Q9": 0, "D3Q19": 1}
 COLLISIONS = {"bgk": 0, "mrt": 1}
 FORCINGS = {"guo": 0, "edm": 1}
 STORAGES = {"f64": 0, "f32": 1, "f16": 2}
-SCHEDULES = {"two_pass": 0, "blocked": 1}
+SCHEDULES = {"two_pass": 0, "blocked": 1, "overlap": 2}
 MAX_NC = 4
 MAX_Q = 19
 Q_OF = {"D2Q9": 9, "D3Q19": 19}

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1909_12390_amd import lbm
@@ -73,3 +74,45 @@ def test_host_validation_rejects_asymmetric_k_and_bad_nc():
 def test_mrt_rates_checked():
     assert _bytes(collision="mrt", mrt_s=[1.0] * 9)[0] == lbm.LBM_OK
     assert _bytes(collision="mrt", mrt_s=[1.0] * 8 + [2.5])[0] == lbm.LBM_ERR_ARG
+
+
+def _batch_layout(nboxes=2, tile=0, grid=0, graph_steps=0, nc=2, lattice="D2Q9", shape=(8, 16), gamma=None):
+    n = nboxes
+    arr = (lbm.LbmBox * max(n, 1))()
+    for i in range(n):
+        m = _mix()
+        arr[i].mix = lbm.mixture_struct(m)
+        arr[i].nx, arr[i].ny, arr[i].nz = shape[1], shape[0], 1
+        arr[i].T, arr[i].tau, arr[i].G, arr[i].beta = 0.06, 0.8, -1.0, 1.16
+        for k, g in enumerate(gamma if gamma is not None else [0.5, 1.0]):
+            arr[i].gamma[k] = g
+    prm = lbm.LbmBatchParams()
+    prm.lattice = lbm.LATTICES[lattice]
+    prm.collision, prm.forcing, prm.storage = 0, 1, 2
+    prm.tile, prm.grid, prm.graph_steps = tile, grid, graph_steps
+    ws, fe, pe = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
+    code = lbm.lib().lbm_batch_layout(arr, n, ctypes.byref(prm), ctypes.byref(ws), ctypes.byref(fe),
+                                      ctypes.byref(pe))
+    return code, ws.value, fe.value, pe.value
+
+
+def test_batch_layout_counts_and_validation():
+    code, ws, fe, pe = _batch_layout(nboxes=3)
+    assert code == lbm.LBM_OK
+    assert fe == 3 * 2 * 8 * 16 and pe == 9 * fe
+    assert ws >= pe * 2 * 2 + fe * 4 * 2          # two f16 offset copies + float32 bases
+    for bad in (dict(tile=512), dict(tile=100), dict(grid=-1), dict(graph_steps=-2), dict(nboxes=0),
+                dict(gamma=[0.0, 1.0]), dict(gamma=[1.5, 1.0]), dict(lattice="D2Q9", shape=(0, 16))):
+        assert _batch_layout(**bad)[0] == lbm.LBM_ERR_ARG, bad
+        assert len(lbm.lib().lbm_last_error()) > 0
+
+
+def test_eos_param_grad_validates():
+    m = lbm.mixture_struct(_mix())
+    z = np.zeros(4)
+    out = np.zeros(4)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    assert lbm.lib().lbm_eos_param_grad(ctypes.byref(m), -1.0, dp(z), dp(z), dp(out), dp(out), dp(out)) \
+        == lbm.LBM_ERR_ARG
+    assert lbm.lib().lbm_eos_param_grad(ctypes.byref(m), 0.05, None, dp(z), dp(out), dp(out), dp(out)) \
+        == lbm.LBM_ERR_ARG

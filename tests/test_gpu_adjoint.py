@@ -15,7 +15,7 @@ oracle's discrete adjoint and against central differences of the GPU forward.
 import numpy as np
 import pytest
 
-from cases import LAT, case, oracle_params
+from cases import LAT, case, mrt_rates, oracle_params
 from oracle import adjoint as oadj
 from oracle import lbm as olbm
 from oracle_backend import BACKEND, to_mixture
@@ -30,22 +30,26 @@ def _lbm():
     return lbm
 
 
-def context(c, lattice, storage="f64", beta=1.16, tau=0.8, forcing="edm", accel=None):
+def context(c, lattice, storage="f64", beta=1.16, tau=0.8, forcing="edm", accel=None, collision="bgk",
+            mrt_s=None):
     return _lbm().LbmContext(c["mix"], lattice, c["shape"], c["T"], tau, beta, c["gamma"], c["rho0"],
-                             collision="bgk", forcing=forcing, storage=storage, accel=accel)
+                             collision=collision, forcing=forcing, storage=storage, accel=accel, mrt_s=mrt_s)
 
 
-@pytest.mark.parametrize("forcing,accel", [("edm", None), ("guo", None), ("guo", (2e-5, -1e-5, 3e-6))])
+@pytest.mark.parametrize("collision,forcing,accel", [("bgk", "edm", None), ("bgk", "guo", None),
+                                                     ("bgk", "guo", (2e-5, -1e-5, 3e-6)), ("mrt", "edm", None),
+                                                     ("mrt", "guo", (1e-5, 2e-5, -1e-5))])
 @pytest.mark.parametrize("lattice,nc,shape", [("D2Q9", 3, (12, 14)), ("D2Q9", 1, (10, 9)), ("D2Q9", 4, (9, 11)),
                                               ("D3Q19", 2, (5, 6, 7))])
-def test_step_adjoint_matches_oracle(lattice, nc, shape, forcing, accel):
-    print(f"case step adjoint {lattice} nc={nc} {shape} {forcing} accel={accel}", flush=True)
+def test_step_adjoint_matches_oracle(lattice, nc, shape, collision, forcing, accel):
+    print(f"case step adjoint {lattice} nc={nc} {shape} {collision} {forcing} accel={accel}", flush=True)
     c = case(lattice, nc, shape, seed=1, u_amp=0.01)
     c["u0"] = None
     D = 2 if lattice == "D2Q9" else 3
     acc = None if accel is None else np.asarray(accel[:D])
     beta = 1.16 if forcing == "edm" else 1.7
-    ctx = context(c, lattice, forcing=forcing, beta=beta, accel=acc)
+    rates = mrt_rates(lattice, 0.8) if collision == "mrt" else None
+    ctx = context(c, lattice, forcing=forcing, beta=beta, accel=acc, collision=collision, mrt_s=rates)
     ctx.step(3)
     f = ctx.get_populations().cpu().numpy()
     h = np.random.default_rng(5).standard_normal(f.shape)
@@ -53,7 +57,7 @@ def test_step_adjoint_matches_oracle(lattice, nc, shape, forcing, accel):
     ctx.check()
     assert np.array_equal(ctx.get_populations().cpu().numpy(), f)   # state untouched
     base = to_mixture(c["mix"])
-    prm = oracle_params(c, "bgk", forcing, tau=0.8, beta=beta, accel=acc)
+    prm = oracle_params(c, collision, forcing, tau=0.8, beta=beta, accel=acc, mrt_s=rates)
     aa, b = oadj.eos_tables(torch.as_tensor(oadj.theta_of(base), dtype=oadj.DT), base, c["T"])
     gf, gaa, gb = oadj.step_vjp_tables(f, h, aa.numpy(), b.numpy(), base, prm, LAT[lattice])
     assert np.max(np.abs(hout.cpu().numpy() - gf)) <= 1e-11 * np.max(np.abs(gf))
@@ -71,25 +75,28 @@ def small_problem(seed=2, shape=(12, 14), nsteps=12):
     return c, mask, base, f0, x_tgt, nsteps
 
 
-def gpu_gradient(c, mask, x_tgt, nsteps, K, storage="f64", forcing="edm"):
+def gpu_gradient(c, mask, x_tgt, nsteps, K, storage="f64", forcing="edm", collision="bgk"):
     from paper_1909_12390_amd import adjoint as padj
-    ctx = context(c, "D2Q9", storage, forcing=forcing, beta=1.16 if forcing == "edm" else 1.7)
+    rates = mrt_rates("D2Q9", 0.8) if collision == "mrt" else None
+    ctx = context(c, "D2Q9", storage, forcing=forcing, beta=1.16 if forcing == "edm" else 1.7, collision=collision,
+                  mrt_s=rates)
     r = ctx.adjoint(nsteps, K, mask, x_tgt)
     ctx.close()
     return r, padj.pack_gradient(r["d_k"], r["d_a"], r["d_b"])
 
 
-@pytest.mark.parametrize("forcing", ["edm", "guo"])
-def test_gradient_run_matches_oracle_gradient(forcing):
-    print(f"case adjoint run vs oracle {forcing}", flush=True)
+@pytest.mark.parametrize("collision,forcing", [("bgk", "edm"), ("bgk", "guo"), ("mrt", "edm")])
+def test_gradient_run_matches_oracle_gradient(collision, forcing):
+    print(f"case adjoint run vs oracle {collision} {forcing}", flush=True)
     c, mask, base, f0, x_tgt, nsteps = small_problem()
-    prm = oracle_params(c, "bgk", forcing, tau=0.8, beta=1.16 if forcing == "edm" else 1.7)
+    rates = mrt_rates("D2Q9", 0.8) if collision == "mrt" else None
+    prm = oracle_params(c, collision, forcing, tau=0.8, beta=1.16 if forcing == "edm" else 1.7, mrt_s=rates)
     L, g = oadj.gradient(oadj.theta_of(base), f0, base, prm, LAT["D2Q9"], nsteps, mask, x_tgt)
-    r, gg = gpu_gradient(c, mask, x_tgt, nsteps, K=5, forcing=forcing)
+    r, gg = gpu_gradient(c, mask, x_tgt, nsteps, K=5, forcing=forcing, collision=collision)
     assert abs(r["loss"] - L) <= 1e-11 * L
     assert np.max(np.abs(gg - g)) <= 1e-9 * np.max(np.abs(g))
     # float32 storage: same gradient to the precision of the stored states
-    r32, g32 = gpu_gradient(c, mask, x_tgt, nsteps, K=5, storage="f32", forcing=forcing)
+    r32, g32 = gpu_gradient(c, mask, x_tgt, nsteps, K=5, storage="f32", forcing=forcing, collision=collision)
     assert np.max(np.abs(g32 - g)) <= 1e-4 * np.max(np.abs(g))
 
 

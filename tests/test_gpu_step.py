@@ -180,15 +180,16 @@ def test_reduced_precision_step_close_to_oracle(lattice, storage, tol1, tol10, c
 @pytest.mark.parametrize("lattice,shape,slab", [("D2Q9", (45, 70), 7), ("D3Q19", (13, 14, 15), 4),
                                                 ("D3Q19", (13, 14, 15), 1)])
 @pytest.mark.parametrize("storage", ["f64", "f16"])
-def test_blocked_schedule_equals_two_pass(lattice, shape, slab, storage):
-    # same arithmetic, different launch order: bitwise identical states
-    print(f"case blocked {lattice} slab={slab} {storage}", flush=True)
+@pytest.mark.parametrize("schedule", ["blocked", "overlap"])
+def test_blocked_schedule_equals_two_pass(lattice, shape, slab, storage, schedule):
+    # same arithmetic, different launch order (and streams): bitwise identical states
+    print(f"case {schedule} {lattice} slab={slab} {storage}", flush=True)
     c = case(lattice, 3, shape, seed=9, u_amp=0.01)
     rates = mrt_rates(lattice, 0.8)
     a = gpu_context(c, lattice, "mrt", "edm", storage=storage, mrt_s=rates, beta=1.16)
     lbm = _lbm()
     b = lbm.LbmContext(c["mix"], lattice, c["shape"], c["T"], 0.8, 1.16, c["gamma"], c["rho0"], c["u0"],
-                       collision="mrt", forcing="edm", storage=storage, schedule="blocked", mrt_s=rates,
+                       collision="mrt", forcing="edm", storage=storage, schedule=schedule, mrt_s=rates,
                        slab_planes=slab)
     a.step(7)
     b.step(7)
