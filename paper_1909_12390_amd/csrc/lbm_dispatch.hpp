@@ -58,7 +58,9 @@ struct OpsImpl {
   }
   static void collide(const KParams& P, const Bufs& in, const Bufs& out, const StepScratch& sc, int plane0,
                       int np, hipStream_t st) {
-    const int nb = (int)xcd_grid((np * P.plane_cells + kCells - 1) / kCells);
+    // one workgroup per 64-cell segment of a row (y, z) of the slab
+    const int rows = np * (VS<LAT>::D == 3 ? P.ny : 1);
+    const int nb = (int)xcd_grid(rows * ((P.nx + kCells - 1) / kCells));
     hipLaunchKernelGGL((k_collide<LAT, NC, ST, COLL, FORC>), dim3(nb), dim3(kCells * NC), 0, st, P,
                        make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
   }

@@ -100,6 +100,16 @@ struct Pops<LBM_F64> {
 #pragma unroll
       for (int a = 0; a < Q; ++a) bstore(rf, idx * 8u, (unsigned)a * plane, v[a]);
     }
+    // row-structured forms: per-lane offset xo within the row, wave-uniform row
+    // offset ro (in cells) folded into the scalar offset of the buffer instruction
+    __device__ __forceinline__ double get_row(int a, unsigned xo, unsigned ro, double) const {
+      return bload(rf, xo * 8u, (unsigned)a * plane + ro * 8u, 0.0);
+    }
+    template <int Q, typename W>
+    __device__ __forceinline__ void put_all_row(unsigned xo, unsigned ro, const double* v, double, W) const {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) bstore(rf, xo * 8u, (unsigned)a * plane + ro * 8u, v[a]);
+    }
   };
   __device__ __forceinline__ View comp(int s, int Q, int cells) const {
     const unsigned plane = (unsigned)cells * 8u;
@@ -117,6 +127,10 @@ struct OffsetPops {
     unsigned plane;   // bytes per direction plane of r
     __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
       return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
+    }
+    __device__ __forceinline__ float get_row(int a, unsigned xo, unsigned ro, float w) const {
+      return bload(rb, xo * 4u, ro * 4u, 0.0f) *
+             (w + bload(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), H()));
     }
     // all Q directions, direction a from cell src(a): every load is issued before
     // the first decode, so the wavefront keeps 2Q loads in flight
@@ -150,6 +164,10 @@ struct OffsetPops {
     // populations are far from all positive (S < 1/2) the base stays b0.
     template <int Q, typename W>
     __device__ __forceinline__ void put_all(unsigned idx, const float* v, double mass, W w) const {
+      put_all_row<Q>(idx, 0u, v, mass, w);
+    }
+    template <int Q, typename W>
+    __device__ __forceinline__ void put_all_row(unsigned xo, unsigned ro, const float* v, double mass, W w) const {
       float b0 = 0.0f;
 #pragma unroll
       for (int a = 0; a < Q; ++a) b0 += fabsf(v[a]);
@@ -160,10 +178,10 @@ struct OffsetPops {
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const H r = enc(v[a] * inv - wm * w(a));
-        bstore(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, r);
+        bstore(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), r);
         S += (double)(w(a) + (float)r);
       }
-      bstore(rb, idx * 4u, 0u, S >= 0.5 ? (float)(mass / S) : b0);
+      bstore(rb, xo * 4u, ro * 4u, S >= 0.5 ? (float)(mass / S) : b0);
     }
   };
   __device__ __forceinline__ View comp(int s, int Q, int cells) const {
@@ -209,6 +227,54 @@ __device__ __forceinline__ Coord make_coord(unsigned cell, const KParams& P) {
   c.zs[1] = z * pl;
   c.zs[2] = (z == nz - 1 ? 0 : z + 1) * pl;
   return c;
+}
+
+// Row-structured position: a wavefront covers 64 consecutive x of one row (y, z),
+// so the row part of every neighbour offset is uniform across the wavefront
+// (scalar registers, passed as the buffer instructions' scalar offset) and only
+// x - 1, x, x + 1 (periodic) live in vector registers.
+struct RowCoord {
+  unsigned xs[3];          // per lane: x-1, x, x+1
+  unsigned ys[3], zs[3];   // uniform: (y+dy) nx and (z+dz) nx ny, dy, dz in -1..1
+  __device__ __forceinline__ unsigned row(int dy, int dz) const { return zs[dz + 1] + ys[dy + 1]; }
+  __device__ __forceinline__ unsigned x(int dx) const { return xs[dx + 1]; }
+};
+
+// Segment `seg` of the launch (uniform): rows of planes [plane0, plane0 + nplanes)
+// (periodic), each row cut into ceil(nx / 64) segments of 64 cells.  False when
+// the segment lies past the range; *in_row is false for lanes with x >= nx.
+template <int D>
+__device__ __forceinline__ bool row_segment(const KParams& P, unsigned seg, int plane0, int nplanes, unsigned lane,
+                                            RowCoord* c, bool* in_row) {
+  const unsigned nx = P.nx, ny = P.ny, nz = P.nz;
+  const unsigned nseg = (nx + 63u) / 64u;
+  const unsigned rows_pp = D == 3 ? ny : 1u;
+  if (seg >= (unsigned)nplanes * rows_pp * nseg) return false;
+  const unsigned sx = seg % nseg, r = seg / nseg;
+  unsigned y, z;
+  if (D == 3) {
+    y = r % ny;
+    z = (unsigned)plane0 + r / ny;
+    if (z >= nz) z -= nz;
+  } else {
+    y = (unsigned)plane0 + r;
+    if (y >= ny) y -= ny;
+    z = 0;
+  }
+  const unsigned x = sx * 64u + lane;
+  *in_row = x < nx;
+  const unsigned xx = *in_row ? x : 0u;
+  c->xs[0] = xx == 0 ? nx - 1 : xx - 1;
+  c->xs[1] = xx;
+  c->xs[2] = xx == nx - 1 ? 0 : xx + 1;
+  c->ys[0] = (y == 0 ? ny - 1 : y - 1) * nx;
+  c->ys[1] = y * nx;
+  c->ys[2] = (y == ny - 1 ? 0 : y + 1) * nx;
+  const unsigned pl = nx * ny;
+  c->zs[0] = (z == 0 ? nz - 1 : z - 1) * pl;
+  c->zs[1] = z * pl;
+  c->zs[2] = (z == nz - 1 ? 0 : z + 1) * pl;
+  return true;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
@@ -511,15 +577,15 @@ __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R r
 }
 
 template <int LAT, int ST, int COLL, int FORC>
-__device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& out, int s, unsigned cell,
-                                              const typename Pops<ST>::R* f, typename Pops<ST>::R rs,
+__device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& out, int s, unsigned xo,
+                                              unsigned ro, const typename Pops<ST>::R* f, typename Pops<ST>::R rs,
                                               const typename Pops<ST>::R* u3, const typename Pops<ST>::R* F3,
                                               double mass) {
   using V = VS<LAT>;
   using R = typename Pops<ST>::R;
   constexpr int Q = V::Q;
   collide_values<LAT, R, COLL, FORC>(P, f, rs, u3, F3, [&](const R* fo) {
-    out.comp(s, Q, P.cells).template put_all<Q>(cell, fo, mass, [](int a) { return (R)V::w(a); });
+    out.comp(s, Q, P.cells).template put_all_row<Q>(xo, ro, fo, mass, [](int a) { return (R)V::w(a); });
   });
 }
 
@@ -572,18 +638,11 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   const int lane = threadIdx.x & (kCells - 1);
   // uniform per wavefront (wave64): read it from lane 0 so it lives in a scalar register
   const int s = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kCells));
-  const unsigned lin = logical_block() * kCells + lane;
-  const unsigned pc = P.plane_cells;
-  const bool valid = lin < (unsigned)nplanes * pc;
-  unsigned cell = 0;
-  if (valid) {
-    const unsigned k = lin / pc;
-    unsigned plane = plane0 + k;
-    if (plane >= (unsigned)P.nplanes) plane -= P.nplanes;
-    cell = plane * pc + (lin - k * pc);
-  }
-  const Coord c = make_coord(cell, P);
+  RowCoord c;
+  bool in_row = false;
+  const bool valid = row_segment<V::D>(P, logical_block(), plane0, nplanes, (unsigned)lane, &c, &in_row) && in_row;
   const auto cv = in.comp(s, Q, P.cells);
+  const rsrc_t psr = make_rsrc(psi, (unsigned)P.cells * 8u);
   R f[Q];
   R rs = 0, jx = 0, jy = 0, jz = 0;
   double mass = 0.0;   // the component's mass, summed exactly (rs in float64 storage)
@@ -591,7 +650,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   if (valid) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      f[a] = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+      f[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
       mass += (double)f[a];
       if (V::cx(a)) jx += (R)V::cx(a) * f[a];
       if (V::cy(a)) jy += (R)V::cy(a) * f[a];
@@ -599,12 +658,12 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
     }
     rs = (R)mass;
     // partial stencil of Eq. (coupledMCforce) over this wavefront's directions
-    const double ps = ldb(psi, cell * 8u);
+    const double ps = bload(psr, c.x(0) * 8u, c.row(0, 0) * 8u, 0.0);
     const double hb = 0.5 * (1.0 - P.beta);
     static_for<1, Q>([&](auto A) {
       constexpr int a = decltype(A)::value;
       if ((a - 1) % NC == s) {
-        const double pn = ldb(psi, c.at(V::cx(a), V::cy(a), V::cz(a)) * 8u);
+        const double pn = bload(psr, c.x(V::cx(a)) * 8u, c.row(V::cy(a), V::cz(a)) * 8u, 0.0);
         const double t = V::w(a) * pn * (P.beta * ps + hb * pn);
         if constexpr (V::cx(a) != 0) Fp[0] += V::cx(a) * t;
         if constexpr (V::cy(a) != 0) Fp[1] += V::cy(a) * t;
@@ -664,7 +723,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
     fs[1] = ch * FR[1] + g1;
     fs[2] = ch * FR[2] + g2;
   }
-  collide_store<LAT, ST, COLL, FORC>(P, out, s, cell, f, rs, u, fs, mass);
+  collide_store<LAT, ST, COLL, FORC>(P, out, s, c.x(0), c.row(0, 0), f, rs, u, fs, mass);
 }
 
 }  // namespace lbmk
