@@ -29,10 +29,24 @@ Readings (the paper is silent on these):
   * Optional uniform body acceleration g adds rbar_sigma g to F_sigma (a test hook
     for momentum balance with forcing).
 
-Pins (tests/test_oracle_lbm.py): per-component mass, momentum balance, equilibrium
-and forcing moment identities, MRT==BGK at equal rates, identical components ==
-single-component model (Sec. 4.1), force stencil on linear psi, invariance to |G|,
-uniform-state fixed point.
+Solid walls (beyond the paper: porous media are its motivation in Sec. 1, but it
+defines no boundary; this is the design used here).  An optional boolean mask
+marks solid cells.  Solid cells hold no fluid (their populations are zero); in the
+force stencil their psi is a wetting constant psi_w (a larger psi_w attracts the
+fluid, G < 0).  Streaming uses halfway bounce-back: a population that would arrive
+at a fluid cell x from a solid cell x - e_a is instead the post-collision
+population of the opposite direction at x itself (it left x towards the wall and
+returned reversed within the step).  Collision, force split and velocity are
+evaluated on fluid cells only.
+
+Pins (tests/test_oracle_lbm.py, tests/test_oracle_walls.py): per-component mass,
+momentum balance, equilibrium and forcing moment identities, MRT==BGK at equal
+rates, identical components == single-component model (Sec. 4.1), force stencil
+on linear psi, invariance to |G|, uniform-state fixed point; with walls: the
+streaming is a permutation of the fluid cells' values, mass is conserved, a
+uniform resting fluid with psi_w = psi(rho) is a fixed point, the wetting sign,
+and the BGK Poiseuille profile that halfway bounce-back reproduces exactly at
+(tau - 1/2)^2 = 3/16.
 """
 from __future__ import annotations
 
@@ -59,6 +73,8 @@ class StepParams:
     forcing: str = "guo"        # "guo" | "edm"
     mrt_s: np.ndarray = None    # relaxation rate per moment row (MRT only)
     accel: np.ndarray = field(default=None)
+    solid: np.ndarray = None    # boolean mask of solid cells (space shape); None = no walls
+    psi_wall: float = 0.0       # psi of the solid cells in the force stencil
 
 
 def _axis(d: int, nspace: int, lead: int) -> int:
@@ -125,15 +141,18 @@ def total_force(psi: np.ndarray, beta: float, G: float, lat: VelocitySet) -> np.
     return F
 
 
-def split_force(F: np.ndarray, rho_s: np.ndarray, gamma) -> np.ndarray:
+def split_force(F: np.ndarray, rho_s: np.ndarray, gamma, fluid=None) -> np.ndarray:
     """F_sigma = chi_sigma F with chi_sigma = gamma_sigma rbar_sigma / sum_i gamma_i rbar_i,
-    Eq. (forcedistribution) and Eq. (distributionforce)."""
+    Eq. (forcedistribution) and Eq. (distributionforce).  With a fluid mask, solid
+    cells get F_sigma = 0 and are not checked."""
     gamma = np.asarray(gamma, dtype=np.float64)
     gshape = (-1,) + (1,) * (rho_s.ndim - 1)
     Gam = np.sum(gamma.reshape(gshape) * rho_s, axis=0)
-    if np.any(Gam <= 0.0):
+    if fluid is None:
+        fluid = np.ones(Gam.shape, dtype=bool)
+    if np.any(Gam[fluid] <= 0.0):
         raise DomainError("sum_i gamma_i rbar_i <= 0")
-    chi = gamma.reshape(gshape) * rho_s / Gam
+    chi = np.where(fluid, gamma.reshape(gshape) * rho_s / np.where(fluid, Gam, 1.0), 0.0)
     return chi[:, None] * F[None]          # (N, D, *space)
 
 
@@ -173,32 +192,67 @@ def _apply_matrix(Mx: np.ndarray, g: np.ndarray) -> np.ndarray:
     return np.tensordot(Mx, g, axes=([1], [0]))
 
 
+def opposite(lat: VelocitySet) -> np.ndarray:
+    """Index of -e_a for every direction a."""
+    return np.array([next(b for b in range(lat.Q) if np.array_equal(lat.e[b], -lat.e[a])) for a in range(lat.Q)])
+
+
+def stream(fstar: np.ndarray, lat: VelocitySet, solid=None) -> np.ndarray:
+    """f(x, t + 1) = f*(x - e_a, t), periodic; with a solid mask, halfway
+    bounce-back: at a fluid cell x whose source x - e_a is solid the arriving
+    population is f*_{opp(a)}(x), and solid cells receive nothing (zero)."""
+    fnew = np.empty_like(fstar)
+    for s in range(fstar.shape[0]):
+        for a in range(lat.Q):
+            fnew[s, a] = shift(fstar[s, a], lat.e[a], lead=0)
+    if solid is None:
+        return fnew
+    opp = opposite(lat)
+    for a in range(lat.Q):
+        from_wall = shift(solid, lat.e[a], lead=0) & ~solid      # x fluid, x - e_a solid
+        for s in range(fstar.shape[0]):
+            fnew[s, a][from_wall] = fstar[s, opp[a]][from_wall]
+    fnew[:, :, solid] = 0.0
+    return fnew
+
+
 def step(f: np.ndarray, mix: thermo.Mixture, prm: StepParams, lat: VelocitySet, return_fields=False):
     """Advance the populations by one time step; see the module docstring."""
     N = f.shape[0]
     D = lat.D
     gshape = (-1,) + (1,) * (f.ndim - 2)
+    solid = prm.solid
+    fluid = None if solid is None else ~solid
+    if solid is not None:
+        f = np.where(solid[None, None], 0.0, f)        # solid cells hold no fluid
     # 1. densities and momentum
     rho_s = densities(f)
     rho = rho_s.sum(axis=0)
     j = momentum(f, lat)
-    # 2-3. EOS and pseudo-potential
-    psi = pseudo_potential(rho_s, prm.T, mix, prm.G)
+    # 2-3. EOS and pseudo-potential (psi_w on solid cells)
+    if solid is None:
+        psi = pseudo_potential(rho_s, prm.T, mix, prm.G)
+    else:
+        psi = np.full(rho.shape, float(prm.psi_wall))
+        psi[fluid] = pseudo_potential(rho_s[:, fluid], prm.T, mix, prm.G)
     # 4. total interaction force
     F = total_force(psi, prm.beta, prm.G, lat)
     # 5. split into components (+ optional body acceleration)
-    F_s = split_force(F, rho_s, prm.gamma)
+    F_s = split_force(F, rho_s, prm.gamma, fluid)
     g = np.zeros(D) if prm.accel is None else np.asarray(prm.accel, dtype=np.float64)
     for d in range(D):
         F_s[:, d] += rho_s * g[d]
     F_tot = F_s.sum(axis=0)
+    rho_div = rho if solid is None else np.where(solid, 1.0, rho)   # solid cells: u = 0
     # 6. velocity, equilibrium, collision with forcing
     if prm.forcing == "guo":
-        u = (j + 0.5 * F_tot) / rho
+        u = (j + 0.5 * F_tot) / rho_div
     elif prm.forcing == "edm":
-        u = j / rho
+        u = j / rho_div
         gamma = np.asarray(prm.gamma, dtype=np.float64)
         Gam = np.sum(gamma.reshape(gshape) * rho_s, axis=0)
+        if solid is not None:
+            Gam = np.where(solid, 1.0, Gam)
     else:
         raise ValueError(prm.forcing)
     if prm.collision == "mrt":
@@ -228,11 +282,10 @@ def step(f: np.ndarray, mix: thermo.Mixture, prm: StepParams, lat: VelocitySet, 
                 du[d] = prm.gamma[s] * F[d] / Gam + g[d]
             post = post + equilibrium(rho_s[s], u + du, lat) - feq
         fstar[s] = post
-    # 7. streaming: f(x + e_a, t + 1) = f*(x, t)
-    fnew = np.empty_like(f)
-    for s in range(N):
-        for a in range(lat.Q):
-            fnew[s, a] = shift(fstar[s, a], lat.e[a], lead=0)
+    if solid is not None:
+        fstar[:, :, solid] = 0.0
+    # 7. streaming: f(x + e_a, t + 1) = f*(x, t) (bounce-back at solid sources)
+    fnew = stream(fstar, lat, solid)
     if return_fields:
         return fnew, {"rho_s": rho_s, "rho": rho, "j": j, "psi": psi, "F": F,
                       "F_s": F_s, "u": u, "fstar": fstar}
@@ -243,15 +296,29 @@ def macroscopic(f: np.ndarray, mix: thermo.Mixture, prm: StepParams, lat: Veloci
     """Fields reported for a population state: rbar_sigma, the physical velocity
     u = (j + F_total/2)/rho, p (= p_EOS, equal to the hydrodynamic pressure of
     Eq. (hydropressure) by construction of psi) and psi."""
+    solid = prm.solid
+    if solid is not None:
+        f = np.where(solid[None, None], 0.0, f)
     rho_s = densities(f)
     rho = rho_s.sum(axis=0)
     j = momentum(f, lat)
-    p = eos_pressure(rho_s, prm.T, mix)
-    psi = pseudo_potential(rho_s, prm.T, mix, prm.G)
+    if solid is None:
+        p = eos_pressure(rho_s, prm.T, mix)
+        psi = pseudo_potential(rho_s, prm.T, mix, prm.G)
+    else:                                   # solid cells: p = 0, psi = psi_w
+        p = np.zeros(rho.shape)
+        p[~solid] = eos_pressure(rho_s[:, ~solid], prm.T, mix)
+        psi = np.full(rho.shape, float(prm.psi_wall))
+        psi[~solid] = pseudo_potential(rho_s[:, ~solid], prm.T, mix, prm.G)
     F = total_force(psi, prm.beta, prm.G, lat)
     g = np.zeros(lat.D) if prm.accel is None else np.asarray(prm.accel, dtype=np.float64)
     F_tot = F + rho[None] * g.reshape((-1,) + (1,) * rho.ndim)
-    u = (j + 0.5 * F_tot) / rho
+    if solid is None:
+        u = (j + 0.5 * F_tot) / rho
+    else:                                   # solid cells: no fluid, u = 0, F = 0
+        F = np.where(solid[None], 0.0, F)
+        F_tot = np.where(solid[None], 0.0, F_tot)
+        u = (j + 0.5 * F_tot) / np.where(solid, 1.0, rho)
     return {"rho_s": rho_s, "u": u, "p": p, "psi": psi, "F": F, "j": j}
 
 

@@ -22,6 +22,7 @@ pressures and fugacities come from the library's host thermodynamics.
 """
 from __future__ import annotations
 
+import math
 
 import numpy as np
 
@@ -173,12 +174,13 @@ def reflash_gamma(case, rho_s):
 
 
 def run_flat(cases, collision="bgk", forcing="guo", storage="f64", max_steps=2_000_000, check_every=20_000,
-             tol=1e-9, graph_steps=1000, progress=None, gamma_update=False):
+             tol=1e-9, graph_steps=1000, progress=None, gamma_update=False, fields_out=None):
     """Advance the boxes together until the bulk densities of every box change by
     less than tol (relative) over check_every steps.  Returns the reports;
     progress(steps, change) is called after every check.  With gamma_update, every
     check re-flashes each box at its current bulk pressure and overall composition
-    and replaces its gamma (state-dependent gamma, Sec. 3.1)."""
+    and replaces its gamma (state-dependent gamma, Sec. 3.1).  A list passed as
+    fields_out receives the final per-component density fields of the boxes."""
     boxes = [{"mix": c["mix"], "shape": c["shape"], "T": c["T"], "tau": c["tau"], "beta": c["beta"],
               "gamma": c["gamma"], "rho0": c["rho0"]} for c in cases]
     rates = None
@@ -219,7 +221,8 @@ def run_flat(cases, collision="bgk", forcing="guo", storage="f64", max_steps=2_0
     for r, c in zip(rho, cases):
         rl, rv = bulk_state(r, c["mix"])
         rep = phase_report(c["mix"], c["T"], rl, rv, c["flash"])
-        rep.update({"p_psia": c["p_psia"], "beta": c["beta"], "steps": steps, "last_change": change,
+        rep.update({"p_psia": c["p_psia"], "nx": int(c["shape"][1]), "beta": c["beta"], "steps": steps,
+                    "last_change": change,
                     "p_lb_psia": 0.5 * (rep["p_l"] + rep["p_v"]) * c["units"].sp,
                     "gamma": np.asarray(c["gamma"]).tolist()})
         # the same bulk states against the flash at the LB pressure and overall composition
@@ -229,6 +232,8 @@ def run_flat(cases, collision="bgk", forcing="guo", storage="f64", max_steps=2_0
         rep["err_composition_at_lb_pressure"] = lb["err_composition"]
         rep["err_density_at_lb_pressure"] = lb["err_density"]
         reports.append(rep)
+    if fields_out is not None:
+        fields_out.extend(rho)
     return reports
 
 
@@ -248,6 +253,97 @@ def calibrate_beta(p_list=(200.0, 240.0), forcing="edm", collision="bgk", betas=
     return {"sweep": [{"beta": bt, "worst_composition_err": score[bt],
                        "worst_density_err": max(r["err_density"] for r in table[bt])} for bt in sorted(table)],
             "best_beta": best, "best_err": score[best], "reports": reps}
+
+
+# ---------------------------------------------------------------------------
+# Grid convergence (Sec. 4.2: phase densities of the flat interface against the
+# finest box; Sec. 4.3: surface tension against the largest drop)
+# ---------------------------------------------------------------------------
+
+def convergence(values: dict) -> list:
+    """values: {n: v}.  Relative error of each v against the value at the largest n,
+    |v_n - v_max| / |v_max|, and the observed order between consecutive sizes,
+    log(e_a / e_b) / log(n_b / n_a) (None where the next error is the last one or zero)."""
+    ns = sorted(values)
+    ref = values[ns[-1]]
+    errs = [abs(values[n] - ref) / abs(ref) for n in ns[:-1]]
+    rows = []
+    for i, n in enumerate(ns[:-1]):
+        order = None
+        if i + 1 < len(errs) and errs[i] > 0.0 and errs[i + 1] > 0.0:
+            order = math.log(errs[i] / errs[i + 1]) / math.log(ns[i + 1] / n)
+        rows.append({"n": n, "error": errs[i], "order": order})
+    return rows
+
+
+def flat_convergence(reports) -> dict:
+    """Per pressure, the liquid and vapour mass densities of the flat-interface
+    reports (any number of runs; one report per (pressure, nx)) against the
+    largest nx."""
+    out = {}
+    for p in sorted({r["p_psia"] for r in reports}):
+        rs = {r["nx"]: r for r in reports if r["p_psia"] == p}
+        out[str(p)] = {"reference_nx": max(rs),
+                       "rho_l": convergence({n: r["rho_l"] for n, r in rs.items()}),
+                       "rho_v": convergence({n: r["rho_v"] for n, r in rs.items()})}
+    return out
+
+
+def sigma_convergence(laplace: dict) -> dict:
+    """Per pressure of a run_laplace result, the surface tension of each drop by
+    Laplace's law alone, sigma_n = dp_n R_n, against the largest box."""
+    out = {}
+    for p, d in laplace["pressures"].items():
+        sig = {m["n"]: m["dp"] * m["R"] for m in d["drops"]}
+        out[p] = {"sigma": {str(n): v for n, v in sorted(sig.items())}, "convergence": convergence(sig)}
+    return out
+
+
+def _level_crossing(prof, level, i0, i1, rising):
+    """Fractional index of the first crossing of level in prof[i0:i1]."""
+    for i in range(max(i0, 1), i1):
+        a, b = prof[i - 1], prof[i]
+        if (a < level <= b) if rising else (a >= level > b):
+            return i - 1 + (level - a) / (b - a)
+    raise ValueError("no interface found")
+
+
+def stretch_flat(rho_s, nx_new, mass=None, keep=24):
+    """A starting state for a larger flat-interface box from a converged smaller
+    one (nc, ny, nx): the slab stays centred and its length scales with the box,
+    the profiles within `keep` cells of each interface are carried over (linear
+    interpolation at the shifted positions), the rest is filled with the bulk
+    values of the small box.  With mass (per-component totals) each component is
+    rescaled to its total, so the run conserves the same amounts as a box
+    initialised directly at nx_new."""
+    r = np.asarray(rho_s, dtype=np.float64)
+    nc, ny, nx = r.shape
+    prof = r.mean(axis=1)
+    tot = prof.sum(axis=0)
+    c_old = nx // 2
+    level = 0.5 * (tot[c_old] + tot[0])
+    xl = _level_crossing(tot, level, 1, c_old + 1, rising=True)
+    xr = _level_crossing(tot, level, c_old, nx, rising=False)
+    s = nx_new / nx
+    c_new = nx_new // 2
+    xl_new = c_new - (c_old - xl) * s
+    xr_new = c_new + (xr - c_old) * s
+    liq, vap = prof[:, c_old], prof[:, 0]
+    xs = np.arange(nx, dtype=np.float64)
+    new = np.empty((nc, nx_new))
+    for X in range(nx_new):
+        if X < c_new:
+            d, x_old, inside = X - xl_new, xl + (X - xl_new), X > xl_new
+        else:
+            d, x_old, inside = X - xr_new, xr + (X - xr_new), X < xr_new
+        if abs(d) <= keep:
+            new[:, X] = [np.interp(x_old, xs, prof[i]) for i in range(nc)]
+        else:
+            new[:, X] = liq if inside else vap
+    out = np.repeat(new[:, None, :], ny, axis=1)
+    if mass is not None:
+        out *= (np.asarray(mass, dtype=np.float64) / out.reshape(nc, -1).sum(axis=1))[:, None, None]
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -457,6 +553,15 @@ def main():
     ap.add_argument("--sizes", default="50,100,200,400,800")
     ap.add_argument("--oscillation", action="store_true", help="oscillating elliptical drop instead (Table 3)")
     ap.add_argument("--betas", default="", help="comma list for --calibrate (default 1.0..2.0 step 0.1)")
+    ap.add_argument("--convergence", action="store_true",
+                    help="flat interface at every nx of --sizes (grid convergence, Sec. 4.2)")
+    ap.add_argument("--save-state", default="", help="flat runs: write the final fields to this .npz")
+    ap.add_argument("--init-from", default="",
+                    help="flat runs: start each box from the largest smaller box of this .npz (stretch_flat)")
+    ap.add_argument("--combine", nargs="+", default=None,
+                    help="merge the reports of flat-run JSON files into convergence tables and exit")
+    ap.add_argument("--sigma-convergence", default="",
+                    help="surface-tension convergence of a --laplace JSON file and exit")
     args = ap.parse_args()
     ps = [float(p) for p in args.pressures.split(",")]
     import sys
@@ -465,6 +570,17 @@ def main():
         print(f"steps {steps} max relative change of the bulk densities {change:.3e}", file=sys.stderr, flush=True)
 
     kw = dict(max_steps=args.max_steps, check_every=args.check_every, tol=args.tol, progress=progress)
+    if args.combine:
+        reps = []
+        for path in args.combine:
+            with open(path) as fh:
+                reps += json.loads(fh.read().strip().splitlines()[-1])["reports"]
+        print(json.dumps(flat_convergence(reps), default=float))
+        return
+    if args.sigma_convergence:
+        with open(args.sigma_convergence) as fh:
+            print(json.dumps(sigma_convergence(json.loads(fh.read().strip().splitlines()[-1])), default=float))
+        return
     if args.oscillation:
         out = run_oscillation(sizes=[int(n) for n in args.sizes.split(",")], beta=args.beta, forcing=args.forcing,
                               progress=progress)
@@ -475,10 +591,27 @@ def main():
         betas = [float(b) for b in args.betas.split(",")] if args.betas else None
         out = calibrate_beta(ps, forcing=args.forcing, collision=args.collision, nx=args.nx, betas=betas, **kw)
     else:
-        cases = [flat_case(p, nx=args.nx, beta=args.beta) for p in ps]
-        reps = run_flat(cases, collision=args.collision, forcing=args.forcing, gamma_update=args.gamma_update, **kw)
+        sizes = [int(n) for n in args.sizes.split(",")] if args.convergence else [args.nx]
+        cases = [flat_case(p, nx=n, beta=args.beta) for p in ps for n in sizes]
+        if args.init_from:
+            saved = np.load(args.init_from)
+            for c in cases:
+                nx = c["shape"][1]
+                keys = [k for k in saved.files if k.startswith(f"p{c['p_psia']:g}_nx")]
+                smaller = [int(k.split("_nx")[1]) for k in keys if int(k.split("_nx")[1]) < nx]
+                if smaller:
+                    src = saved[f"p{c['p_psia']:g}_nx{max(smaller)}"]
+                    mass = c["rho0"].reshape(c["rho0"].shape[0], -1).sum(axis=1)
+                    c["rho0"] = stretch_flat(src, nx, mass=mass)
+        fields = []
+        reps = run_flat(cases, collision=args.collision, forcing=args.forcing, gamma_update=args.gamma_update,
+                        fields_out=fields, **kw)
+        if args.save_state:
+            np.savez(args.save_state, **{f"p{c['p_psia']:g}_nx{c['shape'][1]}": f for c, f in zip(cases, fields)})
         out = {"reports": reps, "worst_composition_err": max(r["err_composition"] for r in reps),
                "worst_density_err": max(r["err_density"] for r in reps)}
+        if len(sizes) > 1:
+            out["convergence"] = flat_convergence(reps)
     print(json.dumps(out, default=float))
 
 

@@ -1,0 +1,187 @@
+"""Pins of the oracle's solid walls (halfway bounce-back, wetting psi_w).
+
+The wall model is a design beyond the paper (porous media motivate it in Sec. 1;
+no boundary is defined there).  Each test checks the oracle against a fact that
+does not come from the oracle itself:
+  * BGK Poiseuille flow between halfway bounce-back walls is the exact parabola
+    u(d) = g d (H - d) / (2 nu) when (tau - 1/2)^2 = 3/16 (the known exactness
+    condition of halfway bounce-back for the parabolic profile), in D2Q9 and D3Q19;
+  * the streaming maps the fluid cells' post-collision values one-to-one onto the
+    fluid cells, and a population sent into a wall comes back reversed at the
+    same cell in the same step;
+  * per-component mass is conserved with walls and interaction forces;
+  * a uniform resting fluid whose psi equals psi_w is a fixed point;
+  * a wall with psi_w above the fluid's psi attracts it (denser next to the wall),
+    below repels it;
+  * an all-fluid mask is the periodic step.
+"""
+import numpy as np
+import pytest
+
+from oracle import lattice as L
+from oracle import lbm, thermo
+from oracle.lattice import CS2
+
+LATS = [L.d2q9(), L.d3q19()]
+
+
+def _pure():
+    # the Sec. 4.1 single-component fluid (a = 2/49, b = 2/21, R = 1, omega = 0.344)
+    return thermo.Mixture(a=[2 / 49], b=[2 / 21], omega=[0.344], M=[1.0], k=[[0.0]], R=1.0)
+
+
+def _binary():
+    return thermo.Mixture(a=[2 / 49, 0.08], b=[2 / 21, 0.15], omega=[0.15, 0.25], M=[1.0, 1.6],
+                          k=[[0, 0.02], [0.02, 0]], R=1.0)
+
+
+def _channel(lat, H, nx=2, nz=2):
+    """Solid rows y = 0 and y = H + 1, fluid rows 1..H; periodic in x (and z)."""
+    shape = (H + 2, nx) if lat.D == 2 else (nz, H + 2, nx)
+    solid = np.zeros(shape, dtype=bool)
+    solid[..., 0, :] = True
+    solid[..., H + 1, :] = True
+    return solid
+
+
+def _porous(shape, seed, frac=0.2):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(size=shape) < frac
+
+
+def _psi_of(rho, T, mix):
+    return float(lbm.pseudo_potential(np.full((mix.nc, 1), rho / mix.nc), T, mix, -1.0)[0])
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+def test_poiseuille_exact_at_magic_tau(lat):
+    mix = _pure()
+    T = 0.9 * float(mix.Tc[0])
+    H = 8
+    solid = _channel(lat, H)
+    rho0 = 0.6
+    tau = 0.5 + np.sqrt(3.0 / 16.0)
+    g = 1e-6
+    acc = np.zeros(lat.D)
+    acc[0] = g
+    prm = lbm.StepParams(T=T, tau=tau, gamma=[1.0], beta=1.5, forcing="guo", accel=acc, solid=solid,
+                         psi_wall=_psi_of(rho0, T, mix))
+    f = lbm.init_populations(np.full((1,) + solid.shape, rho0), lat)
+    for _ in range(3000):
+        f = lbm.step(f, mix, prm, lat)
+    u = lbm.macroscopic(f, mix, prm, lat)["u"]
+    nu = CS2 * (tau - 0.5)
+    d = np.arange(1, H + 1) - 0.5                     # distance of row y from the wall at y = 1/2
+    exact = g * d * (H - d) / (2.0 * nu)
+    ux = u[0][..., 1:H + 1, :]                        # fluid rows
+    prof = ux.reshape(-1, H, ux.shape[-1]).transpose(1, 0, 2).reshape(H, -1)
+    assert np.max(np.abs(prof - exact[:, None])) <= 1e-9 * exact.max()
+    # no flow across the channel, none in the walls
+    assert np.max(np.abs(u[1])) <= 1e-9 * exact.max()
+    assert np.all(u[0][solid] == 0.0)
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+def test_streaming_is_a_permutation_and_reflects_at_walls(lat):
+    shape = (7, 9) if lat.D == 2 else (5, 6, 7)
+    solid = _porous(shape, 3, 0.3)
+    rng = np.random.default_rng(1)
+    fstar = rng.permutation(np.arange(2 * lat.Q * solid.size, dtype=np.float64)).reshape((2, lat.Q) + shape)
+    fnew = lbm.stream(fstar, lat, solid)
+    fluid = ~solid
+    got = np.sort(fnew[:, :, fluid].ravel())
+    sent = np.sort(fstar[:, :, fluid].ravel())
+    assert np.array_equal(got, sent)                   # every fluid value lands once
+    assert np.all(fnew[:, :, solid] == 0.0)
+    # a population that leaves a fluid cell towards a solid neighbour returns
+    # reversed at the same cell
+    opp = lbm.opposite(lat)
+    for a in range(1, lat.Q):
+        assert np.array_equal(lat.e[opp[a]], -lat.e[a])
+        # fluid x whose neighbour x + e_a is solid: f*_a(x) comes back as f_{opp(a)}(x)
+        into_wall = lbm.shift(solid, -lat.e[a], lead=0) & fluid
+        assert np.array_equal(fnew[:, opp[a]][:, into_wall], fstar[:, a][:, into_wall])
+
+
+def _drop(lat, shape, mix, seed):
+    rng = np.random.default_rng(seed)
+    grids = np.meshgrid(*[np.arange(n, dtype=float) for n in shape], indexing="ij")
+    r = np.sqrt(sum((gg - n / 2) ** 2 for gg, n in zip(grids, shape)))
+    t = np.tanh(2 * (r - min(shape) / 4) / 4.0)
+    inner = np.array([1.8, 4.2])[: mix.nc]
+    outer = np.array([0.25, 0.15])[: mix.nc]
+    rho = 0.5 * (inner + outer)[:, None] - 0.5 * (inner - outer)[:, None] * t.reshape(1, -1)
+    return rho.reshape((mix.nc,) + tuple(shape)) * (1 + 1e-3 * rng.uniform(-1, 1, (mix.nc,) + tuple(shape)))
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+@pytest.mark.parametrize("collision,forcing", [("bgk", "guo"), ("bgk", "edm"), ("mrt", "edm")])
+def test_mass_conserved_with_walls(lat, collision, forcing):
+    mix = _binary()
+    shape = (16, 18) if lat.D == 2 else (8, 9, 10)
+    solid = _porous(shape, 5, 0.15)
+    T = 0.8 * float(np.min(mix.Tc))
+    rho = _drop(lat, shape, mix, 2)
+    rates = np.full(lat.Q, 1 / 0.8) if collision == "mrt" else None
+    prm = lbm.StepParams(T=T, tau=0.8, gamma=[0.6, 0.4], beta=1.5, collision=collision, forcing=forcing,
+                         mrt_s=rates, solid=solid, psi_wall=0.3)
+    f = lbm.init_populations(rho, lat)
+    f[:, :, solid] = 0.0
+    m0 = f.sum(axis=tuple(range(1, f.ndim)))
+    for _ in range(30):
+        f = lbm.step(f, mix, prm, lat)
+    m = f.sum(axis=tuple(range(1, f.ndim)))
+    assert np.all(np.abs(m - m0) <= 1e-13 * m0)
+    assert np.all(f[:, :, solid] == 0.0)
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+@pytest.mark.parametrize("forcing", ["guo", "edm"])
+def test_uniform_rest_with_matching_wall_psi_is_fixed_point(lat, forcing):
+    mix = _binary()
+    shape = (10, 12) if lat.D == 2 else (6, 7, 8)
+    solid = _porous(shape, 7, 0.25)
+    T = 0.8 * float(np.min(mix.Tc))
+    rho = np.array([0.3, 0.2])
+    psi = float(lbm.pseudo_potential(rho[:, None], T, mix, -1.0)[0])
+    prm = lbm.StepParams(T=T, tau=0.8, gamma=[0.6, 0.4], beta=1.5, forcing=forcing, solid=solid, psi_wall=psi)
+    f0 = lbm.init_populations(rho.reshape((2,) + (1,) * lat.D) * np.ones((2,) + shape), lat)
+    f0[:, :, solid] = 0.0
+    f = f0
+    for _ in range(5):
+        f = lbm.step(f, mix, prm, lat)
+    assert np.max(np.abs(f - f0)) <= 1e-14 * np.max(f0)     # rounding only
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+def test_wetting_sign(lat):
+    """psi_w above the fluid's psi pulls fluid to the wall, below pushes it away."""
+    mix = _pure()
+    T = 0.9 * float(mix.Tc[0])
+    H = 10
+    solid = _channel(lat, H)
+    rho0 = 0.6
+    p0 = _psi_of(rho0, T, mix)
+    near = []
+    for psi_w in (1.5 * p0, 0.5 * p0):
+        prm = lbm.StepParams(T=T, tau=0.8, gamma=[1.0], beta=1.5, forcing="guo", solid=solid, psi_wall=psi_w)
+        f = lbm.init_populations(np.full((1,) + solid.shape, rho0), lat)
+        f[:, :, solid] = 0.0
+        for _ in range(40):
+            f = lbm.step(f, mix, prm, lat)
+        rho = f.sum(axis=1)[0]
+        near.append(float(rho[..., 1, :].mean()))     # first fluid row
+    assert near[0] > rho0 * (1 + 1e-4)
+    assert near[1] < rho0 * (1 - 1e-4)
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+def test_all_fluid_mask_is_periodic_step(lat):
+    mix = _binary()
+    shape = (9, 11) if lat.D == 2 else (5, 6, 7)
+    T = 0.8 * float(np.min(mix.Tc))
+    f = lbm.init_populations(_drop(lat, shape, mix, 4), lat)
+    base = dict(T=T, tau=0.8, gamma=[0.6, 0.4], beta=1.5, forcing="edm")
+    a = lbm.step(f, mix, lbm.StepParams(**base), lat)
+    b = lbm.step(f, mix, lbm.StepParams(**base, solid=np.zeros(shape, dtype=bool), psi_wall=0.7), lat)
+    assert np.array_equal(a, b)

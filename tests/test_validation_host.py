@@ -59,3 +59,46 @@ def test_flat_profile_limits_and_symmetry():
     assert np.allclose(prof[:, :, 200], l[:, None], atol=1e-12)
     assert np.allclose(prof[:, :, 0], v[:, None], atol=1e-12)
     assert np.allclose(prof[:, 0, 1:], prof[:, 0, 1:][:, ::-1], atol=1e-12)
+
+
+def test_convergence_recovers_a_known_order():
+    """v_n = 1 + 0.3 n^-p against a reference size far enough out that its own
+    error is below rounding: errors 0.3 n^-p, observed order p between sizes."""
+    for p in (1.0, 2.0):
+        vals = {n: 1.0 + 0.3 * n ** -p for n in (50, 100, 200, 400)}
+        vals[10 ** 9] = 1.0 + 0.3 * (10.0 ** 9) ** -p
+        rows = validation.convergence(vals)
+        for r in rows[:3]:
+            assert r["error"] == pytest.approx(0.3 * r["n"] ** -p / (1.0 + 0.3e-9 ** p), rel=1e-6)
+            assert r["order"] == pytest.approx(p, rel=1e-6)
+        assert rows[-1]["order"] is None
+
+
+def test_flat_and_sigma_convergence_group_by_pressure():
+    reps = [{"p_psia": p, "nx": n, "rho_l": 5.0 + 1.0 / n + p, "rho_v": 0.5 + 2.0 / n} for p in (200.0, 240.0)
+            for n in (100, 200, 400)]
+    out = validation.flat_convergence(reps)
+    assert set(out) == {"200.0", "240.0"} and out["200.0"]["reference_nx"] == 400
+    e = out["240.0"]["rho_v"][0]["error"]
+    assert e == pytest.approx((2.0 / 100 - 2.0 / 400) / (0.5 + 2.0 / 400), rel=1e-12)
+    lap = {"pressures": {"200.0": {"drops": [{"n": n, "dp": 0.13 / (n / 5) * (1 + 1 / n), "R": n / 5}
+                                             for n in (50, 100, 200)]}}}
+    s = validation.sigma_convergence(lap)["200.0"]
+    assert s["sigma"]["100"] == pytest.approx(0.13 * 1.01, rel=1e-12)
+    assert s["convergence"][0]["error"] == pytest.approx((0.13 * 1.02 - 0.13 * 1.005) / (0.13 * 1.005), rel=1e-12)
+
+
+def test_stretch_flat_keeps_interfaces_bulk_and_masses():
+    """A tanh slab of a 400-cell box stretched to 800 cells is the tanh slab of the
+    800-cell box with the same width (interfaces at the scaled positions), and the
+    optional rescale hits the requested component totals."""
+    l, v = np.array([4.0, 2.5]), np.array([0.6, 0.2])
+    small = validation.flat_profile(400, 2, 120.0, 8.0, l, v)
+    big = validation.flat_profile(800, 2, 240.0, 8.0, l, v)
+    st = validation.stretch_flat(small, 800)
+    assert st.shape == big.shape
+    # the kept band (24 cells) ends where the tanh tail is 1 - tanh(6) ~ 1e-5 from the bulk
+    assert np.max(np.abs(st - big)) < 1e-5 * l.max()
+    mass = big.reshape(2, -1).sum(axis=1) * np.array([1.001, 0.999])
+    st2 = validation.stretch_flat(small, 800, mass=mass)
+    assert np.allclose(st2.reshape(2, -1).sum(axis=1), mass, rtol=1e-13, atol=0)
