@@ -188,6 +188,25 @@ lbm_status lbm_set_gamma(lbm_ctx* ctx, const double* gamma_host);
 /* Clear the device error flag. */
 lbm_status lbm_clear_error(lbm_ctx* ctx);
 
+/* Solid walls (porous media, the application that motivates the model in Sec. 1;
+ * the paper defines no boundary, so this is a design of its own).
+ * solid_host: one byte per cell in the field order of lbm_moments (x fastest),
+ * nonzero = solid; NULL removes every wall.  psi_wall (finite, >= 0): the value of
+ * psi on solid cells in the force stencil of Eq. (coupledMCforce) -- a wetting
+ * parameter: above the fluid's psi the wall attracts it, below repels it.
+ * Streaming uses halfway bounce-back: a population that would arrive at a fluid
+ * cell from a solid one is the cell's own post-collision population of the
+ * opposite direction.  Solid cells hold no fluid: no collision, zero populations,
+ * zero density / velocity / pressure in lbm_moments, psi = psi_wall.
+ * The call converts the current state: the canonical populations (lbm_get_populations)
+ * of cells that stay fluid are kept, new solid cells are emptied (a cell that stops
+ * being solid starts empty, outside the EOS domain, until lbm_set_populations fills
+ * it).  It allocates the per-cell mask (4 bytes per cell, kept until lbm_destroy)
+ * and a temporary of nc * Q * cells doubles, synchronises the stream, and is not
+ * meant for graph capture.  Every schedule supports walls; the adjoint
+ * (lbm_step_adjoint, lbm_adjoint) returns LBM_ERR_UNSUPPORTED while walls are set. */
+lbm_status lbm_set_solid(lbm_ctx* ctx, const unsigned char* solid_host, double psi_wall);
+
 /* Release the context (not the caller's workspace). NULL is accepted. */
 void lbm_destroy(lbm_ctx* ctx);
 

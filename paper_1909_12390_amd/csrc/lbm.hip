@@ -428,4 +428,66 @@ extern "C" lbm_status lbm_set_populations(lbm_ctx* c, const double* f) {
   return hip_check(hipGetLastError(), "import launch");
 }
 
+namespace {
+
+// bit a of cell x: the source x - e_a of direction a is solid; bit 31: x is solid
+template <int LAT>
+void wall_bits(const lbm_params& prm, const unsigned char* solid, unsigned* bits) {
+  using V = lbmk::VS<LAT>;
+  const long nx = prm.nx, ny = prm.ny, nz = prm.nz;
+  for (long z = 0; z < nz; ++z)
+    for (long y = 0; y < ny; ++y)
+      for (long x = 0; x < nx; ++x) {
+        const long cell = (z * ny + y) * nx + x;
+        unsigned b = solid[cell] ? (1u << lbmk::kSolidBit) : 0u;
+        for (int a = 1; a < V::Q; ++a) {
+          const long sx = (x - V::cx(a) + nx) % nx, sy = (y - V::cy(a) + ny) % ny, sz = (z - V::cz(a) + nz) % nz;
+          if (solid[(sz * ny + sy) * nx + sx]) b |= 1u << a;
+        }
+        bits[cell] = b;
+      }
+}
+
+}  // namespace
+
+extern "C" lbm_status lbm_set_solid(lbm_ctx* c, const unsigned char* solid, double psi_wall) {
+  if (!c) return lbm_fail(LBM_ERR_ARG, "ctx is NULL");
+  if (solid && !(std::isfinite(psi_wall) && psi_wall >= 0.0))
+    return lbm_fail(LBM_ERR_ARG, "psi_wall must be finite and >= 0");
+  // canonical populations under the current walls, re-imported under the new ones
+  const size_t fbytes = sizeof(double) * (size_t)c->mix.nc * c->Q * c->cells;
+  double* tmp = nullptr;
+  lbm_status st = hip_check(hipMalloc((void**)&tmp, fbytes), "hipMalloc(wall conversion)");
+  if (st != LBM_OK) return st;
+  c->ops.exp(c->kp, c->pops[c->cur], tmp, c->stream);
+  st = hip_check(hipGetLastError(), "export launch");
+  if (st == LBM_OK && solid) {
+    unsigned* bits = new (std::nothrow) unsigned[c->cells];
+    if (!bits) st = lbm_fail(LBM_ERR_ARG, "out of host memory");
+    if (st == LBM_OK) {
+      if (c->prm.lattice == LBM_D2Q9) wall_bits<LBM_D2Q9>(c->prm, solid, bits);
+      else wall_bits<LBM_D3Q19>(c->prm, solid, bits);
+      if (!c->bb) st = hip_check(hipMalloc((void**)&c->bb, sizeof(unsigned) * c->cells), "hipMalloc(walls)");
+    }
+    if (st == LBM_OK) st = hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st == LBM_OK)
+      st = hip_check(hipMemcpy(c->bb, bits, sizeof(unsigned) * c->cells, hipMemcpyHostToDevice), "hipMemcpy(walls)");
+    delete[] bits;
+    if (st == LBM_OK) {
+      c->kp.bb = c->bb;
+      c->kp.psi_wall = psi_wall;
+    }
+  } else if (st == LBM_OK) {
+    c->kp.bb = nullptr;
+    c->kp.psi_wall = 0.0;
+  }
+  if (st == LBM_OK) {
+    c->ops.imp(c->kp, c->pops[c->cur], tmp, nullptr, nullptr, 0, c->stream);
+    st = hip_check(hipGetLastError(), "import launch");
+  }
+  const lbm_status st2 = hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  hipFree(tmp);
+  return st != LBM_OK ? st : st2;
+}
+
 extern "C" void lbm_destroy(lbm_ctx* c) { delete c; }

@@ -64,13 +64,24 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams P, Pops<ST> in, cons
 #pragma unroll
   for (int k = 0; k < K; ++k) vals[k] = 0.0;
   unsigned cell;
-  if (launch_cell(P, 0, P.nplanes, &cell)) {
+  const bool inside = launch_cell(P, 0, P.nplanes, &cell);
+  const unsigned bits = (inside && P.bb) ? P.bb[cell] : 0u;
+  if (inside && (bits >> kSolidBit)) {   // solid cell: no fluid; psi is the wall's
+    if (rho_out)
+#pragma unroll
+      for (int s = 0; s < NC; ++s) rho_out[(size_t)s * P.cells + cell] = 0.0;
+    if (u_out)
+#pragma unroll
+      for (int d = 0; d < D; ++d) u_out[(size_t)d * P.cells + cell] = 0.0;
+    if (p_out) p_out[cell] = 0.0;
+    if (psi_out) psi_out[cell] = psi[cell];
+  } else if (inside) {
     const Coord c = make_coord(cell, P);
     double rb[NC], rho = 0.0;
     R jr[3] = {0, 0, 0};
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
-      rb[s] = pull_moments<LAT, ST>(P, in, s, c, jr);
+      rb[s] = pull_moments<LAT, ST>(P, in, s, c, jr, cell, bits);
       rho += rb[s];
     }
     const double j[3] = {(double)jr[0], (double)jr[1], (double)jr[2]};
@@ -113,18 +124,28 @@ __global__ __launch_bounds__(kBlock) void k_export(KParams P, Pops<ST> in, doubl
   unsigned cell;
   if (!launch_cell(P, 0, P.nplanes, &cell)) return;
   const Coord c = make_coord(cell, P);
+  const unsigned bits = P.bb ? P.bb[cell] : 0u;
 #pragma unroll 1
   for (int s = 0; s < NC; ++s) {
     const auto cv = in.comp(s, V::Q, P.cells);
 #pragma unroll
-    for (int a = 0; a < V::Q; ++a)
-      f[(size_t)(s * V::Q + a) * P.cells + cell] = (double)cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+    for (int a = 0; a < V::Q; ++a) {
+      const unsigned nbr = c.at(-V::cx(a), -V::cy(a), -V::cz(a));
+      double v;
+      if (!P.bb) v = (double)cv.get(a, nbr, (R)V::w(a));
+      else if (bits >> kSolidBit) v = 0.0;   // solid cells hold no fluid
+      else v = (double)pull_bb<LAT>(cv, a, bits, cell, nbr, (R)V::w(a));
+      f[(size_t)(s * V::Q + a) * P.cells + cell] = v;
+    }
   }
 }
 
 // mode 0: import canonical f (float64 [nc][Q][cells]);  mode 1: equilibrium of
 // rho0 [nc][cells] and u0 [D][cells] (u0 may be NULL).  The base of the offset
-// formats is the sum of the Q values stored at the cell.
+// formats is the sum of the Q values stored at the cell.  With walls the stored
+// direction a of a fluid cell y whose target y + e_a is solid is the population
+// that bounces back into y as the opposite direction (bit opp(a) of y's mask),
+// and solid cells store zeros.
 template <int LAT, int NC, int ST>
 __global__ __launch_bounds__(kBlock) void k_import(KParams P, Pops<ST> out, const double* __restrict__ f,
                                                   const double* __restrict__ rho0, const double* __restrict__ u0,
@@ -135,15 +156,21 @@ __global__ __launch_bounds__(kBlock) void k_import(KParams P, Pops<ST> out, cons
   unsigned cell;
   if (!launch_cell(P, 0, P.nplanes, &cell)) return;
   const Coord c = make_coord(cell, P);
+  const unsigned bits = P.bb ? P.bb[cell] : 0u;
+  const bool solid = (bits >> kSolidBit) != 0u;
 #pragma unroll 1
   for (int s = 0; s < NC; ++s) {
     double v[Q];
     double sum = 0.0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      const unsigned dst = c.at(V::cx(a), V::cy(a), V::cz(a));
-      if (mode == 0) {
-        v[a] = f[(size_t)(s * Q + a) * P.cells + dst];
+      const bool back = (bits >> V::opp(a)) & 1u;   // y + e_a solid: returns into y
+      const unsigned dst = back ? cell : c.at(V::cx(a), V::cy(a), V::cz(a));
+      const int ad = back ? V::opp(a) : a;          // canonical direction it becomes
+      if (solid) {
+        v[a] = 0.0;
+      } else if (mode == 0) {
+        v[a] = f[(size_t)(s * Q + ad) * P.cells + dst];
       } else {
         const double r = rho0[(size_t)s * P.cells + dst];
         double ux = 0.0, uy = 0.0, uz = 0.0;
@@ -152,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_import(KParams P, Pops<ST> out, cons
           uy = u0[(size_t)P.cells + dst];
           if (V::D == 3) uz = u0[(size_t)2 * P.cells + dst];
         }
-        v[a] = feq<LAT, double>(a, r, ux, uy, uz, ux * ux + uy * uy + uz * uz);
+        v[a] = feq<LAT, double>(ad, r, ux, uy, uz, ux * ux + uy * uy + uz * uz);
       }
       sum += v[a];
     }

@@ -33,9 +33,12 @@ struct lbm_ctx {
   hipStream_t aux;
   hipEvent_t* ev;
   int nev;
+  // solid walls: per-cell direction mask on the device (kp.bb points here when set)
+  unsigned* bb;
   ~lbm_ctx() {
     for (int k = 0; k < nev; ++k) hipEventDestroy(ev[k]);
     delete[] ev;
     if (aux) hipStreamDestroy(aux);
+    if (bb) hipFree(bb);
   }
 };

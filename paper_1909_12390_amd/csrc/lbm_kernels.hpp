@@ -27,7 +27,12 @@ struct KParams {
   double mrt_c[LBM_MAX_Q];         // MRT: (1 - rate) / squared norm of each moment row
   double accel[3];
   int* err;                        // device error flag (set to 1 on a domain violation)
+  // solid walls (null: none): per cell, bit a set when the source x - e_a of
+  // direction a is solid (halfway bounce-back), bit 31 when the cell itself is solid
+  const unsigned* bb = nullptr;
+  double psi_wall = 0.0;           // psi of solid cells in the force stencil (wetting)
 };
+constexpr unsigned kSolidBit = 31u;
 
 // Load / store one element at a 32-bit byte offset from an array base held in
 // scalar registers (used for psi).  Every array stays below 4 GiB (host check).
@@ -89,6 +94,10 @@ struct Pops<LBM_F64> {
     __device__ __forceinline__ double get(int a, unsigned idx, double) const {
       return bload(rf, idx * 8u, (unsigned)a * plane, 0.0);
     }
+    // per-lane direction plane: pbytes = direction * plane
+    __device__ __forceinline__ double get_at(unsigned idx, unsigned pbytes, double) const {
+      return bload(rf, idx * 8u + pbytes, 0u, 0.0);
+    }
     // all Q directions, direction a from cell src(a): loads first, then decode
     template <int Q, typename Src, typename W>
     __device__ __forceinline__ void get_all(Src src, double* out, W) const {
@@ -127,6 +136,9 @@ struct OffsetPops {
     unsigned plane;   // bytes per direction plane of r
     __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
       return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
+    }
+    __device__ __forceinline__ float get_at(unsigned idx, unsigned pbytes, float w) const {
+      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload(rr, idx * (unsigned)sizeof(H) + pbytes, 0u, H()));
     }
     __device__ __forceinline__ float get_row(int a, unsigned xo, unsigned ro, float w) const {
       return bload(rb, xo * 4u, ro * 4u, 0.0f) *
@@ -344,9 +356,19 @@ __device__ __forceinline__ double eos_psi(const KParams& P, const double* rb) {
 // Density of component s at the cell and its momentum contribution, summed in the
 // collision precision R (float64 for float64 storage; float32 for the offset
 // formats, whose decoded populations carry float32 precision), returned as float64.
+// Population of direction a arriving at cell `own` with walls: streamed from the
+// neighbour nbr = own - e_a, or, when bit a of the cell's wall mask is set (nbr is
+// solid), the cell's own post-collision population of the opposite direction
+// (halfway bounce-back; w_a equals the opposite direction's weight).
+template <int LAT, typename View, typename R>
+__device__ __forceinline__ R pull_bb(const View& cv, int a, unsigned bits, unsigned own, unsigned nbr, R w) {
+  const bool back = (bits >> a) & 1u;
+  return cv.get_at(back ? own : nbr, (unsigned)(back ? VS<LAT>::opp(a) : a) * cv.plane, w);
+}
+
 template <int LAT, int ST>
 __device__ __forceinline__ double pull_moments(const KParams& P, const Pops<ST>& in, int s, const Coord& c,
-                                               typename Pops<ST>::R* j) {
+                                               typename Pops<ST>::R* j, unsigned cell = 0, unsigned bits = 0) {
   using V = VS<LAT>;
   using R = typename Pops<ST>::R;
   const auto cv = in.comp(s, V::Q, P.cells);
@@ -354,7 +376,8 @@ __device__ __forceinline__ double pull_moments(const KParams& P, const Pops<ST>&
   R jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int a = 0; a < V::Q; ++a) {
-    const R v = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+    const unsigned nbr = c.at(-V::cx(a), -V::cy(a), -V::cz(a));
+    const R v = P.bb ? pull_bb<LAT>(cv, a, bits, cell, nbr, (R)V::w(a)) : cv.get(a, nbr, (R)V::w(a));
     acc += v;
     if (V::cx(a)) jx += (R)V::cx(a) * v;
     if (V::cy(a)) jy += (R)V::cy(a) * v;
@@ -602,6 +625,14 @@ __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* 
   unsigned cell;
   if (!launch_cell(P, plane0, nplanes, &cell)) return;
   const Coord c = make_coord(cell, P);
+  unsigned bits = 0;
+  if (P.bb) {
+    bits = P.bb[cell];
+    if (bits >> kSolidBit) {
+      psi[cell] = P.psi_wall;
+      return;
+    }
+  }
   double rb[NC];
 #pragma unroll
   for (int s = 0; s < NC; ++s) rb[s] = 0.0;
@@ -609,8 +640,14 @@ __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* 
   for (int s = 0; s < NC; ++s) {
     const auto cv = in.comp(s, V::Q, P.cells);
     R v[V::Q];
-    cv.template get_all<V::Q>([&](int a) { return c.at(-V::cx(a), -V::cy(a), -V::cz(a)); }, v,
-                              [](int a) { return (R)V::w(a); });
+    if (P.bb) {
+#pragma unroll
+      for (int a = 0; a < V::Q; ++a)
+        v[a] = pull_bb<LAT>(cv, a, bits, cell, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+    } else {
+      cv.template get_all<V::Q>([&](int a) { return c.at(-V::cx(a), -V::cy(a), -V::cz(a)); }, v,
+                                [](int a) { return (R)V::w(a); });
+    }
     R acc = 0;
 #pragma unroll
     for (int a = 0; a < V::Q; ++a) acc += v[a];
@@ -640,17 +677,30 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   const int s = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kCells));
   RowCoord c;
   bool in_row = false;
-  const bool valid = row_segment<V::D>(P, logical_block(), plane0, nplanes, (unsigned)lane, &c, &in_row) && in_row;
+  bool valid = row_segment<V::D>(P, logical_block(), plane0, nplanes, (unsigned)lane, &c, &in_row) && in_row;
   const auto cv = in.comp(s, Q, P.cells);
   const rsrc_t psr = make_rsrc(psi, (unsigned)P.cells * 8u);
+  unsigned bits = 0;
+  if (P.bb && valid) {         // walls: solid cells take no part (no collision, no store)
+    bits = P.bb[c.row(0, 0) + c.x(0)];
+    valid = !(bits >> kSolidBit);
+  }
   R f[Q];
   R rs = 0, jx = 0, jy = 0, jz = 0;
   double mass = 0.0;   // the component's mass, summed exactly (rs in float64 storage)
   double Fp[3] = {0.0, 0.0, 0.0};
   if (valid) {
+    if (P.bb) {
+      const unsigned own = c.row(0, 0) + c.x(0);
+#pragma unroll
+      for (int a = 0; a < Q; ++a)
+        f[a] = pull_bb<LAT>(cv, a, bits, own, c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a)), (R)V::w(a));
+    } else {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) f[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
+    }
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      f[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
       mass += (double)f[a];
       if (V::cx(a)) jx += (R)V::cx(a) * f[a];
       if (V::cy(a)) jy += (R)V::cy(a) * f[a];

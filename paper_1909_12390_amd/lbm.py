@@ -37,7 +37,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure",
             "lbm_batch_layout", "lbm_batch_init", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_check",
             "lbm_batch_box_errors", "lbm_batch_destroy", "lbm_adjoint_workspace", "lbm_step_adjoint",
-            "lbm_adjoint", "lbm_eos_param_grad", "lbm_set_gamma", "lbm_batch_set_gamma"]
+            "lbm_adjoint", "lbm_eos_param_grad", "lbm_set_gamma", "lbm_batch_set_gamma", "lbm_set_solid"]
 
 
 class LbmError(RuntimeError):
@@ -126,6 +126,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_eos_param_grad.argtypes = [POINTER(LbmMixture), c_double, dp, dp, dp, dp, dp]
         L.lbm_set_gamma.argtypes = [c_void_p, dp]
         L.lbm_batch_set_gamma.argtypes = [c_void_p, c_int, dp]
+        L.lbm_set_solid.argtypes = [c_void_p, c_void_p, c_double]
         for name in EXPORTED:
             f = getattr(L, name)
             if name not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy"):
@@ -289,11 +290,13 @@ class LbmContext:
 
     rho0: initial cell-volume densities (nc, *shape), float64 (NumPy or torch).
     u0  : optional initial velocity (D, *shape).
+    solid, psi_wall: optional solid-cell mask (*shape, bool) and the wetting psi of
+    the walls (lbm_set_solid), applied right after the initial state.
     """
 
     def __init__(self, mix: dict, lattice: str, shape, T, tau, beta, gamma, rho0, u0=None,
                  collision="bgk", forcing="guo", storage="f64", schedule="two_pass", mrt_s=None,
-                 accel=None, G=-1.0, slab_planes=0, device="cuda"):
+                 accel=None, G=-1.0, slab_planes=0, device="cuda", solid=None, psi_wall=0.0):
         import torch
         self.torch = torch
         self.lattice = lattice
@@ -321,6 +324,19 @@ class LbmContext:
         self._ctx = ctx
         self.stream.synchronize()     # the init kernel has read rho0_t / u0_t
         self._keep = None
+        if solid is not None:
+            self.set_solid(solid, psi_wall)
+
+    def set_solid(self, solid, psi_wall=0.0):
+        """Solid walls (halfway bounce-back, psi = psi_wall on solid cells); None
+        removes them.  Cells that stay fluid keep their populations."""
+        if solid is None:
+            _check(lib().lbm_set_solid(self._ctx, None, c_double(0.0)))
+            return
+        m = np.ascontiguousarray(np.asarray(solid, dtype=bool).astype(np.uint8))
+        if m.shape != self.shape:
+            raise ValueError(f"solid mask must have shape {self.shape}")
+        _check(lib().lbm_set_solid(self._ctx, c_void_p(m.ctypes.data), c_double(float(psi_wall))))
 
     def _to_device(self, a, shape):
         torch = self.torch

@@ -1,0 +1,206 @@
+"""Solid walls on the GPU (lbm_set_solid) against the oracle's wall model.
+
+* float64 storage matches the oracle to 1e-12 after 1 and 10 steps on ragged boxes
+  with a random porous mask, every collision x forcing, D2Q9 nc 1-3 and D3Q19;
+* lbm_moments reports zero density, velocity and pressure on solid cells and
+  psi_w there, the oracle's fields on fluid cells and its mass totals;
+* float32 / float16 offset storage stay within the reduced-precision budget of
+  the periodic step;
+* BLOCKED and OVERLAP schedules are bitwise equal to TWO_PASS with walls;
+* the GPU's Poiseuille profile is the exact parabola at (tau - 1/2)^2 = 3/16;
+* replacing the mask keeps the canonical populations of cells that stay fluid;
+* the adjoint refuses a context with walls.
+"""
+import numpy as np
+import pytest
+
+from cases import LAT, case, mrt_rates, oracle_params
+from oracle import lbm as olbm
+from oracle_backend import to_mixture
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPES = {"D2Q9": (45, 70), "D3Q19": (13, 14, 15)}
+
+
+def _lbm():
+    from paper_1909_12390_amd import lbm
+    return lbm
+
+
+def porous(shape, seed, frac=0.15):
+    return np.random.default_rng([7, seed]).uniform(size=shape) < frac
+
+
+def wall_psi(c):
+    """A wetting psi between the case's phases: 1.3 x psi of the box-corner state."""
+    m = to_mixture(c["mix"])
+    corner = c["rho0"][(slice(None),) + (0,) * len(c["shape"])]
+    return 1.3 * float(olbm.pseudo_potential(corner[:, None], c["T"], m, -1.0)[0])
+
+
+def rel_err(g, f):
+    return max(float(np.max(np.abs(g[s] - f[s])) / np.max(np.abs(f[s]))) for s in range(f.shape[0]))
+
+
+def setup(lattice, nc, seed, collision, forcing, storage="f64", schedule="two_pass", beta=1.7, slab=0):
+    c = case(lattice, nc, SHAPES[lattice], seed=seed, u_amp=0.01)
+    solid = porous(c["shape"], seed)
+    pw = wall_psi(c)
+    rates = mrt_rates(lattice, 0.8) if collision == "mrt" else None
+    prm = oracle_params(c, collision, forcing, mrt_s=rates, beta=beta)
+    prm.solid, prm.psi_wall = solid, pw
+    ctx = _lbm().LbmContext(c["mix"], lattice, c["shape"], c["T"], 0.8, beta, c["gamma"], c["rho0"], c["u0"],
+                            collision=collision, forcing=forcing, storage=storage, schedule=schedule,
+                            mrt_s=rates, slab_planes=slab, solid=solid, psi_wall=pw)
+    f0 = olbm.init_populations(c["rho0"], LAT[lattice], c["u0"])
+    f0[:, :, solid] = 0.0
+    return c, solid, prm, ctx, f0
+
+
+def oracle_steps(c, prm, lattice, f, n):
+    out = [f]
+    m = to_mixture(c["mix"])
+    for _ in range(n):
+        f = olbm.step(f, m, prm, LAT[lattice])
+        out.append(f)
+    return out
+
+
+@pytest.mark.parametrize("lattice,nc", [("D2Q9", 1), ("D2Q9", 2), ("D2Q9", 3), ("D3Q19", 2)])
+@pytest.mark.parametrize("collision,forcing", [("bgk", "guo"), ("bgk", "edm"), ("mrt", "guo"), ("mrt", "edm")])
+def test_f64_walls_match_oracle(lattice, nc, collision, forcing):
+    print(f"case walls f64 {lattice} nc={nc} {collision}+{forcing}", flush=True)
+    # beta 1.16 with exact-difference forcing (1.7 leaves the EOS domain next to the walls)
+    c, solid, prm, ctx, f0 = setup(lattice, nc, nc, collision, forcing, beta=1.16 if forcing == "edm" else 1.7)
+    ref = oracle_steps(c, prm, lattice, f0, 10)
+    g0 = ctx.get_populations().cpu().numpy()
+    assert rel_err(g0, ref[0]) < 1e-15
+    assert np.all(g0[:, :, solid] == 0.0)
+    ctx.step(1)
+    e1 = rel_err(ctx.get_populations().cpu().numpy(), ref[1])
+    ctx.step(9)
+    e10 = rel_err(ctx.get_populations().cpu().numpy(), ref[10])
+    ctx.check()
+    assert e1 < 1e-12 and e10 < 1e-12, (e1, e10)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_moments_with_walls(lattice):
+    print(f"case walls moments {lattice}", flush=True)
+    c, solid, prm, ctx, f0 = setup(lattice, 3, 21, "bgk", "guo")
+    ctx.step(4)
+    f = oracle_steps(c, prm, lattice, f0, 4)[-1]
+    m = ctx.moments()
+    ref = olbm.macroscopic(f, to_mixture(c["mix"]), prm, LAT[lattice])
+    rho = m["rho_s"].cpu().numpy()
+    u = m["u"].cpu().numpy()
+    p = m["p"].cpu().numpy()
+    psi = m["psi"].cpu().numpy()
+    assert np.all(rho[:, solid] == 0.0) and np.all(u[:, solid] == 0.0) and np.all(p[solid] == 0.0)
+    assert np.all(psi[solid] == prm.psi_wall)
+    fl = ~solid
+    assert np.max(np.abs(rho[:, fl] - ref["rho_s"][:, fl])) <= 1e-12 * np.max(ref["rho_s"])
+    assert np.max(np.abs(u[:, fl] - ref["u"][:, fl])) <= 1e-11 * max(np.max(np.abs(ref["u"])), 1e-6)
+    assert np.max(np.abs(p[fl] - ref["p"][fl])) <= 1e-12 * np.max(ref["p"])
+    assert np.max(np.abs(psi - ref["psi"])) <= 1e-12 * np.max(ref["psi"])
+    tot = olbm.totals(f, to_mixture(c["mix"]), prm, LAT[lattice])
+    assert np.allclose(m["mass"], tot["mass"], rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("storage,tol1,tol10", [("f32", 1e-6, 5e-6), ("f16", 1e-4, 2e-4)])
+def test_reduced_precision_walls(lattice, storage, tol1, tol10):
+    print(f"case walls {storage} {lattice}", flush=True)
+    c, solid, prm, ctx, f0 = setup(lattice, 3, 11, "mrt", "edm", storage=storage, beta=1.16)
+    ref = oracle_steps(c, prm, lattice, f0, 10)
+    ctx.step(1)
+    e1 = rel_err(ctx.get_populations().cpu().numpy(), ref[1])
+    ctx.step(9)
+    g = ctx.get_populations().cpu().numpy()
+    e10 = rel_err(g, ref[10])
+    ctx.check()
+    print(f"  {storage}: 1 step {e1:.2e}  10 steps {e10:.2e}", flush=True)
+    assert np.all(g[:, :, solid] == 0.0)
+    assert e1 < tol1 and e10 < tol10, (e1, e10)
+
+
+@pytest.mark.parametrize("lattice,slab", [("D2Q9", 7), ("D3Q19", 4)])
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+@pytest.mark.parametrize("schedule", ["blocked", "overlap"])
+def test_schedules_with_walls_equal_two_pass(lattice, slab, storage, schedule):
+    print(f"case walls {schedule} {lattice} {storage}", flush=True)
+    *_, a, _ = setup(lattice, 3, 9, "mrt", "edm", storage=storage, beta=1.16)
+    *_, b, _ = setup(lattice, 3, 9, "mrt", "edm", storage=storage, schedule=schedule, beta=1.16, slab=slab)
+    a.step(7)
+    b.step(7)
+    fa = a.get_populations().cpu().numpy()
+    fb = b.get_populations().cpu().numpy()
+    a.check()
+    b.check()
+    assert np.array_equal(fa, fb)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_poiseuille_profile_on_gpu(lattice):
+    """Channel of H = 8 fluid rows between solid rows, body acceleration g along x,
+    BGK + Guo at tau = 1/2 + sqrt(3/16): u(d) = g d (H - d) / (2 nu) exactly."""
+    print(f"case walls poiseuille {lattice}", flush=True)
+    from cases import pure_water_mix
+    mix = pure_water_mix()
+    m = to_mixture(mix)
+    T = 0.9 * float(m.Tc[0])
+    H = 8
+    shape = (H + 2, 4) if lattice == "D2Q9" else (3, H + 2, 4)
+    solid = np.zeros(shape, dtype=bool)
+    solid[..., 0, :] = True
+    solid[..., H + 1, :] = True
+    rho0 = 0.6
+    psi0 = float(olbm.pseudo_potential(np.array([[rho0]]), T, m, -1.0)[0])
+    tau = 0.5 + np.sqrt(3.0 / 16.0)
+    g = 1e-6
+    acc = np.zeros(2 if lattice == "D2Q9" else 3)
+    acc[0] = g
+    ctx = _lbm().LbmContext(mix, lattice, shape, T, tau, 1.5, [1.0], np.full((1,) + shape, rho0),
+                            collision="bgk", forcing="guo", storage="f64", accel=acc, solid=solid,
+                            psi_wall=psi0)
+    ctx.step(3000)
+    ctx.check()
+    u = ctx.moments()["u"].cpu().numpy()
+    nu = (tau - 0.5) / 3.0
+    d = np.arange(1, H + 1) - 0.5
+    exact = g * d * (H - d) / (2.0 * nu)
+    ux = np.moveaxis(u[0], -2, 0)[1:H + 1].reshape(H, -1)
+    assert np.max(np.abs(ux - exact[:, None])) <= 1e-9 * exact.max()
+    assert np.max(np.abs(u[1])) <= 1e-9 * exact.max()
+
+
+def test_replacing_the_mask_keeps_fluid_populations():
+    print("case walls replace mask", flush=True)
+    c, solid, prm, ctx, f0 = setup("D2Q9", 2, 31, "bgk", "edm", beta=1.16)
+    ctx.step(3)
+    before = ctx.get_populations().cpu().numpy()
+    solid2 = solid.copy()
+    solid2[10:14, 20:30] = True           # add a block of solid
+    ctx.set_solid(solid2, prm.psi_wall)
+    after = ctx.get_populations().cpu().numpy()
+    expect = before.copy()
+    expect[:, :, solid2] = 0.0
+    assert np.array_equal(after, expect)
+    # and the run continues as the oracle does from that state
+    prm.solid = solid2
+    ref = oracle_steps(c, prm, "D2Q9", expect, 2)[-1]
+    ctx.step(2)
+    ctx.check()
+    assert rel_err(ctx.get_populations().cpu().numpy(), ref) < 1e-12
+
+
+def test_adjoint_refuses_walls():
+    print("case walls adjoint refused", flush=True)
+    lbm = _lbm()
+    c, solid, prm, ctx, f0 = setup("D2Q9", 2, 31, "bgk", "edm", beta=1.16)
+    h = np.zeros((2, 9) + c["shape"])
+    with pytest.raises(lbm.LbmError) as e:
+        ctx.step_adjoint(h)
+    assert e.value.code == lbm.LBM_ERR_UNSUPPORTED
