@@ -280,6 +280,49 @@ def adjoint_section(args, torch, lbm, inputs):
     return res
 
 
+def walls_section(args, torch, lbm, inputs, cfg, make, timed, modes_res):
+    """The headline drop inside a synthetic porous medium (random overlapping
+    spheres, periodic) with halfway bounce-back walls and psi_w midway between the
+    vapour's and the liquid's psi (psi_w at the vapour's repels the liquid cut by
+    the spheres out of the EOS domain in the first step, oracle and GPU alike):
+    time per step against the same step without walls, float16 and float64
+    storage; throughput counted over all cells and over the fluid cells."""
+    solid = inputs.porous_spheres(cfg.shape, args.walls_solid, args.walls_radius, seed=0)
+    probe = make("f64", "two_pass")
+    psi = probe.moments(fields=True, totals=False)["psi"]
+    h = cfg.shape[0] // 2
+    psi_w = 0.5 * float(psi[0, 0, 0].item() + psi[h, h, h].item())
+    del probe, psi
+    torch.cuda.empty_cache()
+    fluid = int((~solid).sum())
+    res = {"workload": f"{cfg.nc}-component D3Q19 {cfg.shape[0]}^3 drop in random overlapping spheres "
+                       f"(radius {args.walls_radius}, solid fraction {solid.mean():.3f}), halfway bounce-back, "
+                       f"psi_w midway between the phases' psi, two_pass schedule",
+           "solid_fraction": float(solid.mean()), "psi_wall": psi_w, "steps": args.walls_steps}
+    for m in ("f16", "f64"):
+        c = make(m, "two_pass")
+        c.set_solid(solid, psi_w)
+        m0 = c.moments(fields=False)["mass"]
+        w, k = timed(c, args.walls_steps, args.warmup, args.diag_every)
+        drift = float(np.max(np.abs(c.moments(fields=False)["mass"] / m0 - 1)))
+        ms = w / args.walls_steps
+        r = {"ms_per_step": ms, "kernel_ms": [x / args.walls_steps for x in k],
+             "mlups_x_comp_all_cells": cfg.cells * cfg.nc / (ms * 1e-3) / 1e6,
+             "mlups_x_comp_fluid_cells": fluid * cfg.nc / (ms * 1e-3) / 1e6, "mass_drift_rel": drift}
+        ref = modes_res.get(f"{m}/two_pass") if modes_res else None
+        if ref is None:
+            c0 = make(m, "two_pass")
+            w0, _ = timed(c0, args.walls_steps, args.warmup, args.diag_every)
+            ref = {"ms_per_step": w0 / args.walls_steps}
+            del c0
+        r["no_walls_ms_per_step"] = ref["ms_per_step"]
+        r["time_ratio_vs_no_walls"] = ms / ref["ms_per_step"]
+        res[m] = r
+        del c
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +346,9 @@ def main():
     ap.add_argument("--batch-precision-steps", type=int, default=10000)
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="adjoint section: steps (0 = skip)")
     ap.add_argument("--adjoint-every", type=int, default=100, help="adjoint section: checkpoint interval")
+    ap.add_argument("--walls-steps", type=int, default=200, help="porous-medium walls section: steps (0 = skip)")
+    ap.add_argument("--walls-solid", type=float, default=0.3, help="walls section: solid fraction")
+    ap.add_argument("--walls-radius", type=float, default=6.0, help="walls section: sphere radius (cells)")
     args = ap.parse_args()
 
     if args.cpu_baseline_worker:
@@ -395,8 +441,8 @@ def main():
         out["copy_GBps_2GiB"] = copy_bandwidth(torch)
 
     modes = [m for m in args.modes.split(",") if m]
+    res = {}
     if modes:
-        res = {}
         for m in modes:
             for sched in ("two_pass", "blocked", "overlap"):
                 c = make(m, sched)
@@ -430,6 +476,9 @@ def main():
         prec["f64_liquid_x"] = fr["f64"]["liquid"].tolist()
         prec["f64_vapor_y"] = fr["f64"]["vapor"].tolist()
         out["precision"] = prec
+
+    if args.walls_steps > 0:
+        out["walls"] = walls_section(args, torch, lbm, inputs, cfg, make, timed, res)
 
     if args.batch_boxes > 0:
         out["batched"] = batched_section(args, torch, lbm, inputs)

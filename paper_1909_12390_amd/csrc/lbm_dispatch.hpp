@@ -53,7 +53,7 @@ inline Pops<LBM_F16_OFS> make_pops<LBM_F16_OFS>(const Bufs& b) {
 template <int LAT, int NC, int ST, int COLL, int FORC>
 struct OpsImpl {
   static void psi(const KParams& P, const Bufs& in, const StepScratch& sc, int plane0, int np, hipStream_t st) {
-    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(nblocks_for(np * P.plane_cells)), dim3(kBlock), 0, st, P,
+    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(psi_blocks(P, np, VS<LAT>::D)), dim3(kBlock), 0, st, P,
                        make_pops<ST>(in), sc.psi, plane0, np);
   }
   static void collide(const KParams& P, const Bufs& in, const Bufs& out, const StepScratch& sc, int plane0,
@@ -67,8 +67,8 @@ struct OpsImpl {
   static void moments(const KParams& P, const Bufs& in, const StepScratch& sc, double* rho, double* u, double* p,
                       double* psi_out, double* partials, hipStream_t st) {
     const int nb = nblocks_for(P.cells);
-    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(nb), dim3(kBlock), 0, st, P, make_pops<ST>(in), sc.psi, 0,
-                       P.nplanes);
+    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(psi_blocks(P, P.nplanes, VS<LAT>::D)), dim3(kBlock), 0, st, P,
+                       make_pops<ST>(in), sc.psi, 0, P.nplanes);
     hipLaunchKernelGGL((k_moments<LAT, NC, ST>), dim3(nb), dim3(kBlock), 0, st, P, make_pops<ST>(in),
                        (const double*)sc.psi, rho, u, p, psi_out, partials);
   }

@@ -134,6 +134,8 @@ struct OffsetPops {
   struct View {
     rsrc_t rb, rr;
     unsigned plane;   // bytes per direction plane of r
+    const float* bp;  // the base array itself (wavefront-uniform scalar loads)
+    using Elem = H;
     __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
       return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
     }
@@ -199,7 +201,7 @@ struct OffsetPops {
   __device__ __forceinline__ View comp(int s, int Q, int cells) const {
     const unsigned plane = (unsigned)cells * (unsigned)sizeof(H);
     return View{make_rsrc(base + (size_t)s * cells, (unsigned)cells * 4u),
-                make_rsrc(r + (size_t)s * Q * cells, (unsigned)Q * plane), plane};
+                make_rsrc(r + (size_t)s * Q * cells, (unsigned)Q * plane), plane, base + (size_t)s * cells};
   }
   static __device__ __forceinline__ H enc(float v) {
     if constexpr (std::is_same<H, __half>::value) return __float2half_rn(v);
@@ -248,6 +250,7 @@ __device__ __forceinline__ Coord make_coord(unsigned cell, const KParams& P) {
 struct RowCoord {
   unsigned xs[3];          // per lane: x-1, x, x+1
   unsigned ys[3], zs[3];   // uniform: (y+dy) nx and (z+dz) nx ny, dy, dz in -1..1
+  unsigned x0;             // uniform: x of lane 0
   __device__ __forceinline__ unsigned row(int dy, int dz) const { return zs[dz + 1] + ys[dy + 1]; }
   __device__ __forceinline__ unsigned x(int dx) const { return xs[dx + 1]; }
 };
@@ -273,7 +276,8 @@ __device__ __forceinline__ bool row_segment(const KParams& P, unsigned seg, int 
     if (y >= ny) y -= ny;
     z = 0;
   }
-  const unsigned x = sx * 64u + lane;
+  c->x0 = sx * 64u;
+  const unsigned x = c->x0 + lane;
   *in_row = x < nx;
   const unsigned xx = *in_row ? x : 0u;
   c->xs[0] = xx == 0 ? nx - 1 : xx - 1;
@@ -616,17 +620,96 @@ __device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& 
 // kernels
 // ---------------------------------------------------------------------------
 
+// Wavefront lane shifts (DPP wave_shr:1 / wave_shl:1): lane i takes lane i - 1
+// (resp. i + 1); lane 0 (resp. 63), which has no source lane, keeps `fill`.
+// Every lane of the wavefront must be active.
+__device__ __forceinline__ float lane_from_left(float v, float fill) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill),
+                                                               __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_from_right(float v, float fill) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill),
+                                                               __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+
+// Source rows of a pull: (dy, dz) = (-c_y, -c_z) as index (dy + 1) + 3 (dz + 1).
+template <int LAT>
+__host__ __device__ constexpr int pull_row(int a) {
+  return (1 - VS<LAT>::cy(a)) + 3 * (1 - VS<LAT>::cz(a));
+}
+template <int LAT>
+__host__ __device__ constexpr bool row_used(int r) {
+  for (int a = 0; a < VS<LAT>::Q; ++a)
+    if (pull_row<LAT>(a) == r) return true;
+  return false;
+}
+template <int LAT>
+__host__ __device__ constexpr bool row_shifted(int r) {
+  for (int a = 0; a < VS<LAT>::Q; ++a)
+    if (pull_row<LAT>(a) == r && VS<LAT>::cx(a) != 0) return true;
+  return false;
+}
+
+// Offset storage, row-structured pull of one component (no walls): the stored
+// base is one value per cell, so the bases of the Q source cells come from one
+// vector load per source row at x; x - 1 and x + 1 follow by lane shifts, and
+// the two values past the wavefront's ends (x0 - 1 and x0 + 64, periodic) from
+// wavefront-uniform scalar loads.  In a row shorter than the wavefront the lanes
+// past its end hold x = 0, so the last cell's right neighbour is the first cell,
+// as periodicity requires.  All lanes must be active; f gets the decoded pulls.
+template <int LAT, typename View>
+__device__ __forceinline__ void pull_row_offset(const View& cv, const RowCoord& c, unsigned nx, float* f) {
+  using V = VS<LAT>;
+  constexpr int Q = V::Q;
+  using H = typename View::Elem;
+  const unsigned xl = c.x0 == 0 ? nx - 1 : c.x0 - 1;
+  const unsigned xr = c.x0 + 64u < nx ? c.x0 + 64u : 0u;
+  float bq[9], hl[9], hr[9], rq[Q];
+  static_for<0, 9>([&](auto Rr) {
+    constexpr int r = decltype(Rr)::value;
+    if constexpr (row_used<LAT>(r)) {
+      const unsigned ro = c.row(r % 3 - 1, r / 3 - 1);
+      bq[r] = bload(cv.rb, c.x(0) * 4u, ro * 4u, 0.0f);
+      if constexpr (row_shifted<LAT>(r)) {
+        hl[r] = cv.bp[ro + xl];
+        hr[r] = cv.bp[ro + xr];
+      }
+    }
+  });
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+    rq[a] = bload(cv.rr, c.x(-V::cx(a)) * (unsigned)sizeof(H),
+                  (unsigned)a * cv.plane + c.row(-V::cy(a), -V::cz(a)) * (unsigned)sizeof(H), H());
+  __builtin_amdgcn_sched_barrier(0);   // every load ahead of the shifts and the decode
+  static_for<0, Q>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    constexpr int r = pull_row<LAT>(a);
+    float b;
+    if constexpr (V::cx(a) == 0) b = bq[r];
+    else if constexpr (V::cx(a) > 0) b = lane_from_left(bq[r], hl[r]);   // source x - 1
+    else b = lane_from_right(bq[r], hr[r]);                              // source x + 1
+    f[a] = b * ((float)V::w(a) + rq[a]);
+  });
+}
+
 // pass 1: densities -> EOS -> psi on planes [plane0, plane0 + nplanes)
+// Each wavefront covers 64 cells of one row (as in the collide pass): segment
+// logical_block() * (kBlock / 64) + wavefront; see psi_blocks for the grid.
 template <int LAT, int NC, int ST>
 __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* __restrict__ psi, int plane0,
                                                int nplanes) {
   using V = VS<LAT>;
   using R = typename Pops<ST>::R;
-  unsigned cell;
-  if (!launch_cell(P, plane0, nplanes, &cell)) return;
-  const Coord c = make_coord(cell, P);
+  constexpr int Q = V::Q;
+  const unsigned lane = threadIdx.x & 63u;
+  const unsigned seg = logical_block() * (kBlock / 64) + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  RowCoord c;
+  bool in_row = false;
+  if (!row_segment<V::D>(P, seg, plane0, nplanes, lane, &c, &in_row)) return;   // uniform per wavefront
+  const unsigned cell = c.row(0, 0) + c.x(0);
   unsigned bits = 0;
   if (P.bb) {
+    if (!in_row) return;
     bits = P.bb[cell];
     if (bits >> kSolidBit) {
       psi[cell] = P.psi_wall;
@@ -638,24 +721,33 @@ __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* 
   for (int s = 0; s < NC; ++s) rb[s] = 0.0;
 #pragma unroll 1
   for (int s = 0; s < NC; ++s) {
-    const auto cv = in.comp(s, V::Q, P.cells);
-    R v[V::Q];
+    const auto cv = in.comp(s, Q, P.cells);
+    R v[Q];
     if (P.bb) {
 #pragma unroll
-      for (int a = 0; a < V::Q; ++a)
-        v[a] = pull_bb<LAT>(cv, a, bits, cell, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+      for (int a = 0; a < Q; ++a)
+        v[a] = pull_bb<LAT>(cv, a, bits, cell, c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a)), (R)V::w(a));
+    } else if constexpr (ST != LBM_F64) {
+      pull_row_offset<LAT>(cv, c, (unsigned)P.nx, v);   // all lanes active here (no walls)
     } else {
-      cv.template get_all<V::Q>([&](int a) { return c.at(-V::cx(a), -V::cy(a), -V::cz(a)); }, v,
-                                [](int a) { return (R)V::w(a); });
+#pragma unroll
+      for (int a = 0; a < Q; ++a) v[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
     }
     R acc = 0;
 #pragma unroll
-    for (int a = 0; a < V::Q; ++a) acc += v[a];
+    for (int a = 0; a < Q; ++a) acc += v[a];
 #pragma unroll
     for (int t = 0; t < NC; ++t)
       if (t == s) rb[t] = (double)acc;
   }
+  if (!in_row) return;
   psi[cell] = eos_psi<NC>(P, rb);
+}
+
+// workgroups of k_psi for planes [plane0, plane0 + np): kBlock / 64 row segments each
+inline unsigned psi_blocks(const KParams& P, int np, int D) {
+  const unsigned segs = (unsigned)np * (D == 3 ? (unsigned)P.ny : 1u) * (((unsigned)P.nx + 63u) / 64u);
+  return xcd_grid((segs + kBlock / 64 - 1) / (kBlock / 64));
 }
 
 // pass 2: a block is 64 cells x NC wavefronts, wavefront s working on component s.
@@ -677,7 +769,9 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   const int s = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kCells));
   RowCoord c;
   bool in_row = false;
-  bool valid = row_segment<V::D>(P, logical_block(), plane0, nplanes, (unsigned)lane, &c, &in_row) && in_row;
+  // a segment past the launch's range: the whole workgroup leaves (uniform)
+  if (!row_segment<V::D>(P, logical_block(), plane0, nplanes, (unsigned)lane, &c, &in_row)) return;
+  bool valid = in_row;
   const auto cv = in.comp(s, Q, P.cells);
   const rsrc_t psr = make_rsrc(psi, (unsigned)P.cells * 8u);
   unsigned bits = 0;
@@ -689,13 +783,16 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   R rs = 0, jx = 0, jy = 0, jz = 0;
   double mass = 0.0;   // the component's mass, summed exactly (rs in float64 storage)
   double Fp[3] = {0.0, 0.0, 0.0};
+  if constexpr (ST != LBM_F64) {
+    if (!P.bb) pull_row_offset<LAT>(cv, c, (unsigned)P.nx, f);   // all lanes (lane shifts)
+  }
   if (valid) {
     if (P.bb) {
       const unsigned own = c.row(0, 0) + c.x(0);
 #pragma unroll
       for (int a = 0; a < Q; ++a)
         f[a] = pull_bb<LAT>(cv, a, bits, own, c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a)), (R)V::w(a));
-    } else {
+    } else if constexpr (ST == LBM_F64) {
 #pragma unroll
       for (int a = 0; a < Q; ++a) f[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
     }

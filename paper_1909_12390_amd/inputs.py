@@ -284,6 +284,31 @@ def adjoint_target(cfg: Config, amplitude=0.02, seed=1):
     return t / t.sum()
 
 
+def porous_spheres(shape, solid_fraction=0.3, radius=6.0, seed=0):
+    """A synthetic porous medium: seeded random overlapping spheres (disks in 2-D)
+    of the given radius, periodic, added until at least solid_fraction of the cells
+    are solid.  Boolean mask of the box shape (solid = True)."""
+    rng = rng_for(7, seed)
+    shape = tuple(int(n) for n in shape)
+    solid = np.zeros(shape, dtype=bool)
+    r = float(radius)
+    k = int(np.ceil(r))
+    offs = np.arange(-k, k + 1)
+    while solid.mean() < solid_fraction:
+        c = [rng.uniform(0.0, n) for n in shape]
+        idx, d2 = [], 0.0
+        for ax, (n, cc) in enumerate(zip(shape, c)):
+            i = (np.floor(cc).astype(int) + offs) % n
+            d = (np.floor(cc) + offs) - cc
+            sh = [1] * len(shape)
+            sh[ax] = -1
+            d2 = d2 + (d * d).reshape(sh)
+            idx.append(i)
+        block = np.ix_(*idx)
+        solid[block] |= d2 <= r * r
+    return solid
+
+
 BOX_SIDES = (32, 48, 64, 96, 128)
 
 

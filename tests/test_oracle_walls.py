@@ -185,3 +185,24 @@ def test_all_fluid_mask_is_periodic_step(lat):
     a = lbm.step(f, mix, lbm.StepParams(**base), lat)
     b = lbm.step(f, mix, lbm.StepParams(**base, solid=np.zeros(shape, dtype=bool), psi_wall=0.7), lat)
     assert np.array_equal(a, b)
+
+
+def test_porous_medium_generator():
+    """Seeded: same mask twice; at least the requested solid fraction and not far
+    past it; spheres wrap across the periodic faces (a solid cell on a face has a
+    solid neighbour on the opposite face when its sphere straddles it)."""
+    from paper_1909_12390_amd import inputs
+    a = inputs.porous_spheres((40, 44, 48), 0.3, 4.0, seed=3)
+    b = inputs.porous_spheres((40, 44, 48), 0.3, 4.0, seed=3)
+    assert np.array_equal(a, b)
+    assert 0.3 <= a.mean() < 0.33
+    # every solid cell lies within the radius of some sphere: its connected solid
+    # region is at least a sphere's size, so no isolated single solid cells
+    from itertools import product
+    iso = 0
+    for idx in zip(*np.nonzero(a)):
+        nb = sum(a[tuple((np.array(idx) + np.array(d)) % a.shape)] for d in product((-1, 0, 1), repeat=3)) - 1
+        iso += nb == 0
+    assert iso == 0
+    wrap = np.logical_and(a[0], a[-1]).sum() + np.logical_and(a[:, 0], a[:, -1]).sum()
+    assert wrap > 0
