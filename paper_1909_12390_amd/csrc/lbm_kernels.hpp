@@ -707,15 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* 
   bool in_row = false;
   if (!row_segment<V::D>(P, seg, plane0, nplanes, lane, &c, &in_row)) return;   // uniform per wavefront
   const unsigned cell = c.row(0, 0) + c.x(0);
-  unsigned bits = 0;
-  if (P.bb) {
-    if (!in_row) return;
-    bits = P.bb[cell];
-    if (bits >> kSolidBit) {
-      psi[cell] = P.psi_wall;
-      return;
-    }
-  }
+  const unsigned bits = P.bb ? P.bb[cell] : 0u;   // walls: per-cell direction mask
   double rb[NC];
 #pragma unroll
   for (int s = 0; s < NC; ++s) rb[s] = 0.0;
@@ -723,12 +715,18 @@ __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* 
   for (int s = 0; s < NC; ++s) {
     const auto cv = in.comp(s, Q, P.cells);
     R v[Q];
-    if (P.bb) {
+    // every lane pulls (lanes past the row end at x = 0; all addresses in range)
+    if (P.bb) {   // walls: halfway bounce-back for pulls whose source is solid; fluid cells only
+      if (in_row && !(bits >> kSolidBit)) {
 #pragma unroll
-      for (int a = 0; a < Q; ++a)
-        v[a] = pull_bb<LAT>(cv, a, bits, cell, c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a)), (R)V::w(a));
+        for (int a = 0; a < Q; ++a)
+          v[a] = pull_bb<LAT>(cv, a, bits, cell, c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a)), (R)V::w(a));
+      } else {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) v[a] = 0;
+      }
     } else if constexpr (ST != LBM_F64) {
-      pull_row_offset<LAT>(cv, c, (unsigned)P.nx, v);   // all lanes active here (no walls)
+      pull_row_offset<LAT>(cv, c, (unsigned)P.nx, v);
     } else {
 #pragma unroll
       for (int a = 0; a < Q; ++a) v[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
@@ -741,7 +739,8 @@ __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* 
       if (t == s) rb[t] = (double)acc;
   }
   if (!in_row) return;
-  psi[cell] = eos_psi<NC>(P, rb);
+  if (bits >> kSolidBit) psi[cell] = P.psi_wall;   // solid: the wall's psi, no EOS
+  else psi[cell] = eos_psi<NC>(P, rb);
 }
 
 // workgroups of k_psi for planes [plane0, plane0 + np): kBlock / 64 row segments each
@@ -774,28 +773,29 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   bool valid = in_row;
   const auto cv = in.comp(s, Q, P.cells);
   const rsrc_t psr = make_rsrc(psi, (unsigned)P.cells * 8u);
-  unsigned bits = 0;
-  if (P.bb && valid) {         // walls: solid cells take no part (no collision, no store)
-    bits = P.bb[c.row(0, 0) + c.x(0)];
-    valid = !(bits >> kSolidBit);
-  }
+  const unsigned own = c.row(0, 0) + c.x(0);
+  const unsigned bits = P.bb ? P.bb[own] : 0u;   // walls: per-cell direction mask
   R f[Q];
   R rs = 0, jx = 0, jy = 0, jz = 0;
   double mass = 0.0;   // the component's mass, summed exactly (rs in float64 storage)
   double Fp[3] = {0.0, 0.0, 0.0};
-  if constexpr (ST != LBM_F64) {
-    if (!P.bb) pull_row_offset<LAT>(cv, c, (unsigned)P.nx, f);   // all lanes (lane shifts)
-  }
-  if (valid) {
-    if (P.bb) {
-      const unsigned own = c.row(0, 0) + c.x(0);
+  // every lane pulls (lanes past the row end at x = 0; all addresses in range)
+  if (P.bb) {
+    // walls: solid cells take no part (no collision, no store); a pull whose
+    // source is solid reads the cell's own opposite population (halfway bounce-back)
+    valid = valid && !(bits >> kSolidBit);
+    if (valid) {
 #pragma unroll
       for (int a = 0; a < Q; ++a)
         f[a] = pull_bb<LAT>(cv, a, bits, own, c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a)), (R)V::w(a));
-    } else if constexpr (ST == LBM_F64) {
-#pragma unroll
-      for (int a = 0; a < Q; ++a) f[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
     }
+  } else if constexpr (ST != LBM_F64) {
+    pull_row_offset<LAT>(cv, c, (unsigned)P.nx, f);
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) f[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
+  }
+  if (valid) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       mass += (double)f[a];
