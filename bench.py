@@ -62,18 +62,19 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_key: str):
-    """HBM bytes per launch recorded from rocprofv3 FETCH_SIZE/WRITE_SIZE runs for
-    this kernel, or None if absent or taken on different kernel sources."""
+def measured_profile(kernel_key: str):
+    """The profile record of this kernel (HBM bytes per launch from rocprofv3
+    FETCH_SIZE/WRITE_SIZE runs, pipe busy fractions from its counter runs), or {}
+    if absent or taken on different kernel sources."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return {}
     ent = rec.get(kernel_key)
     if not ent or ent.get("source_sha") != kernel_source_sha():
-        return None
-    return ent.get("bytes_per_launch")
+        return {}
+    return ent
 
 
 def phase_mole_fractions(rho_s, M, geometry, shape):
@@ -410,7 +411,8 @@ def main():
     bytes_launch = b_alg_collide(nc, Q, args.storage) * cells
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     key = f"{kname}:{args.schedule}:{args.storage}:D3Q19:nc{nc}:{side}^3"
-    traffic = measured_traffic(key)
+    prof = measured_profile(key)
+    traffic = prof.get("bytes_per_launch")
     del ctx
     torch.cuda.empty_cache()
 
@@ -430,13 +432,18 @@ def main():
                      "traffic": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
                      "kernel": kname, "kernel_ms_per_step": avg_ms,
                      "kernel_alg_bytes_per_cell": b_alg_collide(nc, Q, args.storage),
-                     "cells_per_step": cells, "traffic_bytes_per_step": traffic},
+                     "cells_per_step": cells, "traffic_bytes_per_step": traffic,
+                     "pipe_busy": prof.get("pipe_busy")},
         "step_alg_GBps": b_alg(nc, Q, args.storage) * cells / (ms_per_step * 1e-3) / 1e9,
         "step_alg_bytes_per_cell": b_alg(nc, Q, args.storage),
         "kernel_ms_per_step": {"psi": kms[0] / args.steps, "collide": kms[1] / args.steps},
         "mass_drift_rel": mass_drift,
     }
 
+    def progress(what):
+        print(f"bench: {what} done", file=sys.stderr, flush=True)
+
+    progress("headline")
     if not args.no_copy:
         out["copy_GBps_2GiB"] = copy_bandwidth(torch)
 
@@ -458,6 +465,7 @@ def main():
             for key in res:
                 res[key]["speedup_vs_f64_two_pass"] = ref["ms_per_step"] / res[key]["ms_per_step"]
         out["modes"] = res
+        progress("modes")
 
     if args.precision_steps > 0:
         prec = {"steps": args.precision_steps}
@@ -476,18 +484,23 @@ def main():
         prec["f64_liquid_x"] = fr["f64"]["liquid"].tolist()
         prec["f64_vapor_y"] = fr["f64"]["vapor"].tolist()
         out["precision"] = prec
+        progress("precision")
 
     if args.walls_steps > 0:
         out["walls"] = walls_section(args, torch, lbm, inputs, cfg, make, timed, res)
+        progress("walls")
 
     if args.batch_boxes > 0:
         out["batched"] = batched_section(args, torch, lbm, inputs)
+        progress("batched")
 
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_section(args, torch, lbm, inputs)
+        progress("adjoint")
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_side, args.cpu_steps)
+        progress("cpu baseline")
     print(json.dumps(out), flush=True)
 
 
