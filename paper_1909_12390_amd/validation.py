@@ -534,6 +534,111 @@ def run_oscillation(sizes=(200, 300, 400, 600, 800), steps=None, sample_every=50
     return {"steps": steps, "sample_every": sample_every, "beta": beta, "drops": out}
 
 
+# ---------------------------------------------------------------------------
+# Wetting: contact angle of a drop on a wall against psi_w (solid walls are a
+# design of this build; the paper's porous-media motivation, Sec. 1)
+# ---------------------------------------------------------------------------
+
+# the single-component fluid of Sec. 4.1 and its Maxwell densities at T = 0.9 Tc
+PURE = {"a": np.array([2.0 / 49.0]), "b": np.array([2.0 / 21.0]), "omega": np.array([0.344]),
+        "M": np.array([1.0]), "k": np.zeros((1, 1)), "R": 1.0}
+MAXWELL_09 = (5.90796, 0.58007)
+
+
+def sessile_case(nx=160, ny=80, R0=25.0, W=4.0, floor=3):
+    """A drop resting on a solid floor (rows 0 .. floor-1, periodic in x and y, so
+    the floor is a slab with vapour below it as well): a half disk of radius R0
+    centred on the wall surface y = floor - 1/2, tanh profile of width W."""
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    yw = floor - 0.5
+    r = np.sqrt((x - nx / 2.0) ** 2 + (y - yw) ** 2)
+    rl, rv = MAXWELL_09
+    rho = 0.5 * (rl + rv) - 0.5 * (rl - rv) * np.tanh(2.0 * (r - R0) / W)
+    solid = np.zeros((ny, nx), dtype=bool)
+    solid[:floor] = True
+    rho[solid] = rv
+    return {"rho0": rho[None], "solid": solid, "wall_y": yw, "shape": (ny, nx)}
+
+
+def _crossing(prof, level, start):
+    """First fractional index >= start where prof falls below level."""
+    for i in range(start + 1, len(prof)):
+        if prof[i - 1] >= level > prof[i]:
+            return i - 1 + (prof[i - 1] - level) / (prof[i - 1] - prof[i])
+    raise ValueError("no crossing")
+
+
+def contact_angle(rho, wall_y, base_offset=3.0):
+    """Angle (degrees, measured through the liquid) of the circle through the
+    drop's top and its two level crossings base_offset above the wall surface,
+    where it meets the wall: cos(theta) = (wall_y - y_c) / R.  The level is the
+    mean of the drop's interior density (the largest on the centre column; next
+    to a repellent wall the liquid is depleted) and the far-vapour density."""
+    ny, nx = rho.shape
+    cx = nx // 2
+    y0 = int(np.ceil(wall_y))
+    col = rho[:, cx]
+    liquid = float(np.max(col[y0:]))
+    vapour = rho[y0 + (ny - y0) // 2, 0]        # mid-height of the fluid, far from the drop
+    level = 0.5 * (liquid + vapour)
+    top = _crossing(col, level, y0)
+    yb = wall_y + base_offset
+    j = int(np.floor(yb))
+    row = rho[j] + (yb - j) * (rho[j + 1] - rho[j])
+    right = _crossing(row, level, cx)
+    left = _crossing(row[::-1], level, nx - 1 - cx)
+    half = 0.5 * (right - (nx - 1 - left))
+    hgt = top - yb
+    R = (half * half + hgt * hgt) / (2.0 * hgt)
+    yc = top - R
+    c = np.clip((wall_y - yc) / R, -1.0, 1.0)
+    return {"theta_deg": float(np.degrees(np.arccos(c))), "R": float(R), "top": float(top), "half_width": float(half),
+            "liquid": float(liquid), "vapour": float(vapour)}
+
+
+def run_contact_angles(psi_fracs=(0.1, 0.3, 0.5, 0.7, 0.9), steps=60000, nx=160, ny=80, R0=25.0, tau=1.0,
+                       beta=1.945, progress=None, fields_out=None):
+    """One box per psi_w = psi_v + t (psi_l - psi_v) (psi of the Maxwell vapour and
+    liquid), BGK + Guo, float64, run for `steps`; returns the angles (None where
+    no cap sits on the wall).  A dict passed as fields_out receives the final
+    density fields."""
+    T = 0.9 * float(lbm.LibThermo().critical_temperature(PURE)[0])
+    case = sessile_case(nx, ny, R0)
+    probe = lbm.LbmContext(PURE, "D2Q9", case["shape"], T, tau, beta, [1.0], case["rho0"], forcing="guo")
+    psi = probe.moments(totals=False)["psi"].cpu().numpy()
+    probe.close()
+    y0 = int(np.ceil(case["wall_y"]))
+    psi_l, psi_v = float(psi[y0 + 2, nx // 2]), float(psi[y0 + (ny - y0) // 2, 0])
+    out = {"T": T, "steps": steps, "psi_l": psi_l, "psi_v": psi_v, "tau": tau, "beta": beta, "drops": []}
+    for t in psi_fracs:
+        pw = psi_v + t * (psi_l - psi_v)
+        ctx = lbm.LbmContext(PURE, "D2Q9", case["shape"], T, tau, beta, [1.0], case["rho0"], forcing="guo",
+                             solid=case["solid"], psi_wall=pw)
+        try:
+            ctx.step(steps)
+            ctx.check()
+            rho = ctx.moments(totals=False)["rho_s"].cpu().numpy()[0]
+            ctx.step(steps // 10)
+            ctx.check()
+            rho2 = ctx.moments(totals=False)["rho_s"].cpu().numpy()[0]
+        except lbm.LbmError as e:   # a strongly wetting wall condenses liquid past the EOS domain
+            out["drops"].append({"psi_frac": t, "psi_wall": pw, "theta_deg": None, "error": str(e)})
+            continue
+        finally:
+            ctx.close()
+        if fields_out is not None:
+            fields_out[f"psi_frac_{t:g}"] = rho2
+        try:
+            a, b = contact_angle(rho, case["wall_y"]), contact_angle(rho2, case["wall_y"])
+        except ValueError:          # no cap on the wall (the drop left it, or spread into a film)
+            out["drops"].append({"psi_frac": t, "psi_wall": pw, "theta_deg": None})
+            continue
+        out["drops"].append({"psi_frac": t, "psi_wall": pw, **b, "theta_change_last_tenth": b["theta_deg"] - a["theta_deg"]})
+        if progress is not None:
+            progress(t, b["theta_deg"])
+    return out
+
+
 def main():
     import argparse
     import json
@@ -562,6 +667,8 @@ def main():
                     help="merge the reports of flat-run JSON files into convergence tables and exit")
     ap.add_argument("--sigma-convergence", default="",
                     help="surface-tension convergence of a --laplace JSON file and exit")
+    ap.add_argument("--contact-angle", action="store_true", help="sessile drop on a wall against psi_w instead")
+    ap.add_argument("--psi-fracs", default="0.1,0.3,0.5,0.7,0.9")
     args = ap.parse_args()
     ps = [float(p) for p in args.pressures.split(",")]
     import sys
@@ -580,6 +687,16 @@ def main():
     if args.sigma_convergence:
         with open(args.sigma_convergence) as fh:
             print(json.dumps(sigma_convergence(json.loads(fh.read().strip().splitlines()[-1])), default=float))
+        return
+    if args.contact_angle:
+        fields = {}
+        out = run_contact_angles([float(t) for t in args.psi_fracs.split(",")], steps=args.max_steps,
+                                 beta=args.beta, fields_out=fields,
+                                 progress=lambda t, th: print(f"psi fraction {t}: theta {th:.2f}",
+                                                              file=sys.stderr, flush=True))
+        if args.save_state:
+            np.savez(args.save_state, **fields)
+        print(json.dumps(out, default=float))
         return
     if args.oscillation:
         out = run_oscillation(sizes=[int(n) for n in args.sizes.split(",")], beta=args.beta, forcing=args.forcing,

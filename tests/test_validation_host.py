@@ -102,3 +102,19 @@ def test_stretch_flat_keeps_interfaces_bulk_and_masses():
     mass = big.reshape(2, -1).sum(axis=1) * np.array([1.001, 0.999])
     st2 = validation.stretch_flat(small, 800, mass=mass)
     assert np.allclose(st2.reshape(2, -1).sum(axis=1), mass, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("theta", [45.0, 90.0, 120.0, 150.0])
+def test_contact_angle_of_a_circular_cap(theta):
+    """A tanh-profiled circular cap meeting the wall y = 2.5 at a known angle: the
+    measured angle (circle through the top and the crossings 3 cells above the
+    wall) recovers it within 1.5 degrees."""
+    ny, nx, yw, R = 90, 200, 2.5, 30.0
+    yc = yw - R * np.cos(np.radians(theta))
+    y, x = np.meshgrid(np.arange(ny, dtype=float), np.arange(nx, dtype=float), indexing="ij")
+    r = np.sqrt((x - nx // 2) ** 2 + (y - yc) ** 2)
+    rho = 3.2 - 2.6 * np.tanh(2.0 * (r - R) / 4.0)
+    rho[:3] = 0.6
+    m = validation.contact_angle(rho, yw)
+    assert abs(m["theta_deg"] - theta) < 1.5, m
+    assert abs(m["R"] - R) < 1.0
