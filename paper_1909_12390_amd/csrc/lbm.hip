@@ -139,7 +139,11 @@ lbm_status validate(const lbm_mixture* mix, const lbm_params* prm) {
 
 template <int LAT>
 void fill_mrt(const lbm_params* prm, KParams* kp) {
-  for (int k = 0; k < VS<LAT>::Q; ++k) kp->mrt_c[k] = (1.0 - prm->mrt_s[k]) / mrow_norm2<LAT>(k);
+  kp->mrt_rows = 0;
+  for (int k = 0; k < VS<LAT>::Q; ++k) {
+    kp->mrt_c[k] = (1.0 - prm->mrt_s[k]) / mrow_norm2<LAT>(k);
+    if (kp->mrt_c[k] != 0.0) kp->mrt_rows |= 1u << k;
+  }
 }
 
 lbm_status hip_check(hipError_t e, const char* what) {

@@ -109,7 +109,11 @@ void batch_layout(const lbm_box* boxes, int nboxes, const lbm_batch_params* prm,
 
 template <int LAT>
 void fill_mrt_b(const lbm_batch_params* prm, BatchK* K) {
-  for (int k = 0; k < VS<LAT>::Q; ++k) K->mrt_c[k] = (1.0 - prm->mrt_s[k]) / mrow_norm2<LAT>(k);
+  K->mrt_rows = 0;
+  for (int k = 0; k < VS<LAT>::Q; ++k) {
+    K->mrt_c[k] = (1.0 - prm->mrt_s[k]) / mrow_norm2<LAT>(k);
+    if (K->mrt_c[k] != 0.0) K->mrt_rows |= 1u << k;
+  }
 }
 
 }  // namespace

@@ -40,6 +40,7 @@ struct BatchK {
   int tile;                         // cells per tile (= workgroup size)
   int collision, forcing;
   double mrt_c[LBM_MAX_Q];
+  unsigned mrt_rows;                // bit k: mrt_c[k] != 0
   double accel[3];
   int* err;                         // [0]: any box; [1 + b]: box b
 };
@@ -181,6 +182,7 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restr
   P.mrt_c[0] = 0.0;
 #pragma unroll
   for (int k = 0; k < LBM_MAX_Q; ++k) P.mrt_c[k] = K.mrt_c[k];
+  P.mrt_rows = K.mrt_rows;
   const TileRange tr = tile_range(K.ntiles);
   for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
     const int bx = __builtin_amdgcn_readfirstlane(tile_box[t]);

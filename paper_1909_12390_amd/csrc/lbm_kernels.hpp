@@ -25,6 +25,7 @@ struct KParams {
   double invM[LBM_MAX_NC];
   double gamma[LBM_MAX_NC];
   double mrt_c[LBM_MAX_Q];         // MRT: (1 - rate) / squared norm of each moment row
+  unsigned mrt_rows;               // MRT: bit k set when mrt_c[k] != 0 (rows at rate 1 are skipped)
   double accel[3];
   int* err;                        // device error flag (set to 1 on a domain violation)
   // solid walls (null: none): per cell, bit a set when the source x - e_a of
@@ -562,9 +563,10 @@ __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R r
     static_for<1, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
       const double ck = P.mrt_c[k];
-      // skip rows relaxed at rate 1 (a uniform branch); in float64 the kernel
-      // streams at HBM speed and the branches cost more than the skipped rows
-      if (std::is_same<R, double>::value || ck != 0.0) {
+      // skip rows relaxed at rate 1 (a uniform branch on a scalar bit mask); in
+      // float64 the kernel streams at HBM speed and the branches cost more than
+      // the skipped rows
+      if (std::is_same<R, double>::value || ((P.mrt_rows >> k) & 1u)) {
         R m = 0;
         if constexpr (!row_odd<LAT>(k)) {
           if constexpr (V::mrow(k, 0) != 0.0) m += (R)V::mrow(k, 0) * d0;
