@@ -241,7 +241,8 @@ def adjoint_section(args, torch, lbm, inputs):
     """Gradient of the liquid-composition loss on the ternary D2Q9 128^2 drop:
     wall time of a forward-only run and of the checkpointed forward + reverse
     (lbm_adjoint), float32 and float64 storage, and the float32 gradient's
-    relative difference from the float64 one."""
+    relative difference from the float64 one.  The forward steps replay HIP graphs
+    of one checkpoint interval (the box is small enough for launches to dominate)."""
     from paper_1909_12390_amd import adjoint as padj
     cfg = inputs.config_c5(lbm.LibThermo())
     mask = inputs.drop_mask(cfg.shape, cfg.geometry["R0"])
@@ -249,15 +250,16 @@ def adjoint_section(args, torch, lbm, inputs):
     res = {"workload": f"ternary D2Q9 {cfg.shape[0]}x{cfg.shape[1]} drop, BGK + exact-difference forcing, "
                        f"{args.adjoint_steps} steps, checkpoint every {args.adjoint_every}, "
                        f"loss = squared liquid mole-fraction mismatch",
-           "steps": args.adjoint_steps, "checkpoint_every": args.adjoint_every}
+           "steps": args.adjoint_steps, "checkpoint_every": args.adjoint_every,
+           "graph_steps": args.adjoint_every}
     grads = {}
     for storage in ("f32", "f64"):
         def ctx():
             return lbm.LbmContext(cfg.mix, "D2Q9", cfg.shape, cfg.T, cfg.tau, cfg.beta, cfg.gamma, cfg.rho0,
-                                  collision="bgk", forcing="edm", storage=storage)
+                                  collision="bgk", forcing="edm", storage=storage, graph_steps=args.adjoint_every)
         c = ctx()
-        c.step(20)
-        torch.cuda.synchronize()
+        c.step(2 * args.adjoint_every)            # warm-up, captures both graphs
+        c.check()
         t0 = time.perf_counter()
         c.step(args.adjoint_steps)
         c.check()

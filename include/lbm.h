@@ -142,6 +142,14 @@ lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, void* workspa
                     size_t workspace_bytes, const double* rho_bar0_dev, const double* u0_dev,
                     void* stream, lbm_ctx** out);
 
+/* Capture `steps` time steps (rounded up to even, so the population buffers end
+ * where they started) once per buffer parity in a HIP graph; lbm_step then
+ * replays it for every full `steps` and launches the rest one by one.  0 (the
+ * default) launches every kernel.  Needs a non-default stream (LBM_ERR_ARG
+ * otherwise); the OVERLAP schedule keeps plain launches.  lbm_set_gamma and
+ * lbm_set_solid drop captured graphs (their values are kernel arguments). */
+lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
+
 /* Enqueue nsteps time steps (Sec. 3.4 order) on the context's stream.
  * Asynchronous: device domain errors are recorded in a device flag and reported by
  * the next lbm_moments or lbm_check. */

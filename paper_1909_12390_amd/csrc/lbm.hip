@@ -329,8 +329,37 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
 
 extern "C" lbm_status lbm_step(lbm_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return lbm_fail(LBM_ERR_ARG, "bad lbm_step arguments");
-  for (int i = 0; i < nsteps; ++i) enqueue_step(c, [](int) {});
+  int left = nsteps;
+  if (c->graph_steps > 0 && c->prm.schedule != LBM_SCHED_OVERLAP) {
+    while (left >= c->graph_steps) {
+      const int p = c->cur;
+      if (!c->graph[p]) {
+        hipGraph_t g = nullptr;
+        lbm_status st = hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (st != LBM_OK) return st;
+        for (int i = 0; i < c->graph_steps; ++i) enqueue_step(c, [](int) {});
+        st = hip_check(hipStreamEndCapture(c->stream, &g), "end capture");
+        c->cur = p;   // capture only recorded the launches; the replay below performs them
+        if (st != LBM_OK) return st;
+        st = hip_check(hipGraphInstantiate(&c->graph[p], g, nullptr, nullptr, 0), "instantiate graph");
+        hipGraphDestroy(g);
+        if (st != LBM_OK) return st;
+      }
+      lbm_status st = hip_check(hipGraphLaunch(c->graph[p], c->stream), "graph launch");
+      if (st != LBM_OK) return st;
+      left -= c->graph_steps;   // an even number of steps keeps the buffer parity
+    }
+  }
+  for (int i = 0; i < left; ++i) enqueue_step(c, [](int) {});
   return hip_check(hipGetLastError(), "step launch");
+}
+
+extern "C" lbm_status lbm_set_graph_steps(lbm_ctx* c, int steps) {
+  if (!c || steps < 0) return lbm_fail(LBM_ERR_ARG, "bad lbm_set_graph_steps arguments");
+  if (steps > 0 && !c->stream) return lbm_fail(LBM_ERR_ARG, "graph capture needs a non-default stream");
+  c->drop_graphs();
+  c->graph_steps = steps > 0 ? (steps + 1) / 2 * 2 : 0;
+  return LBM_OK;
 }
 
 extern "C" lbm_status lbm_step_timed(lbm_ctx* c, int nsteps, double* kernel_ms) {
@@ -394,6 +423,7 @@ extern "C" lbm_status lbm_set_gamma(lbm_ctx* c, const double* gamma) {
     c->prm.gamma[i] = gamma[i];
     c->kp.gamma[i] = gamma[i];   // kernel arguments: the next launch uses the new values
   }
+  c->drop_graphs();              // captured launches hold the old values
   return LBM_OK;
 }
 
@@ -486,6 +516,7 @@ extern "C" lbm_status lbm_set_solid(lbm_ctx* c, const unsigned char* solid, doub
     c->kp.psi_wall = 0.0;
   }
   if (st == LBM_OK) {
+    c->drop_graphs();   // captured launches hold the old wall arguments
     c->ops.imp(c->kp, c->pops[c->cur], tmp, nullptr, nullptr, 0, c->stream);
     st = hip_check(hipGetLastError(), "import launch");
   }

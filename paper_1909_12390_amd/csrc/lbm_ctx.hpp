@@ -35,7 +35,18 @@ struct lbm_ctx {
   int nev;
   // solid walls: per-cell direction mask on the device (kp.bb points here when set)
   unsigned* bb;
+  // lbm_step replay: graph_steps (even) steps captured once per buffer parity
+  hipGraphExec_t graph[2];
+  int graph_steps;
+  void drop_graphs() {
+    if ((graph[0] || graph[1]) && stream) hipStreamSynchronize(stream);   // no replay in flight
+    for (int p = 0; p < 2; ++p) {
+      if (graph[p]) hipGraphExecDestroy(graph[p]);
+      graph[p] = nullptr;
+    }
+  }
   ~lbm_ctx() {
+    drop_graphs();
     for (int k = 0; k < nev; ++k) hipEventDestroy(ev[k]);
     delete[] ev;
     if (aux) hipStreamDestroy(aux);

@@ -37,7 +37,8 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure",
             "lbm_batch_layout", "lbm_batch_init", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_check",
             "lbm_batch_box_errors", "lbm_batch_destroy", "lbm_adjoint_workspace", "lbm_step_adjoint",
-            "lbm_adjoint", "lbm_eos_param_grad", "lbm_set_gamma", "lbm_batch_set_gamma", "lbm_set_solid"]
+            "lbm_adjoint", "lbm_eos_param_grad", "lbm_set_gamma", "lbm_batch_set_gamma", "lbm_set_solid",
+            "lbm_set_graph_steps"]
 
 
 class LbmError(RuntimeError):
@@ -127,6 +128,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_set_gamma.argtypes = [c_void_p, dp]
         L.lbm_batch_set_gamma.argtypes = [c_void_p, c_int, dp]
         L.lbm_set_solid.argtypes = [c_void_p, c_void_p, c_double]
+        L.lbm_set_graph_steps.argtypes = [c_void_p, c_int]
         for name in EXPORTED:
             f = getattr(L, name)
             if name not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy"):
@@ -292,11 +294,14 @@ class LbmContext:
     u0  : optional initial velocity (D, *shape).
     solid, psi_wall: optional solid-cell mask (*shape, bool) and the wetting psi of
     the walls (lbm_set_solid), applied right after the initial state.
+    graph_steps > 0: step() replays HIP graphs of that many steps (lbm_set_graph_steps);
+    the context then runs on its own (default-priority) stream, and every call that
+    hands tensors to or from torch orders that stream against torch's current one.
     """
 
     def __init__(self, mix: dict, lattice: str, shape, T, tau, beta, gamma, rho0, u0=None,
                  collision="bgk", forcing="guo", storage="f64", schedule="two_pass", mrt_s=None,
-                 accel=None, G=-1.0, slab_planes=0, device="cuda", solid=None, psi_wall=0.0):
+                 accel=None, G=-1.0, slab_planes=0, device="cuda", solid=None, psi_wall=0.0, graph_steps=0):
         import torch
         self.torch = torch
         self.lattice = lattice
@@ -315,7 +320,12 @@ class LbmContext:
         self._ws_ptr = (base + 255) // 256 * 256
         rho0_t = self._to_device(rho0, (self.nc,) + self.shape)
         u0_t = None if u0 is None else self._to_device(u0, (self.D,) + self.shape)
-        self.stream = torch.cuda.current_stream(self.workspace.device)
+        self._own_stream = graph_steps > 0
+        if self._own_stream:
+            self.stream = torch.cuda.Stream(device=self.workspace.device)
+            self.stream.wait_stream(torch.cuda.current_stream(self.workspace.device))
+        else:
+            self.stream = torch.cuda.current_stream(self.workspace.device)
         ctx = c_void_p()
         _check(lib().lbm_init(ctypes.byref(self._mix), ctypes.byref(self._prm), c_void_p(self._ws_ptr),
                               c_size_t(int(nbytes.value)), c_void_p(rho0_t.data_ptr()),
@@ -326,6 +336,18 @@ class LbmContext:
         self._keep = None
         if solid is not None:
             self.set_solid(solid, psi_wall)
+        if graph_steps > 0:
+            _check(lib().lbm_set_graph_steps(self._ctx, int(graph_steps)))
+
+    def _inputs_ready(self):
+        """Own stream: wait for torch's current stream (tensors it just wrote)."""
+        if self._own_stream:
+            self.stream.wait_stream(self.torch.cuda.current_stream(self.workspace.device))
+
+    def _outputs_ready(self):
+        """Own stream: torch's current stream waits for the library's writes."""
+        if self._own_stream:
+            self.torch.cuda.current_stream(self.workspace.device).wait_stream(self.stream)
 
     def set_solid(self, solid, psi_wall=0.0):
         """Solid walls (halfway bounce-back, psi = psi_wall on solid cells); None
@@ -379,7 +401,9 @@ class LbmContext:
             out["psi"] = torch.empty(self.shape, dtype=torch.float64, device=dev)
             ptrs = [c_void_p(out[k].data_ptr()) for k in ("rho_s", "u", "p", "psi")]
         tot = np.zeros(self.nc + 2 * self.D) if totals else None
+        self._inputs_ready()
         _check(lib().lbm_moments(self._ctx, *ptrs, None if tot is None else _dptr(tot)))
+        self._outputs_ready()
         if totals:
             out["mass"] = tot[: self.nc].copy()
             out["momentum"] = tot[self.nc: self.nc + self.D].copy()
@@ -389,11 +413,14 @@ class LbmContext:
     def get_populations(self):
         torch = self.torch
         f = torch.empty((self.nc, self.Q) + self.shape, dtype=torch.float64, device=self.workspace.device)
+        self._inputs_ready()
         _check(lib().lbm_get_populations(self._ctx, c_void_p(f.data_ptr())))
+        self._outputs_ready()
         return f
 
     def set_populations(self, f):
         t = self._to_device(f, (self.nc, self.Q) + self.shape)
+        self._inputs_ready()
         _check(lib().lbm_set_populations(self._ctx, c_void_p(t.data_ptr())))
         self.stream.synchronize()
 
@@ -413,8 +440,10 @@ class LbmContext:
         daa = np.zeros(self.nc * self.nc)
         db = np.zeros(self.nc)
         ws, ptr, nbytes = self._adjoint_ws(1, 1)
+        self._inputs_ready()
         _check(lib().lbm_step_adjoint(self._ctx, c_void_p(h.data_ptr()), c_void_p(out.data_ptr()), _dptr(daa),
                                       _dptr(db), c_void_p(ptr), c_size_t(nbytes)))
+        self._outputs_ready()
         del ws
         return out, daa.reshape(self.nc, self.nc), db
 
@@ -435,6 +464,7 @@ class LbmContext:
         da = np.zeros(self.nc)
         db = np.zeros(self.nc)
         ws, ptr, nbytes = self._adjoint_ws(nsteps, checkpoint_every)
+        self._inputs_ready()
         _check(lib().lbm_adjoint(self._ctx, int(nsteps), int(checkpoint_every), c_void_p(m.data_ptr()), _dptr(xt),
                                  c_void_p(ptr), c_size_t(nbytes), _dptr(loss), _dptr(x), _dptr(dk), _dptr(da),
                                  _dptr(db)))
@@ -443,6 +473,8 @@ class LbmContext:
 
     def close(self):
         if getattr(self, "_ctx", None) is not None:
+            if self._own_stream:
+                self.stream.synchronize()      # the workspace goes back to torch
             lib().lbm_destroy(self._ctx)
             self._ctx = None
 
