@@ -116,3 +116,11 @@ def test_eos_param_grad_validates():
         == lbm.LBM_ERR_ARG
     assert lbm.lib().lbm_eos_param_grad(ctypes.byref(m), 0.05, None, dp(z), dp(out), dp(out), dp(out)) \
         == lbm.LBM_ERR_ARG
+
+
+def test_host_validation_rejects_planes_past_4gib():
+    """One component's direction planes are addressed with 32-bit byte offsets:
+    a box whose float64 planes would pass 4 GiB is refused on the host."""
+    assert _bytes(lattice="D3Q19", shape=(310, 310, 310))[0] == lbm.LBM_ERR_ARG   # 19 x 8 x 2.98e7 B > 4 GiB
+    assert _bytes(lattice="D3Q19", shape=(300, 300, 300))[0] == lbm.LBM_OK        # 19 x 8 x 2.70e7 B < 4 GiB
+    assert _bytes(lattice="D3Q19", shape=(128, 128, 128))[0] == lbm.LBM_OK

@@ -142,3 +142,28 @@ def test_c4_full_batch_sampled_boxes():
             f = olbm.step(f, to_mixture(c.mix), prm, LAT["D2Q9"])
         e = rel_err(got[i], f)
         assert e < 1e-12, (i, c.shape, e)
+
+
+@pytest.mark.parametrize("lattice,shape", [("D2Q9", (5, 1)), ("D2Q9", (1, 7)), ("D2Q9", (1, 1)),
+                                           ("D2Q9", (3, 64)), ("D2Q9", (2, 65)), ("D3Q19", (3, 1, 5)),
+                                           ("D3Q19", (1, 1, 1)), ("D3Q19", (2, 3, 128))])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f16", 1e-4)])
+def test_degenerate_and_edge_boxes(lattice, shape, storage, tol):
+    """One-cell-wide rows and columns, a single cell (every neighbour is the cell
+    itself), rows of exactly 64 / 128 cells (the right neighbour of a wavefront's
+    last lane wraps to x = 0) and of 65 (a one-cell second segment)."""
+    from cases import case
+    print(f"case edge box {lattice} {shape} {storage}", flush=True)
+    c = case(lattice, 2, shape, seed=4, u_amp=0.01)
+    ctx = _lbm().LbmContext(c["mix"], lattice, c["shape"], c["T"], 0.8, 1.16, c["gamma"], c["rho0"], c["u0"],
+                            collision="bgk", forcing="edm", storage=storage)
+    prm = olbm.StepParams(T=c["T"], tau=0.8, gamma=c["gamma"], beta=1.16, collision="bgk", forcing="edm")
+    m = to_mixture(c["mix"])
+    f = ctx.get_populations().cpu().numpy()          # the GPU's own (decoded) state
+    for _ in range(3):
+        ref = olbm.step(f, m, prm, LAT[lattice])
+        ctx.step(1)
+        f = ctx.get_populations().cpu().numpy()
+        e = rel_err(f, ref)
+        assert e < tol, (shape, storage, e)
+    ctx.check()
