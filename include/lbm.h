@@ -261,6 +261,10 @@ typedef struct {
   int nx, ny, nz;            /* nz = 1 for D2Q9; periodic                         */
   double T, tau, G, beta;
   double gamma[LBM_MAX_NC];  /* each in (0, 1]                                    */
+  const unsigned char* solid;  /* host, one byte per cell (x fastest), nonzero =
+                                  solid; NULL = no walls.  Same wall model as
+                                  lbm_set_solid; read during lbm_batch_init only. */
+  double psi_wall;           /* psi of the box's solid cells (finite, >= 0)       */
 } lbm_box;
 
 typedef struct {

@@ -22,6 +22,7 @@
 
 #include "lbm.h"
 #include "lbm_ctx.hpp"
+#include "lbm_walls.hpp"
 #include "lbm_internal.hpp"
 
 namespace {
@@ -462,28 +463,6 @@ extern "C" lbm_status lbm_set_populations(lbm_ctx* c, const double* f) {
   return hip_check(hipGetLastError(), "import launch");
 }
 
-namespace {
-
-// bit a of cell x: the source x - e_a of direction a is solid; bit 31: x is solid
-template <int LAT>
-void wall_bits(const lbm_params& prm, const unsigned char* solid, unsigned* bits) {
-  using V = lbmk::VS<LAT>;
-  const long nx = prm.nx, ny = prm.ny, nz = prm.nz;
-  for (long z = 0; z < nz; ++z)
-    for (long y = 0; y < ny; ++y)
-      for (long x = 0; x < nx; ++x) {
-        const long cell = (z * ny + y) * nx + x;
-        unsigned b = solid[cell] ? (1u << lbmk::kSolidBit) : 0u;
-        for (int a = 1; a < V::Q; ++a) {
-          const long sx = (x - V::cx(a) + nx) % nx, sy = (y - V::cy(a) + ny) % ny, sz = (z - V::cz(a) + nz) % nz;
-          if (solid[(sz * ny + sy) * nx + sx]) b |= 1u << a;
-        }
-        bits[cell] = b;
-      }
-}
-
-}  // namespace
-
 extern "C" lbm_status lbm_set_solid(lbm_ctx* c, const unsigned char* solid, double psi_wall) {
   if (!c) return lbm_fail(LBM_ERR_ARG, "ctx is NULL");
   if (solid && !(std::isfinite(psi_wall) && psi_wall >= 0.0))
@@ -499,8 +478,8 @@ extern "C" lbm_status lbm_set_solid(lbm_ctx* c, const unsigned char* solid, doub
     unsigned* bits = new (std::nothrow) unsigned[c->cells];
     if (!bits) st = lbm_fail(LBM_ERR_ARG, "out of host memory");
     if (st == LBM_OK) {
-      if (c->prm.lattice == LBM_D2Q9) wall_bits<LBM_D2Q9>(c->prm, solid, bits);
-      else wall_bits<LBM_D3Q19>(c->prm, solid, bits);
+      if (c->prm.lattice == LBM_D2Q9) wall_bits<LBM_D2Q9>(c->prm.nx, c->prm.ny, c->prm.nz, solid, bits);
+      else wall_bits<LBM_D3Q19>(c->prm.nx, c->prm.ny, c->prm.nz, solid, bits);
       if (!c->bb) st = hip_check(hipMalloc((void**)&c->bb, sizeof(unsigned) * c->cells), "hipMalloc(walls)");
     }
     if (st == LBM_OK) st = hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");

@@ -14,6 +14,7 @@
 #include "lbm.h"
 #include "lbm_batch_dispatch.hpp"
 #include "lbm_internal.hpp"
+#include "lbm_walls.hpp"
 
 using namespace lbmk;
 
@@ -29,8 +30,8 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32_OFS ? 4 : 2); }
 
 struct BLayout {
-  size_t pop0[2], pop1[2], psi, boxes, tiles, fld, err, total;
-  size_t field_elems, pop_elems, cells;
+  size_t pop0[2], pop1[2], psi, boxes, tiles, fld, err, walls, total;
+  size_t field_elems, pop_elems, cells, wall_cells;
   unsigned ntiles;
 };
 
@@ -56,6 +57,8 @@ lbm_status batch_validate(const lbm_box* boxes, int nboxes, const lbm_batch_para
     if ((double)B.nx * B.ny * B.nz * Q * 8.0 >= 4294967295.0) return lbm_fail(LBM_ERR_ARG, "box %d too large", i);
     if (!(B.tau > 0.5) || !(B.G < 0.0) || !(B.T > 0.0) || !std::isfinite(B.beta) || !(m.R > 0.0))
       return lbm_fail(LBM_ERR_ARG, "box %d: need tau > 0.5, G < 0, T > 0, finite beta, R > 0", i);
+    if (B.solid && !(std::isfinite(B.psi_wall) && B.psi_wall >= 0.0))
+      return lbm_fail(LBM_ERR_ARG, "box %d: psi_wall must be finite and >= 0", i);
     for (int a = 0; a < m.nc; ++a) {
       if (!(B.gamma[a] > 0.0 && B.gamma[a] <= 1.0)) return lbm_fail(LBM_ERR_ARG, "box %d: gamma outside (0, 1]", i);
       if (!(m.a[a] > 0.0 && m.b[a] > 0.0 && m.M[a] > 0.0)) return lbm_fail(LBM_ERR_ARG, "box %d: a, b, M > 0", i);
@@ -72,10 +75,12 @@ void batch_layout(const lbm_box* boxes, int nboxes, const lbm_batch_params* prm,
   L->field_elems = 0;
   L->pop_elems = 0;
   L->cells = 0;
+  L->wall_cells = 0;
   L->ntiles = 0;
   for (int i = 0; i < nboxes; ++i) {
     const size_t cells = (size_t)boxes[i].nx * boxes[i].ny * boxes[i].nz;
     L->cells += cells;
+    if (boxes[i].solid) L->wall_cells += cells;
     L->field_elems += (size_t)boxes[i].mix.nc * cells;
     L->pop_elems += (size_t)boxes[i].mix.nc * Q * cells;
     L->ntiles += (unsigned)((cells + tile - 1) / tile);
@@ -104,6 +109,8 @@ void batch_layout(const lbm_box* boxes, int nboxes, const lbm_batch_params* prm,
   off = align_up(off + (size_t)nboxes * sizeof(unsigned long long));
   L->err = off;
   off = align_up(off + (size_t)(nboxes + 1) * sizeof(int));
+  L->walls = off;                      // masks of the boxes with walls, in box order
+  off = align_up(off + L->wall_cells * sizeof(unsigned));
   L->total = off;
 }
 
@@ -175,8 +182,9 @@ extern "C" lbm_status lbm_batch_init(const lbm_box* boxes, int nboxes, const lbm
   std::vector<BoxK> hb(nboxes);
   std::vector<int> tiles;
   std::vector<unsigned long long> fld(nboxes);
+  std::vector<unsigned> bits(L.wall_cells);
   tiles.reserve(L.ntiles);
-  unsigned long long pop_off = 0, base_off = 0, psi_off = 0, fo = 0;
+  unsigned long long pop_off = 0, base_off = 0, psi_off = 0, fo = 0, bb_off = 0;
   for (int i = 0; i < nboxes; ++i) {
     const lbm_box& B = boxes[i];
     BoxK& k = hb[i];
@@ -201,6 +209,14 @@ extern "C" lbm_status lbm_batch_init(const lbm_box* boxes, int nboxes, const lbm
       k.invM[a] = 1.0 / B.mix.M[a];
       k.gamma[a] = B.gamma[a];
       for (int c = 0; c < k.nc; ++c) k.aa[a][c] = std::sqrt(aa[a] * aa[c]) * (1.0 - B.mix.k[a][c]);
+    }
+    if (B.solid) {
+      k.walls = 1;
+      k.bb_off = bb_off;
+      k.psi_wall = B.psi_wall;
+      if (prm->lattice == LBM_D2Q9) wall_bits<LBM_D2Q9>(B.nx, B.ny, B.nz, B.solid, bits.data() + bb_off);
+      else wall_bits<LBM_D3Q19>(B.nx, B.ny, B.nz, B.solid, bits.data() + bb_off);
+      bb_off += k.cells;
     }
     const unsigned nt = (k.cells + tile - 1) / tile;
     for (unsigned t = 0; t < nt; ++t) tiles.push_back(i);
@@ -243,6 +259,7 @@ extern "C" lbm_status lbm_batch_init(const lbm_box* boxes, int nboxes, const lbm
   const int D = prm->lattice == LBM_D2Q9 ? 2 : 3;
   for (int d = 0; d < 3; ++d) b->K.accel[d] = d < D ? prm->accel[d] : 0.0;
   b->K.err = b->err;
+  b->K.bb = L.wall_cells ? (const unsigned*)(base + L.walls) : nullptr;
   int ncmax = 1;
   for (int i = 0; i < nboxes; ++i) ncmax = std::max(ncmax, boxes[i].mix.nc);
   b->ops = prm->lattice == LBM_D2Q9 ? bops_d2q9(prm->storage, prm->collision, prm->forcing, ncmax)
@@ -274,6 +291,9 @@ extern "C" lbm_status lbm_batch_init(const lbm_box* boxes, int nboxes, const lbm
   if (st == LBM_OK)
     st = hip_check(hipMemcpyAsync(b->fld_off, fld.data(), fld.size() * sizeof(unsigned long long),
                                   hipMemcpyHostToDevice, b->stream), "upload offsets");
+  if (st == LBM_OK && L.wall_cells)
+    st = hip_check(hipMemcpyAsync((void*)b->K.bb, bits.data(), bits.size() * sizeof(unsigned), hipMemcpyHostToDevice,
+                                  b->stream), "upload wall masks");
   if (st == LBM_OK)
     st = hip_check(hipMemsetAsync(b->err, 0, (size_t)(nboxes + 1) * sizeof(int), b->stream), "clear error flags");
   if (st == LBM_OK) {

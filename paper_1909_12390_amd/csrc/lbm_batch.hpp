@@ -28,6 +28,9 @@ struct BoxK {
   double RT, G, beta, omega;
   double aa[LBM_MAX_NC][LBM_MAX_NC];
   double b[LBM_MAX_NC], invM[LBM_MAX_NC], gamma[LBM_MAX_NC];
+  int walls;                        // the box has solid cells (masks at BatchK::bb + bb_off)
+  unsigned long long bb_off;        // element offset of the box's wall masks
+  double psi_wall;                  // psi of the box's solid cells
 };
 
 // Scalars of a batch; the box table and the work list (box of each tile) are
@@ -43,6 +46,8 @@ struct BatchK {
   unsigned mrt_rows;                // bit k: mrt_c[k] != 0
   double accel[3];
   int* err;                         // [0]: any box; [1 + b]: box b
+  const unsigned* bb;               // wall masks of every box with walls (bit a: the source
+                                    // x - e_a is solid; bit 31: the cell is solid), or null
 };
 
 // Storage views over a box's planes (same encodings as Pops<ST>).
@@ -139,6 +144,11 @@ __global__ __launch_bounds__(1024) void kb_psi(BatchK K, const BoxK* __restrict_
     const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
     if (cell >= B.cells) continue;
     const Coord c = box_coord(cell, B);
+    const unsigned bits = B.walls ? K.bb[B.bb_off + cell] : 0u;
+    if (bits >> kSolidBit) {           // solid cell: the wall's psi
+      psi[B.psi_off + cell] = B.psi_wall;
+      continue;
+    }
     double rb[LBM_MAX_NC];
 #pragma unroll
     for (int s = 0; s < LBM_MAX_NC; ++s) rb[s] = 0.0;
@@ -146,8 +156,14 @@ __global__ __launch_bounds__(1024) void kb_psi(BatchK K, const BoxK* __restrict_
     for (int s = 0; s < B.nc; ++s) {
       const auto cv = in.comp(B, s, V::Q);
       R v[V::Q];
-      cv.template get_all<V::Q>([&](int a) { return c.at(-V::cx(a), -V::cy(a), -V::cz(a)); }, v,
-                                [](int a) { return (R)V::w(a); });
+      if (B.walls) {                   // halfway bounce-back for sources that are solid
+#pragma unroll
+        for (int a = 0; a < V::Q; ++a)
+          v[a] = pull_bb<LAT>(cv, a, bits, cell, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+      } else {
+        cv.template get_all<V::Q>([&](int a) { return c.at(-V::cx(a), -V::cy(a), -V::cz(a)); }, v,
+                                  [](int a) { return (R)V::w(a); });
+      }
       R acc = 0;
 #pragma unroll
       for (int a = 0; a < V::Q; ++a) acc += v[a];
@@ -189,9 +205,11 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restr
     const BoxK& B = boxes[bx];
     const int nc = B.nc;
     const unsigned cell = (t - B.first_tile) * (unsigned)tile + (unsigned)lane;
-    const bool in_box = cell < B.cells;
+    // solid cells (walls) take no part: no pull, no force, no collision, no store
+    const unsigned bits = (B.walls && cell < B.cells) ? K.bb[B.bb_off + cell] : 0u;
+    const bool in_box = cell < B.cells && !(bits >> kSolidBit);
     const bool active = in_box && s < nc;
-    const Coord c = box_coord(in_box ? cell : 0u, B);
+    const Coord c = box_coord(cell < B.cells ? cell : 0u, B);
     R f[Q];
     R jx = 0, jy = 0, jz = 0;
     double mass = 0.0;   // summed exactly for the offset formats' base (put_all)
@@ -200,7 +218,8 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restr
       const auto cv = in.comp(B, s, Q);
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
-        f[a] = cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+        const unsigned nbr = c.at(-V::cx(a), -V::cy(a), -V::cz(a));
+        f[a] = B.walls ? pull_bb<LAT>(cv, a, bits, cell, nbr, (R)V::w(a)) : cv.get(a, nbr, (R)V::w(a));
         mass += (double)f[a];
         if (V::cx(a)) jx += (R)V::cx(a) * f[a];
         if (V::cy(a)) jy += (R)V::cy(a) * f[a];
@@ -303,13 +322,18 @@ __global__ __launch_bounds__(1024) void kb_export(BatchK K, const BoxK* __restri
     const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
     if (cell >= B.cells) continue;
     const Coord c = box_coord(cell, B);
+    const unsigned bits = B.walls ? K.bb[B.bb_off + cell] : 0u;
 #pragma unroll 1
     for (int s = 0; s < B.nc; ++s) {
       const auto cv = in.comp(B, s, V::Q);
       double acc = 0.0;
 #pragma unroll
       for (int a = 0; a < V::Q; ++a) {
-        const double v = (double)cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+        const unsigned nbr = c.at(-V::cx(a), -V::cy(a), -V::cz(a));
+        double v;
+        if (!B.walls) v = (double)cv.get(a, nbr, (R)V::w(a));
+        else if (bits >> kSolidBit) v = 0.0;   // solid cells hold no fluid
+        else v = (double)pull_bb<LAT>(cv, a, bits, cell, nbr, (R)V::w(a));
         acc += v;
         if (f_out) f_out[B.pop_off + ((size_t)s * V::Q + a) * B.cells + cell] = v;
       }
@@ -334,13 +358,18 @@ __global__ __launch_bounds__(1024) void kb_init(BatchK K, const BoxK* __restrict
     const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
     if (cell >= B.cells) continue;
     const Coord c = box_coord(cell, B);
+    const unsigned bits = B.walls ? K.bb[B.bb_off + cell] : 0u;
 #pragma unroll 1
     for (int s = 0; s < B.nc; ++s) {
       R v[Q];
       double sum = 0.0;
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
-        const double r = rho0[fld_off[bx] + (size_t)s * B.cells + c.at(V::cx(a), V::cy(a), V::cz(a))];
+        // at rest feq depends on |e| only: a population that will bounce back into
+        // this cell (its target y + e_a is solid) is the equilibrium of this cell
+        const bool back = (bits >> V::opp(a)) & 1u;
+        const unsigned src = back ? cell : c.at(V::cx(a), V::cy(a), V::cz(a));
+        const double r = (bits >> kSolidBit) ? 0.0 : rho0[fld_off[bx] + (size_t)s * B.cells + src];
         const double fe = feq<LAT, double>(a, r, 0.0, 0.0, 0.0, 0.0);
         v[a] = (R)fe;
         sum += fe;

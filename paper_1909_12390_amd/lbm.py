@@ -69,7 +69,8 @@ class LbmFlashResult(ctypes.Structure):
 
 class LbmBox(ctypes.Structure):
     _fields_ = [("mix", LbmMixture), ("nx", c_int), ("ny", c_int), ("nz", c_int), ("T", c_double),
-                ("tau", c_double), ("G", c_double), ("beta", c_double), ("gamma", c_double * MAX_NC)]
+                ("tau", c_double), ("G", c_double), ("beta", c_double), ("gamma", c_double * MAX_NC),
+                ("solid", c_void_p), ("psi_wall", c_double)]
 
 
 class LbmBatchParams(ctypes.Structure):
@@ -503,8 +504,9 @@ class LbmBatch:
     """Many independent boxes advanced together (one lbm_batch).
 
     boxes: list of dicts {"mix", "shape" (ny, nx) or (nz, ny, nx), "T", "tau", "beta",
-    "gamma", "rho0" (nc, *shape)}.  With graph_steps > 0 the batch runs on its own
-    (default-priority) stream so the steps can be captured in a HIP graph.
+    "gamma", "rho0" (nc, *shape)}, optionally "solid" (*shape, bool) and "psi_wall"
+    for walls (the model of lbm_set_solid).  With graph_steps > 0 the batch runs on
+    its own (default-priority) stream so the steps can be captured in a HIP graph.
     """
 
     def __init__(self, boxes, lattice="D2Q9", collision="bgk", forcing="edm", storage="f64", tile=0,
@@ -516,6 +518,7 @@ class LbmBatch:
         n = len(boxes)
         arr = (LbmBox * n)()
         self.shapes, self.ncs = [], []
+        masks = []                         # alive until lbm_batch_init has read them
         for i, bx in enumerate(boxes):
             shape = tuple(int(v) for v in bx["shape"])
             if lattice == "D2Q9":
@@ -531,6 +534,13 @@ class LbmBatch:
             arr[i].beta = float(bx["beta"])
             for k, g in enumerate(bx["gamma"]):
                 arr[i].gamma[k] = float(g)
+            if bx.get("solid") is not None:
+                m = np.ascontiguousarray(np.asarray(bx["solid"], dtype=bool).astype(np.uint8))
+                if m.shape != shape:
+                    raise ValueError(f"box {i}: solid mask must have shape {shape}")
+                masks.append(m)
+                arr[i].solid = m.ctypes.data
+                arr[i].psi_wall = float(bx.get("psi_wall", 0.0))
             self.shapes.append(shape)
             self.ncs.append(len(bx["mix"]["a"]))
         self._boxes = arr
@@ -564,6 +574,7 @@ class LbmBatch:
         _check(lib().lbm_batch_init(arr, n, ctypes.byref(prm), c_void_p(wsp), c_size_t(int(ws.value)),
                                     c_void_p(rho0.data_ptr()), c_void_p(self.stream.cuda_stream),
                                     ctypes.byref(ctx)))
+        del masks
         self._ctx = ctx
 
     def step(self, n=1):

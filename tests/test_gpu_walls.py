@@ -204,3 +204,47 @@ def test_adjoint_refuses_walls():
     with pytest.raises(lbm.LbmError) as e:
         ctx.step_adjoint(h)
     assert e.value.code == lbm.LBM_ERR_UNSUPPORTED
+
+
+def batch_boxes(lattice, specs):
+    """Boxes of a mixed batch: (nc, shape, seed, porous) each; porous boxes get a
+    random mask and the wetting psi of wall_psi."""
+    boxes, cases_ = [], []
+    for nc, shape, seed, por in specs:
+        c = case(lattice, nc, shape, seed=seed)
+        solid = porous(shape, 100 + seed) if por else None
+        pw = wall_psi(c) if por else 0.0
+        boxes.append({"mix": c["mix"], "shape": shape, "T": c["T"], "tau": 0.8, "beta": 1.16, "gamma": c["gamma"],
+                      "rho0": c["rho0"], "solid": solid, "psi_wall": pw})
+        cases_.append((c, solid, pw))
+    return boxes, cases_
+
+
+@pytest.mark.parametrize("lattice,specs", [
+    ("D2Q9", [(2, (30, 41), 1, True), (3, (24, 70), 2, False), (1, (33, 17), 3, True), (3, (20, 20), 4, True)]),
+    ("D3Q19", [(2, (9, 10, 11), 5, True), (2, (7, 8, 13), 6, False)])])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f16", 2e-4)])
+def test_batch_walls_match_oracle(lattice, specs, storage, tol):
+    """Batched boxes with and without walls: each box equals the oracle's wall
+    model stepping that box alone."""
+    print(f"case batch walls {lattice} {storage} {len(specs)} boxes", flush=True)
+    boxes, cs = batch_boxes(lattice, specs)
+    b = _lbm().LbmBatch(boxes, lattice, collision="bgk", forcing="edm", storage=storage, tile=64)
+    f0 = [x.cpu().numpy() for x in b.fields(populations=True)[1]]
+    b.step(1)
+    f1 = [x.cpu().numpy() for x in b.fields(populations=True)[1]]
+    b.step(4)
+    f5 = [x.cpu().numpy() for x in b.fields(populations=True)[1]]
+    b.check()
+    assert not b.box_errors().any()
+    for i, (c, solid, pw) in enumerate(cs):
+        prm = oracle_params(c, "bgk", "edm", beta=1.16)
+        prm.solid, prm.psi_wall = solid, pw
+        f = olbm.init_populations(c["rho0"], LAT[lattice])
+        if solid is not None:
+            f[:, :, solid] = 0.0
+            assert np.all(f0[i][:, :, solid] == 0.0)
+        assert rel_err(f0[i], f) < (1e-15 if storage == "f64" else 1e-4)
+        ref = oracle_steps(c, prm, lattice, f, 5)
+        e1, e5 = rel_err(f1[i], ref[1]), rel_err(f5[i], ref[5])
+        assert e1 < tol and e5 < tol, (i, e1, e5)
