@@ -18,10 +18,15 @@ Loss (reading): L = sum_i (x_i - x_i^tgt)^2 with x_i = N_i / sum_j N_j,
 N_i = sum over a fixed cell mask of rbar_i / M_i, from the post-streaming
 populations after the last step (the liquid mask of a drop is r <= R0/2).
 
-Pins (tests/test_oracle_adjoint.py): the torch step equals the NumPy step; the
-gradient equals central differences of the NumPy oracle's loss; forward- and
-reverse-mode products satisfy the dot-product identity; L and its gradient vanish
-when the target is the reached composition.
+Solid walls (prm.solid, prm.psi_wall) follow oracle.lbm: solid cells hold no fluid,
+carry psi_w, and streaming bounces back; their EOS, force split and velocity are
+evaluated on harmless stand-in values and masked, so that no NaN reaches the
+reverse pass.
+
+Pins (tests/test_oracle_adjoint.py): the torch step equals the NumPy step (with and
+without walls); the gradient equals central differences of the NumPy oracle's
+loss; forward- and reverse-mode products satisfy the dot-product identity; L and
+its gradient vanish when the target is the reached composition.
 """
 from __future__ import annotations
 
@@ -30,6 +35,7 @@ import torch
 
 from . import thermo
 from .lattice import CS2, VelocitySet, mrt_basis
+from .lbm import opposite
 
 DT = torch.float64
 
@@ -136,13 +142,20 @@ def step(f, aa, b, base: thermo.Mixture, prm, lat: VelocitySet):
     N = f.shape[0]
     D = lat.D
     gshape = (-1,) + (1,) * (f.dim() - 2)
+    solid = None if getattr(prm, "solid", None) is None else torch.as_tensor(np.asarray(prm.solid, dtype=bool))
+    if solid is not None:
+        f = torch.where(solid, torch.zeros((), dtype=DT), f)       # solid cells hold no fluid
     rho_s = f.sum(dim=1)
     rho = rho_s.sum(dim=0)
     j = torch.stack([sum(float(lat.e[a, d]) * f[s, a] for s in range(N) for a in range(lat.Q)
                          if lat.e[a, d] != 0) for d in range(D)])
-    p = pressure(rho_s, prm.T, aa, b, base.M, base.R)
-    X = 2.0 * (p - CS2 * rho) / (prm.G * CS2)
+    rho_eos = rho_s if solid is None else torch.where(solid, torch.full((), 1e-3, dtype=DT), rho_s)
+    p = pressure(rho_eos, prm.T, aa, b, base.M, base.R)
+    X = 2.0 * (p - CS2 * rho_eos.sum(dim=0)) / (prm.G * CS2)
     psi = torch.sqrt(X)
+    if solid is not None:
+        psi = torch.where(solid, torch.full((), float(prm.psi_wall), dtype=DT), psi)
+        rho = torch.where(solid, torch.ones((), dtype=DT), rho)    # u = j / rho = 0 there
     F = [torch.zeros_like(psi) for _ in range(D)]
     for a in range(1, lat.Q):
         e = lat.e[a]
@@ -154,6 +167,8 @@ def step(f, aa, b, base: thermo.Mixture, prm, lat: VelocitySet):
     F = torch.stack(F)
     gamma = torch.as_tensor(np.asarray(prm.gamma, dtype=np.float64), dtype=DT)
     Gam = (gamma.reshape(gshape) * rho_s).sum(dim=0)
+    if solid is not None:
+        Gam = torch.where(solid, torch.ones((), dtype=DT), Gam)
     g = np.zeros(D) if prm.accel is None else np.asarray(prm.accel, dtype=np.float64)
     F_s = torch.stack([torch.stack([gamma[s] * rho_s[s] / Gam * F[d] + rho_s[s] * float(g[d])
                                     for d in range(D)]) for s in range(N)])
@@ -185,8 +200,22 @@ def step(f, aa, b, base: thermo.Mixture, prm, lat: VelocitySet):
             post = post + equilibrium(rho_s[s], u + du, lat) - feq
         posts.append(post)
     fstar = torch.stack(posts)
-    return torch.stack([torch.stack([shift(fstar[s, a], lat.e[a], lead=0) for a in range(lat.Q)])
-                        for s in range(N)])
+    if solid is None:
+        return torch.stack([torch.stack([shift(fstar[s, a], lat.e[a], lead=0) for a in range(lat.Q)])
+                            for s in range(N)])
+    # halfway bounce-back: a fluid cell whose source x - e_a is solid receives its
+    # own opposite post-collision population; solid cells receive nothing
+    opp = opposite(lat)
+    zero = torch.zeros((), dtype=DT)
+    out = []
+    for s in range(N):
+        row = []
+        for a in range(lat.Q):
+            from_wall = shift(solid, lat.e[a], lead=0) & ~solid
+            v = torch.where(from_wall, fstar[s, opp[a]], shift(fstar[s, a], lat.e[a], lead=0))
+            row.append(torch.where(solid, zero, v))
+        out.append(torch.stack(row))
+    return torch.stack(out)
 
 
 # ---------------------------------------------------------------------------

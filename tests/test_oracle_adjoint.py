@@ -130,3 +130,53 @@ def test_vjp_over_eos_tables_chains_to_theta():
     aa2, b2 = oadj.eos_tables(thr, base, prm.T)
     (chain,) = torch.autograd.grad((aa2 * torch.as_tensor(gaa)).sum() + (b2 * torch.as_tensor(gb)).sum(), thr)
     assert np.max(np.abs(chain.numpy() - gth)) <= 1e-13 * np.max(np.abs(gth))
+
+
+def porous_mask(shape, seed, frac=0.15):
+    return np.random.default_rng([7, seed]).uniform(size=shape) < frac
+
+
+def wall_psi(c, base):
+    corner = c["rho0"][(slice(None),) + (0,) * len(c["shape"])]
+    return 1.3 * float(olbm.pseudo_potential(corner[:, None], c["T"], base, -1.0)[0])
+
+
+@pytest.mark.parametrize("lattice,nc,shape", [("D2Q9", 3, (12, 14)), ("D3Q19", 2, (6, 7, 8))])
+@pytest.mark.parametrize("collision,forcing", [("bgk", "edm"), ("bgk", "guo"), ("mrt", "edm"), ("mrt", "guo")])
+def test_torch_step_is_the_numpy_step_with_walls(lattice, nc, shape, collision, forcing):
+    c, lat, prm, base, f0 = setup(lattice, nc, shape, collision, forcing, seed=4)
+    prm.solid, prm.psi_wall = porous_mask(shape, 4), wall_psi(c, base)
+    f0 = f0.copy()
+    f0[:, :, prm.solid] = 0.0
+    aa, b = oadj.eos_tables(torch.as_tensor(oadj.theta_of(base), dtype=oadj.DT), base, prm.T)
+    f_np, f_t = f0, torch.as_tensor(f0, dtype=oadj.DT)
+    for _ in range(3):
+        f_np = olbm.step(f_np, base, prm, lat)
+        f_t = oadj.step(f_t, aa, b, base, prm, lat)
+        err = np.max(np.abs(f_t.numpy() - f_np)) / np.max(np.abs(f_np))
+        assert err < 1e-13
+
+
+@pytest.mark.parametrize("collision,forcing", [("bgk", "edm"), ("mrt", "guo")])
+def test_gradient_with_walls_matches_central_differences(collision, forcing):
+    shape = (12, 14)
+    c, lat, prm, base, f0 = setup("D2Q9", 3, shape, collision, forcing, seed=5)
+    prm.solid, prm.psi_wall = porous_mask(shape, 5), wall_psi(c, base)
+    f0 = f0.copy()
+    f0[:, :, prm.solid] = 0.0
+    mask = drop_mask(shape, min(shape) / 2.0) & ~prm.solid
+    nsteps = 10
+    theta = oadj.theta_of(base)
+    x0 = oadj.mole_fractions(torch.as_tensor(f0, dtype=oadj.DT), base.M, mask).numpy()
+    x_tgt = x0 + np.array([0.01, -0.015, 0.005])
+    L, g = oadj.gradient(theta, f0, base, prm, lat, nsteps, mask, x_tgt)
+    assert np.all(np.isfinite(g))
+    assert abs(L - numpy_loss(theta, base, f0, prm, lat, nsteps, mask, x_tgt)) <= 1e-14 * L
+    h = 1e-6
+    for i in range(theta.size):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (numpy_loss(tp, base, f0, prm, lat, nsteps, mask, x_tgt)
+              - numpy_loss(tm, base, f0, prm, lat, nsteps, mask, x_tgt)) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-6 * np.max(np.abs(g)) + 1e-7 * abs(g[i]), (i, g[i], fd)
