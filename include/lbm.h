@@ -211,8 +211,8 @@ lbm_status lbm_clear_error(lbm_ctx* ctx);
  * being solid starts empty, outside the EOS domain, until lbm_set_populations fills
  * it).  It allocates the per-cell mask (4 bytes per cell, kept until lbm_destroy)
  * and a temporary of nc * Q * cells doubles, synchronises the stream, and is not
- * meant for graph capture.  Every schedule supports walls; the adjoint
- * (lbm_step_adjoint, lbm_adjoint) returns LBM_ERR_UNSUPPORTED while walls are set. */
+ * meant for graph capture.  Every schedule and the adjoint (lbm_step_adjoint,
+ * lbm_adjoint: solid cells carry no adjoint) support walls. */
 lbm_status lbm_set_solid(lbm_ctx* ctx, const unsigned char* solid_host, double psi_wall);
 
 /* Release the context (not the caller's workspace). NULL is accepted. */

@@ -133,7 +133,6 @@ lbm_status copy_state(const lbm_ctx* c, const Bufs& dst, const Bufs& src, const 
 
 lbm_status supported(const lbm_ctx* c) {
   if (!c) return lbm_fail(LBM_ERR_ARG, "ctx is NULL");
-  if (c->kp.bb) return lbm_fail(LBM_ERR_UNSUPPORTED, "the adjoint does not cover solid walls");
   return LBM_OK;
 }
 

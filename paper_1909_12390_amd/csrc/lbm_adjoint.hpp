@@ -46,6 +46,11 @@
 // equilibrium / source term above takes the moments of the vector that multiplies
 // it: EDM  feq(u): -g, feq(v): hs;   Guo  feq(u): hs - g, src: (hs + g)/2.
 //
+// Walls (P.bb): the forward pulls with halfway bounce-back, so the adjoint of f*_a(x)
+// at a fluid cell is h_{opp(a)}(x) where x + e_a is solid (bit opp(a) of x's mask)
+// and h_a(x + e_a) elsewhere; solid cells hold no fluid and a constant psi_w, so
+// they carry no adjoint (zero F^, j^, rbar^, output) and no EOS or parameter term.
+//
 // Two passes per step: ka_cell (everything local to x, writes F^, j^, the local
 // part of rbar^ and rbar) and kb_cell (the transposed psi stencil, the EOS adjoint,
 // the output and the parameter partials).  psi of the state comes from k_psi.
@@ -180,6 +185,19 @@ __device__ __forceinline__ void wgphi(const WMom& m, const double* v, double* ou
   for (int d = 0; d < 3; ++d) out[d] = -3.0 * m.A0 * v[d] + 3.0 * m.A1[d] + 9.0 * Av[d];
 }
 
+// The adjoint of the post-collision populations of cell x, one component
+// (hs [Q][cells]): h_a(x + e_a), or h_{opp(a)}(x) where x + e_a is solid.
+template <int LAT>
+__device__ __forceinline__ void gather_h(const double* hs, size_t N, const Coord& c, unsigned cell, unsigned bits,
+                                         double* hv) {
+  using V = VS<LAT>;
+#pragma unroll
+  for (int a = 0; a < V::Q; ++a) {
+    const bool back = (bits >> V::opp(a)) & 1u;
+    hv[a] = back ? hs[(size_t)V::opp(a) * N + cell] : hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))];
+  }
+}
+
 template <int LAT, int NC, int ST, int COLL, int FORC>
 __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, const double* __restrict__ psi,
                                                  const double* __restrict__ h, AdjScratch S) {
@@ -190,6 +208,20 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
   if (!launch_cell(P, 0, P.nplanes, &cell)) return;
   const Coord c = make_coord(cell, P);
   const size_t N = (size_t)P.cells;
+  const unsigned bits = P.bb ? P.bb[cell] : 0u;
+  if (bits >> kSolidBit) {          // solid cell: no adjoint
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+      S.rbA[(size_t)s * N + cell] = 0.0;
+      S.rb[(size_t)s * N + cell] = 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      S.Fbar[(size_t)d * N + cell] = 0.0;
+      S.jbar[(size_t)d * N + cell] = 0.0;
+    }
+    return;
+  }
   // forward quantities at x
   double rb[NC], rho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -198,7 +230,8 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
     double acc = 0.0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      const double v = (double)cv.get(a, c.at(-V::cx(a), -V::cy(a), -V::cz(a)), (R)V::w(a));
+      const unsigned nbr = c.at(-V::cx(a), -V::cy(a), -V::cz(a));
+      const double v = (double)(P.bb ? pull_bb<LAT>(cv, a, bits, cell, nbr, (R)V::w(a)) : cv.get(a, nbr, (R)V::w(a)));
       acc += v;
       if (V::cx(a)) j[0] += V::cx(a) * v;
       if (V::cy(a)) j[1] += V::cy(a) * v;
@@ -225,9 +258,7 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
   for (int s = 0; s < NC; ++s) {
     // the adjoint of f* (gathered from the downstream neighbours) and K applied to it
     double hv[Q], kv[Q];
-    const double* hs = h + (size_t)s * Q * N;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) hv[a] = hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))];
+    gather_h<LAT>(h + (size_t)s * Q * N, N, c, cell, bits, hv);
     apply_K<LAT, COLL>(P, hv, kv);
     const WMom A = wmoments<LAT>(hv), B = wmoments<LAT>(kv);
     if constexpr (FORC == LBM_EDM) {
@@ -310,7 +341,15 @@ __global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __res
 #pragma unroll
   for (int k = 0; k < K; ++k) vals[k] = 0.0;
   unsigned cell;
-  if (launch_cell(P, 0, P.nplanes, &cell)) {
+  const bool inside = launch_cell(P, 0, P.nplanes, &cell);
+  const unsigned bits = (inside && P.bb) ? P.bb[cell] : 0u;
+  if (inside && (bits >> kSolidBit)) {   // solid cell: no adjoint, no EOS or parameter term
+    const size_t N = (size_t)P.cells;
+#pragma unroll
+    for (int s = 0; s < NC; ++s)
+#pragma unroll
+      for (int a = 0; a < Q; ++a) hout[((size_t)s * Q + a) * N + cell] = 0.0;
+  } else if (inside) {
     const Coord c = make_coord(cell, P);
     const size_t N = (size_t)P.cells;
     const double hb = 0.5 * (1.0 - P.beta);
@@ -364,11 +403,9 @@ __global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __res
     const double jb[3] = {S.jbar[cell], S.jbar[N + cell], D == 3 ? S.jbar[2 * N + cell] : 0.0};
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
-      const double* hs = h + (size_t)s * Q * N;
       double* ho = hout + (size_t)s * Q * N;
       double hv[Q], kv[Q];
-#pragma unroll
-      for (int a = 0; a < Q; ++a) hv[a] = hs[(size_t)a * N + c.at(V::cx(a), V::cy(a), V::cz(a))];
+      gather_h<LAT>(h + (size_t)s * Q * N, N, c, cell, bits, hv);
       apply_K<LAT, COLL>(P, hv, kv);
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
@@ -391,10 +428,13 @@ __global__ __launch_bounds__(kBlock) void k_masked_moles(KParams P, Pops<ST> sta
   for (int s = 0; s < NC; ++s) vals[s] = 0.0;
   unsigned cell;
   if (launch_cell(P, 0, P.nplanes, &cell) && mask[cell]) {
-    const Coord c = make_coord(cell, P);
-    typename Pops<ST>::R jr[3] = {0, 0, 0};
+    const unsigned bits = P.bb ? P.bb[cell] : 0u;
+    if (!(bits >> kSolidBit)) {         // solid cells hold no fluid
+      const Coord c = make_coord(cell, P);
+      typename Pops<ST>::R jr[3] = {0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < NC; ++s) vals[s] = pull_moments<LAT, ST>(P, state, s, c, jr) * P.invM[s];
+      for (int s = 0; s < NC; ++s) vals[s] = pull_moments<LAT, ST>(P, state, s, c, jr, cell, bits) * P.invM[s];
+    }
   }
   block_partials<NC>(vals, partials);
 }

@@ -163,3 +163,69 @@ def test_full_case_gradient_matches_central_differences():
     rel = float(np.max(np.abs(g32 - g)) / np.max(np.abs(g)))
     print(f"  float32-storage gradient vs float64: max rel {rel:.3e}; loss {L32:.6e} vs {L:.6e}", flush=True)
     assert rel < 1e-2
+
+
+def porous(shape, seed, frac=0.15):
+    return np.random.default_rng([7, seed]).uniform(size=shape) < frac
+
+
+def wall_psi(c):
+    corner = c["rho0"][(slice(None),) + (0,) * len(c["shape"])]
+    return 1.3 * float(olbm.pseudo_potential(corner[:, None], c["T"], to_mixture(c["mix"]), -1.0)[0])
+
+
+@pytest.mark.parametrize("collision,forcing", [("bgk", "edm"), ("bgk", "guo"), ("mrt", "edm"), ("mrt", "guo")])
+@pytest.mark.parametrize("lattice,nc,shape", [("D2Q9", 3, (12, 14)), ("D3Q19", 2, (5, 6, 7))])
+def test_step_adjoint_with_walls_matches_oracle(lattice, nc, shape, collision, forcing):
+    print(f"case step adjoint walls {lattice} nc={nc} {shape} {collision} {forcing}", flush=True)
+    c = case(lattice, nc, shape, seed=1, u_amp=0.01)
+    c["u0"] = None
+    beta = 1.16 if forcing == "edm" else 1.7
+    rates = mrt_rates(lattice, 0.8) if collision == "mrt" else None
+    solid, pw = porous(shape, 11), wall_psi(c)
+    ctx = _lbm().LbmContext(c["mix"], lattice, c["shape"], c["T"], 0.8, beta, c["gamma"], c["rho0"],
+                            collision=collision, forcing=forcing, storage="f64", mrt_s=rates, solid=solid,
+                            psi_wall=pw)
+    ctx.step(3)
+    f = ctx.get_populations().cpu().numpy()
+    h = np.random.default_rng(5).standard_normal(f.shape)
+    hout, daa, db = ctx.step_adjoint(h)
+    ctx.check()
+    base = to_mixture(c["mix"])
+    prm = oracle_params(c, collision, forcing, tau=0.8, beta=beta, mrt_s=rates)
+    prm.solid, prm.psi_wall = solid, pw
+    aa, b = oadj.eos_tables(torch.as_tensor(oadj.theta_of(base), dtype=oadj.DT), base, c["T"])
+    gf, gaa, gb = oadj.step_vjp_tables(f, h, aa.numpy(), b.numpy(), base, prm, LAT[lattice])
+    ho = hout.cpu().numpy()
+    assert np.all(ho[:, :, solid] == 0.0)
+    assert np.max(np.abs(ho - gf)) <= 1e-11 * np.max(np.abs(gf))
+    assert np.max(np.abs(daa - gaa)) <= 1e-10 * np.max(np.abs(gaa))
+    assert np.max(np.abs(db - gb)) <= 1e-10 * np.max(np.abs(gb))
+
+
+@pytest.mark.parametrize("collision,forcing", [("bgk", "edm"), ("mrt", "guo")])
+def test_gradient_run_with_walls_matches_oracle_gradient(collision, forcing):
+    print(f"case adjoint run with walls {collision} {forcing}", flush=True)
+    shape = (12, 14)
+    c = case("D2Q9", 3, shape, seed=2)
+    base = to_mixture(c["mix"])
+    solid, pw = porous(shape, 12), wall_psi(c)
+    mask = inputs.drop_mask(shape, min(shape) / 2.0) & ~solid
+    f0 = olbm.init_populations(c["rho0"], LAT["D2Q9"])
+    f0[:, :, solid] = 0.0
+    x0 = oadj.mole_fractions(torch.as_tensor(f0, dtype=oadj.DT), base.M, mask).numpy()
+    x_tgt = x0 + np.array([0.01, -0.015, 0.005])
+    beta = 1.16 if forcing == "edm" else 1.7
+    rates = mrt_rates("D2Q9", 0.8) if collision == "mrt" else None
+    prm = oracle_params(c, collision, forcing, tau=0.8, beta=beta, mrt_s=rates)
+    prm.solid, prm.psi_wall = solid, pw
+    nsteps = 10
+    L, g = oadj.gradient(oadj.theta_of(base), f0, base, prm, LAT["D2Q9"], nsteps, mask, x_tgt)
+    from paper_1909_12390_amd import adjoint as padj
+    ctx = _lbm().LbmContext(c["mix"], "D2Q9", shape, c["T"], 0.8, beta, c["gamma"], c["rho0"], collision=collision,
+                            forcing=forcing, storage="f64", mrt_s=rates, solid=solid, psi_wall=pw)
+    r = ctx.adjoint(nsteps, 4, mask, x_tgt)
+    ctx.close()
+    gg = padj.pack_gradient(r["d_k"], r["d_a"], r["d_b"])
+    assert abs(r["loss"] - L) <= 1e-11 * L
+    assert np.max(np.abs(gg - g)) <= 1e-9 * np.max(np.abs(g))
