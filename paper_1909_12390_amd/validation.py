@@ -536,7 +536,7 @@ def run_oscillation(sizes=(200, 300, 400, 600, 800), steps=None, sample_every=50
 
 # ---------------------------------------------------------------------------
 # Wetting: contact angle of a drop on a wall against psi_w (solid walls are a
-# design of this build; the paper's porous-media motivation, Sec. 1)
+# design of this library; the paper's porous-media motivation, Sec. 1)
 # ---------------------------------------------------------------------------
 
 # the single-component fluid of Sec. 4.1 and its Maxwell densities at T = 0.9 Tc
