@@ -35,18 +35,13 @@ struct KParams {
 };
 constexpr unsigned kSolidBit = 31u;
 
-// Load / store one element at a 32-bit byte offset from an array base held in
-// scalar registers (used for psi).  Every array stays below 4 GiB (host check).
-template <typename T>
-__device__ __forceinline__ T ldb(const T* base, unsigned byte_off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
 // Raw buffer access for the population planes: a scalar buffer descriptor per
-// component, the per-lane byte offset of the cell in a vector register and the
-// byte offset of the direction plane in a scalar register.  Descriptor word 3 is
-// the gfx9 raw-buffer format (32-bit data format, no swizzle, no index stride);
-// num_records bounds every access to the component's planes.
+// component, a per-lane byte offset in a vector register and a wavefront-uniform
+// byte offset (direction plane, and in the row-structured kernels the row) in a
+// scalar register.  Descriptor word 3 is the gfx9 raw-buffer format (32-bit data
+// format, no swizzle, no index stride); num_records is the size of the
+// component's planes.  Every offset is formed inside the planes by construction
+// (cell and row indices below the box's cell count, planes below 4 GiB: host check).
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 __device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
