@@ -435,6 +435,96 @@ def run_laplace(p_list=(200.0, 240.0), sizes=(50, 100, 200, 400, 800), beta=1.91
 
 
 # ---------------------------------------------------------------------------
+# Laplace's law in three dimensions (D3Q19): a sphere has dp = 2 sigma / R, and the
+# tension of the flat interface does not depend on the lattice dimension, so the
+# slope should reproduce the two-dimensional sigma (a cross-check of the 3-D path)
+# ---------------------------------------------------------------------------
+
+def drop3d_case(p_psia, n, beta=1.915, tau=0.8, W=4.0, z1=0.4, names=("C3", "nC5")):
+    """A sphere of initial radius n/5 at the centre of an n^3 periodic box, the
+    radial profile of drop_case, phase densities from the flash at p_psia."""
+    c2 = drop_case(p_psia, 8, beta=beta, tau=tau, W=W, z1=z1, names=names)
+    fl = c2["flash"]
+    g = np.meshgrid(*[np.arange(n, dtype=np.float64)] * 3, indexing="ij")
+    r = np.sqrt(sum((x - n / 2.0) ** 2 for x in g))
+    t = np.tanh(2.0 * (r - n / 5.0) / W)
+    l = np.asarray(fl.rbar_l)[:, None, None, None]
+    v = np.asarray(fl.rbar_v)[:, None, None, None]
+    rho0 = 0.5 * (l + v) - 0.5 * (l - v) * t[None]
+    return {**c2, "shape": (n, n, n), "rho0": rho0, "n": n}
+
+
+def drop3d_measure(rho_s, mix, T):
+    """Radius at the level 0.5 (rho_l + rho_v) along the six axis rays from the
+    centre (averaged) and p_EOS at the centre and at the box corner; None once the
+    sphere has dissolved (below a critical size a small drop evaporates into the
+    vapour of a closed box)."""
+    r = np.asarray(rho_s)
+    rho = r.sum(axis=0)
+    n = rho.shape[0]
+    c = n // 2
+    rl, rv = rho[c, c, c], rho[0, 0, 0]
+    if not rl > 1.5 * rv:
+        return None
+    level = 0.5 * (rl + rv)
+    radii = []
+    for prof in (rho[c, c, c:], rho[c, c, c::-1], rho[c, c:, c], rho[c, c::-1, c], rho[c:, c, c], rho[c::-1, c, c]):
+        k = int(np.argmax(prof < level))
+        a, b = prof[k - 1], prof[k]
+        radii.append(k - 1 + (a - level) / (a - b))
+    M = np.asarray(mix["M"], dtype=np.float64)
+    n_l, n_v = r[:, c, c, c] / M, r[:, 0, 0, 0] / M
+    p = lbm.lbm_pressure(mix, T, np.stack([n_l, n_v]))
+    return {"R": float(np.mean(radii)), "p_l": float(p[0]), "p_v": float(p[1]), "dp": float(p[0] - p[1])}
+
+
+def run_laplace3d(p_list=(200.0,), sizes=(40, 60, 80, 100), beta=1.915, forcing="guo", max_steps=200_000,
+                  check_every=10_000, tol=1e-6, progress=None):
+    """All (pressure, size) spheres as one D3Q19 batch to steady state; per pressure
+    sigma is the least-squares slope of dp against 2/R (with intercept), and
+    sigma_n = dp_n R_n / 2 per sphere."""
+    cases = [drop3d_case(p, n, beta=beta) for p in p_list for n in sizes]
+    boxes = [{"mix": c["mix"], "shape": c["shape"], "T": c["T"], "tau": c["tau"], "beta": c["beta"],
+              "gamma": c["gamma"], "rho0": c["rho0"]} for c in cases]
+    b = lbm.LbmBatch(boxes, "D3Q19", collision="bgk", forcing=forcing, storage="f64",
+                     graph_steps=min(1000, check_every))
+    steps, prev, change = 0, None, float("inf")
+    try:
+        while steps < max_steps:
+            b.step(check_every)
+            steps += check_every
+            bad = b.box_errors()
+            if bad.any():
+                raise lbm.LbmError(lbm.LBM_ERR_DOMAIN, f"boxes {np.nonzero(bad)[0].tolist()} left the EOS domain")
+            meas = [drop3d_measure(r.cpu().numpy(), c["mix"], c["T"]) for r, c in zip(b.fields(), cases)]
+            cur = np.array([[m["R"], m["dp"]] if m is not None else [np.nan, np.nan] for m in meas])
+            if prev is not None:
+                ok = ~np.isnan(cur[:, 0]) & ~np.isnan(prev[:, 0])
+                change = float(np.max(np.abs(cur[ok] - prev[ok]) / np.abs(prev[ok]))) if ok.any() else 0.0
+            if progress is not None:
+                progress(steps, change)
+            if change < tol:
+                break
+            prev = cur
+        b.check()
+    finally:
+        b.close()
+    out = {"steps": steps, "last_change": change, "beta": beta, "forcing": forcing, "pressures": {}}
+    for p in p_list:
+        rows = [(c["n"], m) for c, m in zip(cases, meas) if c["p_psia"] == p and m is not None]
+        gone = [c["n"] for c, m in zip(cases, meas) if c["p_psia"] == p and m is None]
+        x = np.array([2.0 / m["R"] for _, m in rows])
+        dp = np.array([m["dp"] for _, m in rows])
+        sigma = icpt = float("nan")
+        if len(rows) >= 2:
+            A = np.stack([x, np.ones_like(x)], axis=1)
+            (sigma, icpt), *_ = np.linalg.lstsq(A, dp, rcond=None)
+        out["pressures"][str(p)] = {"sigma": float(sigma), "intercept": float(icpt), "dissolved": gone,
+                                    "drops": [{"n": n, "sigma_n": 0.5 * m["dp"] * m["R"], **m} for n, m in rows]}
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Oscillating elliptical drop (Sec. 4.3, Table 3)
 # ---------------------------------------------------------------------------
 
@@ -668,6 +758,7 @@ def main():
     ap.add_argument("--sigma-convergence", default="",
                     help="surface-tension convergence of a --laplace JSON file and exit")
     ap.add_argument("--contact-angle", action="store_true", help="sessile drop on a wall against psi_w instead")
+    ap.add_argument("--laplace3d", action="store_true", help="Laplace's law on D3Q19 spheres instead")
     ap.add_argument("--psi-fracs", default="0.1,0.3,0.5,0.7,0.9")
     args = ap.parse_args()
     ps = [float(p) for p in args.pressures.split(",")]
@@ -687,6 +778,11 @@ def main():
     if args.sigma_convergence:
         with open(args.sigma_convergence) as fh:
             print(json.dumps(sigma_convergence(json.loads(fh.read().strip().splitlines()[-1])), default=float))
+        return
+    if args.laplace3d:
+        out = run_laplace3d(ps, sizes=[int(n) for n in args.sizes.split(",")], beta=args.beta, forcing=args.forcing,
+                            **kw)
+        print(json.dumps(out, default=float))
         return
     if args.contact_angle:
         fields = {}

@@ -118,3 +118,21 @@ def test_contact_angle_of_a_circular_cap(theta):
     m = validation.contact_angle(rho, yw)
     assert abs(m["theta_deg"] - theta) < 1.5, m
     assert abs(m["R"] - R) < 1.0
+
+
+def test_sphere_measurement_recovers_radius_and_dissolution():
+    """A tanh sphere of radius 17.3 in a 64^3 box: the six-ray level crossing gives
+    the radius; centre and corner hold the flash's coexisting phases, so their
+    pressures agree (the Laplace jump appears only once the drop equilibrates); a
+    uniform vapour box reads as dissolved."""
+    n, R = 64, 17.3
+    g = np.meshgrid(*[np.arange(n, dtype=float)] * 3, indexing="ij")
+    r = np.sqrt(sum((x - n // 2) ** 2 for x in g))
+    prof = 0.5 * (1 - np.tanh(2.0 * (r - R) / 4.0))
+    c = validation.drop3d_case(200.0, 8)
+    l, v = np.asarray(c["flash"].rbar_l), np.asarray(c["flash"].rbar_v)
+    rho = v[:, None, None, None] + (l - v)[:, None, None, None] * prof[None]
+    m = validation.drop3d_measure(rho, c["mix"], c["T"])
+    assert abs(m["R"] - R) < 0.05
+    assert abs(m["dp"]) < 1e-5 * m["p_l"]
+    assert validation.drop3d_measure(np.broadcast_to(v[:, None, None, None], rho.shape), c["mix"], c["T"]) is None
