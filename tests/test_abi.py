@@ -76,7 +76,8 @@ def test_mrt_rates_checked():
     assert _bytes(collision="mrt", mrt_s=[1.0] * 8 + [2.5])[0] == lbm.LBM_ERR_ARG
 
 
-def _batch_layout(nboxes=2, tile=0, grid=0, graph_steps=0, nc=2, lattice="D2Q9", shape=(8, 16), gamma=None):
+def _batch_layout(nboxes=2, tile=0, grid=0, graph_steps=0, nc=2, lattice="D2Q9", shape=(8, 16), gamma=None,
+                  solid=None, psi_wall=0.0):
     n = nboxes
     arr = (lbm.LbmBox * max(n, 1))()
     for i in range(n):
@@ -86,6 +87,9 @@ def _batch_layout(nboxes=2, tile=0, grid=0, graph_steps=0, nc=2, lattice="D2Q9",
         arr[i].T, arr[i].tau, arr[i].G, arr[i].beta = 0.06, 0.8, -1.0, 1.16
         for k, g in enumerate(gamma if gamma is not None else [0.5, 1.0]):
             arr[i].gamma[k] = g
+        if solid is not None and i == 0:
+            arr[i].solid = solid.ctypes.data
+            arr[i].psi_wall = psi_wall
     prm = lbm.LbmBatchParams()
     prm.lattice = lbm.LATTICES[lattice]
     prm.collision, prm.forcing, prm.storage = 0, 1, 2
@@ -124,3 +128,27 @@ def test_host_validation_rejects_planes_past_4gib():
     assert _bytes(lattice="D3Q19", shape=(310, 310, 310))[0] == lbm.LBM_ERR_ARG   # 19 x 8 x 2.98e7 B > 4 GiB
     assert _bytes(lattice="D3Q19", shape=(300, 300, 300))[0] == lbm.LBM_OK        # 19 x 8 x 2.70e7 B < 4 GiB
     assert _bytes(lattice="D3Q19", shape=(128, 128, 128))[0] == lbm.LBM_OK
+
+
+def test_batch_walls_layout_and_validation():
+    """Wall masks take 4 bytes per cell of the boxes that have walls, in the caller's
+    workspace; a non-finite or negative wall psi is refused on the host."""
+    solid = np.zeros((8, 16), dtype=np.uint8)
+    solid[0] = 1
+    code0, ws0, _, _ = _batch_layout(nboxes=3)
+    code1, ws1, _, _ = _batch_layout(nboxes=3, solid=solid, psi_wall=0.5)
+    assert code0 == lbm.LBM_OK and code1 == lbm.LBM_OK
+    assert ws1 >= ws0 + 8 * 16 * 4
+    for pw in (float("nan"), -0.1, float("inf")):
+        assert _batch_layout(nboxes=2, solid=solid, psi_wall=pw)[0] == lbm.LBM_ERR_ARG
+
+
+def test_context_calls_reject_null_handles():
+    """Host-side argument checks of the calls added for walls, gamma updates and
+    graph replay (no device needed)."""
+    L = lbm.lib()
+    g = np.full(4, 0.5)
+    assert L.lbm_set_solid(None, None, ctypes.c_double(0.0)) == lbm.LBM_ERR_ARG
+    assert L.lbm_set_graph_steps(None, 4) == lbm.LBM_ERR_ARG
+    assert L.lbm_set_gamma(None, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == lbm.LBM_ERR_ARG
+    assert L.lbm_step(None, 1) == lbm.LBM_ERR_ARG
