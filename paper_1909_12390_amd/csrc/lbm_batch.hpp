@@ -205,10 +205,13 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restr
     const BoxK& B = boxes[bx];
     const int nc = B.nc;
     const unsigned cell = (t - B.first_tile) * (unsigned)tile + (unsigned)lane;
-    // solid cells (walls) take no part: no pull, no force, no collision, no store
+    // solid cells (walls) do not pull and do not collide; their slots are never
+    // read and hold zeros, which their lanes store again so that the tile's rows
+    // are written whole
     const unsigned bits = (B.walls && cell < B.cells) ? K.bb[B.bb_off + cell] : 0u;
     const bool in_box = cell < B.cells && !(bits >> kSolidBit);
     const bool active = in_box && s < nc;
+    const bool store = cell < B.cells && s < nc;
     const Coord c = box_coord(cell < B.cells ? cell : 0u, B);
     R f[Q];
     R jx = 0, jy = 0, jz = 0;
@@ -225,6 +228,9 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restr
         if (V::cy(a)) jy += (R)V::cy(a) * f[a];
         if (V::cz(a)) jz += (R)V::cz(a) * f[a];
       }
+    } else {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) f[a] = 0;
     }
     if (in_box) {
       const double* ps = psi + B.psi_off;
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restr
     red[5 * tile + lane] = Fp[1];
     red[6 * tile + lane] = Fp[2];
     __syncthreads();
-    if (active) {
+    if (store) {
       double rho = 0.0, Gam = 0.0, j[3] = {0.0, 0.0, 0.0}, F[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < NCMAX; ++q) {
@@ -270,7 +276,7 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restr
       F[0] *= -B.G;
       F[1] *= -B.G;
       F[2] *= -B.G;
-      if (!(Gam > 0.0)) batch_flag(K, bx);
+      if (active && !(Gam > 0.0)) batch_flag(K, bx);
       const R g0 = (R)K.accel[0], g1 = (R)K.accel[1], g2 = (R)K.accel[2];
       const R rhoR = (R)rho, irho = (R)1 / rhoR;
       const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
@@ -295,6 +301,10 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restr
         fs[0] = ch * FR[0] + g0;
         fs[1] = ch * FR[1] + g1;
         fs[2] = ch * FR[2] + g2;
+      }
+      if (!active) {   // a solid cell: f = 0, rbar = 0 and u = du = 0 collide to zeros
+        u[0] = u[1] = u[2] = 0;
+        fs[0] = fs[1] = fs[2] = 0;
       }
       P.cells = (int)B.cells;
       P.omega = B.omega;

@@ -778,13 +778,18 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   double Fp[3] = {0.0, 0.0, 0.0};
   // every lane pulls (lanes past the row end at x = 0; all addresses in range)
   if (P.bb) {
-    // walls: solid cells take no part (no collision, no store); a pull whose
-    // source is solid reads the cell's own opposite population (halfway bounce-back)
+    // walls: solid cells do not pull and do not collide; a pull whose source is
+    // solid reads the cell's own opposite population (halfway bounce-back).  A
+    // solid cell's slots are never read and hold zeros; its lane stores those
+    // zeros again, so that every row is written whole (no partially written lines)
     valid = valid && !(bits >> kSolidBit);
     if (valid) {
 #pragma unroll
       for (int a = 0; a < Q; ++a)
         f[a] = pull_bb<LAT>(cv, a, bits, own, c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a)), (R)V::w(a));
+    } else {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) f[a] = 0;
     }
   } else if constexpr (ST != LBM_F64) {
     pull_row_offset<LAT>(cv, c, (unsigned)P.nx, f);
@@ -823,7 +828,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   red[s][5][lane] = Fp[1];
   red[s][6][lane] = Fp[2];
   __syncthreads();
-  if (!valid) return;
+  if (!in_row) return;
   double rho = 0.0, Gam = 0.0, j[3] = {0.0, 0.0, 0.0}, F[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int t = 0; t < NC; ++t) {
@@ -840,7 +845,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   F[0] *= -P.G;
   F[1] *= -P.G;
   F[2] *= -P.G;
-  if (!(Gam > 0.0)) flag_error(P);
+  if (valid && !(Gam > 0.0)) flag_error(P);
   // velocity and split in the collision precision R (float64 storage: double)
   const R g0 = (R)P.accel[0], g1 = (R)P.accel[1], g2 = (R)P.accel[2];
   const R rhoR = (R)rho, irho = (R)1 / rhoR;
@@ -866,6 +871,10 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
     fs[0] = ch * FR[0] + g0;
     fs[1] = ch * FR[1] + g1;
     fs[2] = ch * FR[2] + g2;
+  }
+  if (!valid) {   // a solid cell (walls): f = 0, rbar = 0 and u = du = 0 collide to zeros
+    u[0] = u[1] = u[2] = 0;
+    fs[0] = fs[1] = fs[2] = 0;
   }
   collide_store<LAT, ST, COLL, FORC>(P, out, s, c.x(0), c.row(0, 0), f, rs, u, fs, mass);
 }
