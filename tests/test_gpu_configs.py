@@ -12,6 +12,10 @@ configurations bench.py times.
   own input state and its centre is exact.  Samples include the row-segment edges
   (x = 0, 63, 64, 127) and the periodic faces.  float64 to 1e-12; the benchmarked
   float16 two-pass configuration to 1e-4 of max |f| (one re-encoding).
+* C3 inside the synthetic porous medium the benchmark's walls section uses (random
+  overlapping spheres of radius 6, solid fraction 0.30, psi_w midway between the
+  phases): the same patch check with the patch of the solid mask, on cells next to
+  walls, solid cells and row-segment edges; float64 to 1e-12, float16 to 1e-4.
 * C4 (512 independent boxes, tile 64, persistent grid) is checked box by box on a
   sample of boxes of every side, against the oracle stepping each box alone.
 """
@@ -113,6 +117,65 @@ def test_c3_full_size_sampled_cells(storage, tol):
         worst = max(worst, err)
         assert err < tol, (c, err)
     print(f"  worst sampled error {worst:.2e} over {len(c3_samples(n))} cells", flush=True)
+
+
+def wall_samples(solid, seed=5):
+    """Fluid cells with a solid neighbour (D3Q19), solid cells, fluid cells at the
+    row-segment edges x = 0, 63, 64, 127 and random fluid cells, as (z, y, x)."""
+    rng = np.random.default_rng([12390, seed])
+    near = np.zeros_like(solid)
+    for e in LAT["D3Q19"].e[1:]:
+        near |= np.roll(solid, shift=tuple(int(v) for v in e[::-1]), axis=(0, 1, 2))
+    near &= ~solid
+    pts = []
+    for mask, k in ((near, 16), (solid, 4), (~solid, 6)):
+        idx = np.argwhere(mask)
+        pts += [tuple(int(v) for v in idx[i]) for i in rng.choice(len(idx), size=k, replace=False)]
+    n = solid.shape[2]
+    for x in (0, 63, 64, n - 1):
+        col = np.argwhere(~solid[:, :, x])
+        z, y = col[rng.integers(len(col))]
+        pts.append((int(z), int(y), x))
+    return pts
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f16", 1e-4)])
+def test_c3_walls_full_size_sampled_cells(storage, tol):
+    cfg = inputs.config_c3(BACKEND)
+    solid = inputs.porous_spheres(cfg.shape, 0.30, 6.0, seed=0)
+    print(f"case C3 walls {cfg.shape} {storage} solid fraction {solid.mean():.3f}, sampled cells", flush=True)
+    ctx = context(cfg, storage)
+    psi = ctx.moments(fields=True, totals=False)["psi"]
+    h = cfg.shape[0] // 2
+    psi_w = 0.5 * float(psi[0, 0, 0].item() + psi[h, h, h].item())   # midway between the phases
+    del psi
+    ctx.set_solid(solid, psi_w)
+    ctx.step(2)
+    ctx.check()
+    f0 = ctx.get_populations().cpu().numpy()
+    ctx.step(1)
+    ctx.check()
+    f1 = ctx.get_populations().cpu().numpy()
+    del ctx
+    torch.cuda.empty_cache()
+    m = to_mixture(cfg.mix)
+    prm = oracle_prm(cfg)
+    prm.psi_wall = psi_w
+    scale = np.max(np.abs(f1), axis=(1, 2, 3, 4))
+    worst = 0.0
+    pts = wall_samples(solid)
+    for c in pts:
+        idx = [np.arange(v - 2, v + 3) % n for v, n in zip(c, solid.shape)]
+        prm.solid = solid[idx[0]][:, idx[1]][:, :, idx[2]]
+        ref = olbm.step(patch(f0, c), m, prm, LAT["D3Q19"])[:, :, 2, 2, 2]
+        got = f1[:, :, c[0], c[1], c[2]]
+        if solid[c]:
+            assert np.all(got == 0.0) and np.all(ref == 0.0), c
+            continue
+        err = float(np.max(np.abs(got - ref) / scale[:, None]))
+        worst = max(worst, err)
+        assert err < tol, (c, err)
+    print(f"  worst sampled error {worst:.2e} over {len(pts)} cells", flush=True)
 
 
 def test_c4_full_batch_sampled_boxes():
