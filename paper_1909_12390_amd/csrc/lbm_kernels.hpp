@@ -46,24 +46,40 @@ using rsrc_t = __amdgpu_buffer_rsrc_t;
 __device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
+// CP: the instruction's cache-policy bits (bit 1 = nt, non-temporal: the line is
+// not kept for reuse).  Each population plane is read once per pass (the psi pass
+// and the collide pass read it once each) and written once per step, while the
+// per-cell bases and psi are read again from the source rows of three planes; the
+// population loads are therefore non-temporal, so that they do not evict the lines
+// that are read again.  Stores keep the default policy (measured: non-temporal
+// stores speed up the next psi pass but slow the collide pass by more).
+constexpr int kPopLoad = 2;
+constexpr int kPopStore = 0;
+constexpr int kBaseStore = 0;
+template <int CP = 0>
 __device__ __forceinline__ double bload(rsrc_t r, unsigned voff, unsigned soff, double) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, CP));
 }
+template <int CP = 0>
 __device__ __forceinline__ float bload(rsrc_t r, unsigned voff, unsigned soff, float) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, CP));
 }
+template <int CP = 0>
 __device__ __forceinline__ float bload(rsrc_t r, unsigned voff, unsigned soff, __half) {
-  return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+  return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, CP)));
 }
+template <int CP = 0>
 __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
-                                        r, voff, soff, 0);
+                                        r, voff, soff, CP);
 }
+template <int CP = 0>
 __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, CP);
 }
+template <int CP = 0>
 __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, __half v) {
-  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, CP);
 }
 
 // ---------------------------------------------------------------------------
@@ -88,32 +104,32 @@ struct Pops<LBM_F64> {
     rsrc_t rf;
     unsigned plane;   // bytes per direction plane
     __device__ __forceinline__ double get(int a, unsigned idx, double) const {
-      return bload(rf, idx * 8u, (unsigned)a * plane, 0.0);
+      return bload<kPopLoad>(rf, idx * 8u, (unsigned)a * plane, 0.0);
     }
     // per-lane direction plane: pbytes = direction * plane
     __device__ __forceinline__ double get_at(unsigned idx, unsigned pbytes, double) const {
-      return bload(rf, idx * 8u + pbytes, 0u, 0.0);
+      return bload<kPopLoad>(rf, idx * 8u + pbytes, 0u, 0.0);
     }
     // all Q directions, direction a from cell src(a): loads first, then decode
     template <int Q, typename Src, typename W>
     __device__ __forceinline__ void get_all(Src src, double* out, W) const {
 #pragma unroll
-      for (int a = 0; a < Q; ++a) out[a] = bload(rf, src(a) * 8u, (unsigned)a * plane, 0.0);
+      for (int a = 0; a < Q; ++a) out[a] = bload<kPopLoad>(rf, src(a) * 8u, (unsigned)a * plane, 0.0);
     }
     template <int Q, typename W>
     __device__ __forceinline__ void put_all(unsigned idx, const double* v, double, W) const {
 #pragma unroll
-      for (int a = 0; a < Q; ++a) bstore(rf, idx * 8u, (unsigned)a * plane, v[a]);
+      for (int a = 0; a < Q; ++a) bstore<kPopStore>(rf, idx * 8u, (unsigned)a * plane, v[a]);
     }
     // row-structured forms: per-lane offset xo within the row, wave-uniform row
     // offset ro (in cells) folded into the scalar offset of the buffer instruction
     __device__ __forceinline__ double get_row(int a, unsigned xo, unsigned ro, double) const {
-      return bload(rf, xo * 8u, (unsigned)a * plane + ro * 8u, 0.0);
+      return bload<kPopLoad>(rf, xo * 8u, (unsigned)a * plane + ro * 8u, 0.0);
     }
     template <int Q, typename W>
     __device__ __forceinline__ void put_all_row(unsigned xo, unsigned ro, const double* v, double, W) const {
 #pragma unroll
-      for (int a = 0; a < Q; ++a) bstore(rf, xo * 8u, (unsigned)a * plane + ro * 8u, v[a]);
+      for (int a = 0; a < Q; ++a) bstore<kPopStore>(rf, xo * 8u, (unsigned)a * plane + ro * 8u, v[a]);
     }
   };
   __device__ __forceinline__ View comp(int s, int Q, int cells) const {
@@ -133,14 +149,14 @@ struct OffsetPops {
     const float* bp;  // the base array itself (wavefront-uniform scalar loads)
     using Elem = H;
     __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
-      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
+      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<kPopLoad>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
     }
     __device__ __forceinline__ float get_at(unsigned idx, unsigned pbytes, float w) const {
-      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload(rr, idx * (unsigned)sizeof(H) + pbytes, 0u, H()));
+      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<kPopLoad>(rr, idx * (unsigned)sizeof(H) + pbytes, 0u, H()));
     }
     __device__ __forceinline__ float get_row(int a, unsigned xo, unsigned ro, float w) const {
       return bload(rb, xo * 4u, ro * 4u, 0.0f) *
-             (w + bload(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), H()));
+             (w + bload<kPopLoad>(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), H()));
     }
     // all Q directions, direction a from cell src(a): every load is issued before
     // the first decode, so the wavefront keeps 2Q loads in flight
@@ -151,7 +167,7 @@ struct OffsetPops {
       for (int a = 0; a < Q; ++a) {
         const unsigned idx = src(a);
         bq[a] = bload(rb, idx * 4u, 0u, 0.0f);
-        rq[a] = bload(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H());
+        rq[a] = bload<kPopLoad>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H());
       }
       __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the decode
 #pragma unroll
@@ -188,10 +204,10 @@ struct OffsetPops {
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const H r = enc(v[a] * inv - wm * w(a));
-        bstore(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), r);
+        bstore<kPopStore>(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), r);
         S += (double)(w(a) + (float)r);
       }
-      bstore(rb, xo * 4u, ro * 4u, S >= 0.5 ? (float)(mass / S) : b0);
+      bstore<kBaseStore>(rb, xo * 4u, ro * 4u, S >= 0.5 ? (float)(mass / S) : b0);
     }
   };
   __device__ __forceinline__ View comp(int s, int Q, int cells) const {
@@ -675,7 +691,7 @@ __device__ __forceinline__ void pull_row_offset(const View& cv, const RowCoord& 
   });
 #pragma unroll
   for (int a = 0; a < Q; ++a)
-    rq[a] = bload(cv.rr, c.x(-V::cx(a)) * (unsigned)sizeof(H),
+    rq[a] = bload<kPopLoad>(cv.rr, c.x(-V::cx(a)) * (unsigned)sizeof(H),
                   (unsigned)a * cv.plane + c.row(-V::cy(a), -V::cz(a)) * (unsigned)sizeof(H), H());
   __builtin_amdgcn_sched_barrier(0);   // every load ahead of the shifts and the decode
   static_for<0, Q>([&](auto A) {
