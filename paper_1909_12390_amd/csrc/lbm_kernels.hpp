@@ -143,20 +143,22 @@ struct OffsetPops {
   using R = float;
   float* base;
   H* r;
-  struct View {
+  // LP: cache policy of the offset loads (kPopLoad; the batched kernels choose their own)
+  template <int LP>
+  struct ViewT {
     rsrc_t rb, rr;
     unsigned plane;   // bytes per direction plane of r
     const float* bp;  // the base array itself (wavefront-uniform scalar loads)
     using Elem = H;
     __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
-      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<kPopLoad>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
+      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<LP>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
     }
     __device__ __forceinline__ float get_at(unsigned idx, unsigned pbytes, float w) const {
-      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<kPopLoad>(rr, idx * (unsigned)sizeof(H) + pbytes, 0u, H()));
+      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<LP>(rr, idx * (unsigned)sizeof(H) + pbytes, 0u, H()));
     }
     __device__ __forceinline__ float get_row(int a, unsigned xo, unsigned ro, float w) const {
       return bload(rb, xo * 4u, ro * 4u, 0.0f) *
-             (w + bload<kPopLoad>(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), H()));
+             (w + bload<LP>(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), H()));
     }
     // all Q directions, direction a from cell src(a): every load is issued before
     // the first decode, so the wavefront keeps 2Q loads in flight
@@ -167,7 +169,7 @@ struct OffsetPops {
       for (int a = 0; a < Q; ++a) {
         const unsigned idx = src(a);
         bq[a] = bload(rb, idx * 4u, 0u, 0.0f);
-        rq[a] = bload<kPopLoad>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H());
+        rq[a] = bload<LP>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H());
       }
       __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the decode
 #pragma unroll
@@ -210,6 +212,7 @@ struct OffsetPops {
       bstore<kBaseStore>(rb, xo * 4u, ro * 4u, S >= 0.5 ? (float)(mass / S) : b0);
     }
   };
+  using View = ViewT<kPopLoad>;
   __device__ __forceinline__ View comp(int s, int Q, int cells) const {
     const unsigned plane = (unsigned)cells * (unsigned)sizeof(H);
     return View{make_rsrc(base + (size_t)s * cells, (unsigned)cells * 4u),
