@@ -56,6 +56,19 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes) {
 constexpr int kPopLoad = 2;
 constexpr int kPopStore = 0;
 constexpr int kBaseStore = 0;
+// 1.0f that the compiler cannot fold (an empty asm statement owns its value, no
+// instruction is emitted).  w + r with r widened from float16 is then written
+// fmaf(r, one, w): r * 1 is exact, so the result is the float32 sum itself, and it
+// compiles to one mixed-precision FMA (v_fma_mix_f32 reading r as float16) in
+// place of a conversion and an add.
+__device__ __forceinline__ float opaque_one() {
+  float one = 1.0f;
+  asm("" : "+s"(one));
+  return one;
+}
+// w + r (float32 sum) for an offset r loaded as float16 (or float32)
+__device__ __forceinline__ float w_plus(float w, float r, float one) { return __builtin_fmaf(r, one, w); }
+
 template <int CP = 0>
 __device__ __forceinline__ double bload(rsrc_t r, unsigned voff, unsigned soff, double) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, CP));
@@ -126,7 +139,7 @@ struct Pops<LBM_F64> {
     __device__ __forceinline__ double get_row(int a, unsigned xo, unsigned ro, double) const {
       return bload<kPopLoad>(rf, xo * 8u, (unsigned)a * plane + ro * 8u, 0.0);
     }
-    template <int Q, typename W>
+    template <int Q, bool MIX = false, typename W>
     __device__ __forceinline__ void put_all_row(unsigned xo, unsigned ro, const double* v, double, W) const {
 #pragma unroll
       for (int a = 0; a < Q; ++a) bstore<kPopStore>(rf, xo * 8u, (unsigned)a * plane + ro * 8u, v[a]);
@@ -194,7 +207,9 @@ struct OffsetPops {
     __device__ __forceinline__ void put_all(unsigned idx, const float* v, double mass, W w) const {
       put_all_row<Q>(idx, 0u, v, mass, w);
     }
-    template <int Q, typename W>
+    // MIX: form w + r with the mixed-precision FMA (same values, fewer instructions;
+    // the single-box collide pass, where it does not cost registers)
+    template <int Q, bool MIX = false, typename W>
     __device__ __forceinline__ void put_all_row(unsigned xo, unsigned ro, const float* v, double mass, W w) const {
       float b0 = 0.0f;
 #pragma unroll
@@ -203,11 +218,13 @@ struct OffsetPops {
       const float inv = (b0 > 0.0f) ? __builtin_amdgcn_rcpf(b0) : 0.0f;
       const float wm = (b0 > 0.0f) ? 1.0f : 0.0f;
       double S = 0.0;
+      const float one = opaque_one();
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const H r = enc(v[a] * inv - wm * w(a));
         bstore<kPopStore>(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), r);
-        S += (double)(w(a) + (float)r);
+        if constexpr (MIX) S += (double)w_plus(w(a), (float)r, one);
+        else S += (double)(w(a) + (float)r);
       }
       bstore<kBaseStore>(rb, xo * 4u, ro * 4u, S >= 0.5 ? (float)(mass / S) : b0);
     }
@@ -427,6 +444,12 @@ __device__ __forceinline__ void force_at(const KParams& P, double ps, PsiAt psi_
   F[2] = -P.G * fz;
 }
 
+// a / b in the collision precision: float64 divides (correctly rounded); float32
+// multiplies by the hardware reciprocal (1 ulp), an error below the float32
+// collision's own rounding, in place of the ~10-instruction exact division.
+__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+__device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // Compile-time loop: f(integral_constant<int, I>) for I in [B, E).
 template <int B, int E, typename Fn>
 __device__ __forceinline__ void static_for(Fn&& fn) {
@@ -628,7 +651,7 @@ __device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& 
   using R = typename Pops<ST>::R;
   constexpr int Q = V::Q;
   collide_values<LAT, R, COLL, FORC>(P, f, rs, u3, F3, [&](const R* fo) {
-    out.comp(s, Q, P.cells).template put_all_row<Q>(xo, ro, fo, mass, [](int a) { return (R)V::w(a); });
+    out.comp(s, Q, P.cells).template put_all_row<Q, true>(xo, ro, fo, mass, [](int a) { return (R)V::w(a); });
   });
 }
 
@@ -673,7 +696,10 @@ __host__ __device__ constexpr bool row_shifted(int r) {
 // wavefront-uniform scalar loads.  In a row shorter than the wavefront the lanes
 // past its end hold x = 0, so the last cell's right neighbour is the first cell,
 // as periodicity requires.  All lanes must be active; f gets the decoded pulls.
-template <int LAT, typename View>
+// MIX: decode w + r with the mixed-precision FMA (fewer instructions, same values;
+// the collide pass); the psi pass, bound by memory, keeps the add, whose schedule
+// needs fewer registers (98 against 91 VGPRs cost it a wave per SIMD).
+template <int LAT, bool MIX, typename View>
 __device__ __forceinline__ void pull_row_offset(const View& cv, const RowCoord& c, unsigned nx, float* f) {
   using V = VS<LAT>;
   constexpr int Q = V::Q;
@@ -697,6 +723,7 @@ __device__ __forceinline__ void pull_row_offset(const View& cv, const RowCoord& 
     rq[a] = bload<kPopLoad>(cv.rr, c.x(-V::cx(a)) * (unsigned)sizeof(H),
                   (unsigned)a * cv.plane + c.row(-V::cy(a), -V::cz(a)) * (unsigned)sizeof(H), H());
   __builtin_amdgcn_sched_barrier(0);   // every load ahead of the shifts and the decode
+  const float one = opaque_one();
   static_for<0, Q>([&](auto A) {
     constexpr int a = decltype(A)::value;
     constexpr int r = pull_row<LAT>(a);
@@ -704,7 +731,8 @@ __device__ __forceinline__ void pull_row_offset(const View& cv, const RowCoord& 
     if constexpr (V::cx(a) == 0) b = bq[r];
     else if constexpr (V::cx(a) > 0) b = lane_from_left(bq[r], hl[r]);   // source x - 1
     else b = lane_from_right(bq[r], hr[r]);                              // source x + 1
-    f[a] = b * ((float)V::w(a) + rq[a]);
+    if constexpr (MIX) f[a] = b * w_plus((float)V::w(a), rq[a], one);
+    else f[a] = b * ((float)V::w(a) + rq[a]);
   });
 }
 
@@ -742,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* 
         for (int a = 0; a < Q; ++a) v[a] = 0;
       }
     } else if constexpr (ST != LBM_F64) {
-      pull_row_offset<LAT>(cv, c, (unsigned)P.nx, v);
+      pull_row_offset<LAT, false>(cv, c, (unsigned)P.nx, v);
     } else {
 #pragma unroll
       for (int a = 0; a < Q; ++a) v[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
@@ -766,6 +794,32 @@ inline unsigned psi_blocks(const KParams& P, int np, int D) {
 }
 
 // pass 2: a block is 64 cells x NC wavefronts, wavefront s working on component s.
+// psi at a cell and at the stencil directions a with (a - 1) mod NC == s of the
+// wavefront of component s; a uniform branch on s keeps every direction's offsets
+// compile-time constants (all addresses in range).
+template <int LAT, int NC>
+struct PsiShare {
+  double ps;
+  double pn[(VS<LAT>::Q - 1 + NC - 1) / NC];
+};
+template <int LAT, int NC>
+__device__ __forceinline__ PsiShare<LAT, NC> load_psi_share(rsrc_t psr, const RowCoord& c, int s) {
+  using V = VS<LAT>;
+  PsiShare<LAT, NC> v;
+  v.ps = bload(psr, c.x(0) * 8u, c.row(0, 0) * 8u, 0.0);
+  static_for<0, NC>([&](auto S_) {
+    constexpr int S = decltype(S_)::value;
+    if (s == S) {
+      static_for<1, V::Q>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        if constexpr ((a - 1) % NC == S)
+          v.pn[(a - 1) / NC] = bload(psr, c.x(V::cx(a)) * 8u, c.row(V::cy(a), V::cz(a)) * 8u, 0.0);
+      });
+    }
+  });
+  return v;
+}
+
 // Each wavefront pulls its component (rbar_s, j_s) and sums the psi stencil over
 // the directions a with (a - 1) mod NC == s; the block combines the per-component
 // sums through LDS in a fixed component order (rho, Gamma, j, F identical in every
@@ -791,6 +845,12 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   const rsrc_t psr = make_rsrc(psi, (unsigned)P.cells * 8u);
   const unsigned own = c.row(0, 0) + c.x(0);
   const unsigned bits = P.bb ? P.bb[own] : 0u;   // walls: per-cell direction mask
+  // psi at the cell and at this wavefront's stencil directions: the offset formats
+  // load them ahead of the pulls, so that their latency overlaps the pulls'
+  // (float16 collide -5 %); the float64 kernel, bound by HBM bandwidth, loads them
+  // after its pulls (ahead: +1.6 %)
+  PsiShare<LAT, NC> pv{};
+  if constexpr (ST != LBM_F64) pv = load_psi_share<LAT, NC>(psr, c, s);
   R f[Q];
   R rs = 0, jx = 0, jy = 0, jz = 0;
   double mass = 0.0;   // the component's mass, summed exactly (rs in float64 storage)
@@ -811,7 +871,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
       for (int a = 0; a < Q; ++a) f[a] = 0;
     }
   } else if constexpr (ST != LBM_F64) {
-    pull_row_offset<LAT>(cv, c, (unsigned)P.nx, f);
+    pull_row_offset<LAT, true>(cv, c, (unsigned)P.nx, f);
   } else {
 #pragma unroll
     for (int a = 0; a < Q; ++a) f[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
@@ -826,18 +886,31 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
     }
     rs = (R)mass;
     // partial stencil of Eq. (coupledMCforce) over this wavefront's directions
-    const double ps = bload(psr, c.x(0) * 8u, c.row(0, 0) * 8u, 0.0);
     const double hb = 0.5 * (1.0 - P.beta);
-    static_for<1, Q>([&](auto A) {
+    auto term = [&](auto A, double ps, double pn) {
       constexpr int a = decltype(A)::value;
-      if ((a - 1) % NC == s) {
-        const double pn = bload(psr, c.x(V::cx(a)) * 8u, c.row(V::cy(a), V::cz(a)) * 8u, 0.0);
-        const double t = V::w(a) * pn * (P.beta * ps + hb * pn);
-        if constexpr (V::cx(a) != 0) Fp[0] += V::cx(a) * t;
-        if constexpr (V::cy(a) != 0) Fp[1] += V::cy(a) * t;
-        if constexpr (V::cz(a) != 0) Fp[2] += V::cz(a) * t;
-      }
-    });
+      const double t = V::w(a) * pn * (P.beta * ps + hb * pn);
+      if constexpr (V::cx(a) != 0) Fp[0] += V::cx(a) * t;
+      if constexpr (V::cy(a) != 0) Fp[1] += V::cy(a) * t;
+      if constexpr (V::cz(a) != 0) Fp[2] += V::cz(a) * t;
+    };
+    if constexpr (ST == LBM_F64) {   // each psi loaded where it is used
+      const double ps = bload(psr, c.x(0) * 8u, c.row(0, 0) * 8u, 0.0);
+      static_for<1, Q>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        if ((a - 1) % NC == s) term(A, ps, bload(psr, c.x(V::cx(a)) * 8u, c.row(V::cy(a), V::cz(a)) * 8u, 0.0));
+      });
+    } else {
+      static_for<0, NC>([&](auto S_) {
+        constexpr int S = decltype(S_)::value;
+        if (s == S) {
+          static_for<1, Q>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            if constexpr ((a - 1) % NC == S) term(A, pv.ps, pv.pn[(a - 1) / NC]);
+          });
+        }
+      });
+    }
   }
   red[s][0][lane] = mass;
   red[s][1][lane] = (double)jx;
@@ -867,7 +940,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   if (valid && !(Gam > 0.0)) flag_error(P);
   // velocity and split in the collision precision R (float64 storage: double)
   const R g0 = (R)P.accel[0], g1 = (R)P.accel[1], g2 = (R)P.accel[2];
-  const R rhoR = (R)rho, irho = (R)1 / rhoR;
+  const R rhoR = (R)rho, irho = quot((R)1, rhoR);
   const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
   R u[3];
   if (FORC == LBM_GUO) {
@@ -880,7 +953,7 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
     u[1] = (R)j[1] * irho;
     u[2] = (R)j[2] * irho;
   }
-  const R ch = (R)P.gamma[s] / (R)Gam;   // chi_s / rbar_s
+  const R ch = quot((R)P.gamma[s], (R)Gam);   // chi_s / rbar_s
   R fs[3];
   if (FORC == LBM_GUO) {                // F_s = chi_s F + rbar_s g
     fs[0] = ch * rs * FR[0] + rs * g0;
