@@ -106,7 +106,7 @@ void adj_layout(const lbm_ctx* c, int nsteps, int K, AdjLayout* L) {
   L->rb = off;
   off = align_up(off + nc * cells * 8);
   L->partials = off;
-  off = align_up(off + (size_t)nblocks_for((int)cells) * (LBM_MAX_NC * LBM_MAX_NC + LBM_MAX_NC) * 8);
+  off = align_up(off + (size_t)adj_blocks((int)cells) * (LBM_MAX_NC * LBM_MAX_NC + LBM_MAX_NC) * 8);
   L->acc = off;
   off = align_up(off + 32 * 8);
   L->ckpt = off;
@@ -161,7 +161,7 @@ void zero(double* p, int n, hipStream_t st) {
 // acc[0..K) = sum over blocks of the per-block accumulator
 void finish_partials(const lbm_ctx* c, const double* partials, int K, double* acc) {
   zero(acc, 32, c->stream);
-  hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(kBlock), 0, c->stream, partials, nblocks_for((int)c->cells), K,
+  hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(kBlock), 0, c->stream, partials, adj_blocks((int)c->cells), K,
                      acc);
 }
 
@@ -198,7 +198,7 @@ extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* h_next, double*
   char* w = (char*)ws;
   double* acc = (double*)(w + L.acc);
   double* partials = (double*)(w + L.partials);
-  const int nb = nblocks_for((int)c->cells);
+  const int nb = adj_blocks((int)c->cells);
   zero(partials, nb * L.ktheta, c->stream);
   enqueue_reverse(c, c->pops[c->cur], h_next, h_out, scratch_of(w, L), partials);
   finish_partials(c, partials, L.ktheta, acc);
@@ -233,7 +233,7 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, int nsteps, int checkpoint_every, 
   double* partials = (double*)(w + L.partials);
   double* acc = (double*)(w + L.acc);
   const AdjScratch S = scratch_of(w, L);
-  const int nb = nblocks_for((int)c->cells);
+  const int nb = adj_blocks((int)c->cells);
 
   // forward with checkpoints
   for (int s = 0; s < L.nseg && st == LBM_OK; ++s) {

@@ -59,6 +59,13 @@
 
 namespace lbmk {
 
+// Workgroup size of the one-thread-per-cell adjoint kernels: the boxes an adjoint
+// runs on are small (C5: 16,384 cells), and 64-thread workgroups spread them over
+// four times as many CUs as the step's 256-thread ones (one wavefront per CU on a
+// 128^2 box), which shortens these latency-bound kernels.
+constexpr int kAdjBlock = 64;
+inline int adj_blocks(int cells) { return (int)xcd_grid((unsigned)((cells + kAdjBlock - 1) / kAdjBlock)); }
+
 // per-cell scratch of the adjoint passes (float64, [k][cells])
 struct AdjScratch {
   double* Fbar;    // [D]
@@ -199,13 +206,13 @@ __device__ __forceinline__ void gather_h(const double* hs, size_t N, const Coord
 }
 
 template <int LAT, int NC, int ST, int COLL, int FORC>
-__global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, const double* __restrict__ psi,
+__global__ __launch_bounds__(kAdjBlock) void ka_cell(KParams P, Pops<ST> state, const double* __restrict__ psi,
                                                  const double* __restrict__ h, AdjScratch S) {
   using V = VS<LAT>;
   using R = typename Pops<ST>::R;
   constexpr int Q = V::Q, D = V::D;
   unsigned cell;
-  if (!launch_cell(P, 0, P.nplanes, &cell)) return;
+  if (!launch_cell<kAdjBlock>(P, 0, P.nplanes, &cell)) return;
   const Coord c = make_coord(cell, P);
   const size_t N = (size_t)P.cells;
   const unsigned bits = P.bb ? P.bb[cell] : 0u;
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void ka_cell(KParams P, Pops<ST> state, con
 // Parameter partials per block, added to a running per-block accumulator:
 // [dL/daa_ij (NC*NC, ordered pairs), dL/db_i (NC)].
 template <int LAT, int NC, int COLL>
-__global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __restrict__ psi,
+__global__ __launch_bounds__(kAdjBlock) void kb_cell(KParams P, const double* __restrict__ psi,
                                                  const double* __restrict__ h, AdjScratch S,
                                                  double* __restrict__ hout, double* __restrict__ partials) {
   using V = VS<LAT>;
@@ -341,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __res
 #pragma unroll
   for (int k = 0; k < K; ++k) vals[k] = 0.0;
   unsigned cell;
-  const bool inside = launch_cell(P, 0, P.nplanes, &cell);
+  const bool inside = launch_cell<kAdjBlock>(P, 0, P.nplanes, &cell);
   const unsigned bits = (inside && P.bb) ? P.bb[cell] : 0u;
   if (inside && (bits >> kSolidBit)) {   // solid cell: no adjoint, no EOS or parameter term
     const size_t N = (size_t)P.cells;
@@ -414,20 +421,20 @@ __global__ __launch_bounds__(kBlock) void kb_cell(KParams P, const double* __res
       }
     }
   }
-  block_partials_add<K>(vals, partials);
+  block_partials_add<K, kAdjBlock>(vals, partials);
 }
 
 // Masked molar sums N_s = sum_{mask} rbar_s / M_s of the post-streaming state
 // (per-block partials, [NC]).
 template <int LAT, int NC, int ST>
-__global__ __launch_bounds__(kBlock) void k_masked_moles(KParams P, Pops<ST> state,
+__global__ __launch_bounds__(kAdjBlock) void k_masked_moles(KParams P, Pops<ST> state,
                                                         const unsigned char* __restrict__ mask,
                                                         double* __restrict__ partials) {
   double vals[NC];
 #pragma unroll
   for (int s = 0; s < NC; ++s) vals[s] = 0.0;
   unsigned cell;
-  if (launch_cell(P, 0, P.nplanes, &cell) && mask[cell]) {
+  if (launch_cell<kAdjBlock>(P, 0, P.nplanes, &cell) && mask[cell]) {
     const unsigned bits = P.bb ? P.bb[cell] : 0u;
     if (!(bits >> kSolidBit)) {         // solid cells hold no fluid
       const Coord c = make_coord(cell, P);
@@ -436,17 +443,17 @@ __global__ __launch_bounds__(kBlock) void k_masked_moles(KParams P, Pops<ST> sta
       for (int s = 0; s < NC; ++s) vals[s] = pull_moments<LAT, ST>(P, state, s, c, jr, cell, bits) * P.invM[s];
     }
   }
-  block_partials<NC>(vals, partials);
+  block_partials<NC, kAdjBlock>(vals, partials);
 }
 
 // Adjoint seed of L(N): dL/df_sa(y) = mask(y) * coef_s for every direction.
 template <int LAT, int NC>
-__global__ __launch_bounds__(kBlock) void k_adj_seed(KParams P, const unsigned char* __restrict__ mask,
+__global__ __launch_bounds__(kAdjBlock) void k_adj_seed(KParams P, const unsigned char* __restrict__ mask,
                                                     double c0, double c1, double c2, double c3,
                                                     double* __restrict__ h) {
   using V = VS<LAT>;
   unsigned cell;
-  if (!launch_cell(P, 0, P.nplanes, &cell)) return;
+  if (!launch_cell<kAdjBlock>(P, 0, P.nplanes, &cell)) return;
   const double coef[4] = {c0, c1, c2, c3};
   const size_t N = (size_t)P.cells;
   const bool in = mask[cell] != 0;

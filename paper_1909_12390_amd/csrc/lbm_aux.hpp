@@ -7,46 +7,53 @@
 
 namespace lbmk {
 
-__device__ __forceinline__ double wave_sum(double v) {
+// Butterfly sums over the wavefront of K values at once (every lane ends with the
+// totals): each step exchanges all K values before adding, so the K exchanges of a
+// step are in flight together (one wait per step rather than one per value)
+template <int K>
+__device__ __forceinline__ void wave_sums(double* v) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  for (int off = 32; off > 0; off >>= 1) {
+    double t[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[k] = __shfl_xor(v[k], off, 64);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += t[k];
+  }
 }
 
-template <int K>
+template <int K, int B = kBlock>   // B: threads per workgroup
 __device__ __forceinline__ void block_partials(double* vals, double* partials) {
-  __shared__ double red[kBlock / 64][K];
+  __shared__ double red[B / 64][K];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  wave_sums<K>(vals);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double s = wave_sum(vals[k]);
-    if (lane == 0) red[wv][k] = s;
-  }
+  for (int k = 0; k < K; ++k)
+    if (lane == 0) red[wv][k] = vals[k];
   __syncthreads();
   if (threadIdx.x < K) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+    for (int w = 0; w < B / 64; ++w) s += red[w][threadIdx.x];
     partials[(size_t)blockIdx.x * K + threadIdx.x] = s;
   }
 }
 
 // as block_partials, but adds the block's sums to partials[block][k] (a running
 // per-block accumulator across launches on one stream; each block owns its row)
-template <int K>
+template <int K, int B = kBlock>
 __device__ __forceinline__ void block_partials_add(double* vals, double* partials) {
-  __shared__ double red[kBlock / 64][K];
+  __shared__ double red[B / 64][K];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  wave_sums<K>(vals);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double s = wave_sum(vals[k]);
-    if (lane == 0) red[wv][k] = s;
-  }
+  for (int k = 0; k < K; ++k)
+    if (lane == 0) red[wv][k] = vals[k];
   __syncthreads();
   if (threadIdx.x < K) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+    for (int w = 0; w < B / 64; ++w) s += red[w][threadIdx.x];
     partials[(size_t)blockIdx.x * K + threadIdx.x] += s;
   }
 }

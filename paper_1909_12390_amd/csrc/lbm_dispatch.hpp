@@ -53,8 +53,13 @@ inline Pops<LBM_F16_OFS> make_pops<LBM_F16_OFS>(const Bufs& b) {
 template <int LAT, int NC, int ST, int COLL, int FORC>
 struct OpsImpl {
   static void psi(const KParams& P, const Bufs& in, const StepScratch& sc, int plane0, int np, hipStream_t st) {
-    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(psi_blocks(P, np, VS<LAT>::D)), dim3(kBlock), 0, st, P,
-                       make_pops<ST>(in), sc.psi, plane0, np);
+    constexpr int D = VS<LAT>::D;
+    if (psi_small(P, np, D))
+      hipLaunchKernelGGL((k_psi<LAT, NC, ST, 64>), dim3(psi_blocks(P, np, D, 64)), dim3(64), 0, st, P,
+                         make_pops<ST>(in), sc.psi, plane0, np);
+    else
+      hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(psi_blocks(P, np, D)), dim3(kBlock), 0, st, P,
+                         make_pops<ST>(in), sc.psi, plane0, np);
   }
   static void collide(const KParams& P, const Bufs& in, const Bufs& out, const StepScratch& sc, int plane0,
                       int np, hipStream_t st) {
@@ -125,21 +130,21 @@ template <int LAT, int NC, int ST, int COLL, int FORC>
 struct AdjOpsImpl {
   static void a(const KParams& P, const Bufs& state, const double* psi, const double* h, const AdjScratch& S,
                 hipStream_t st) {
-    hipLaunchKernelGGL((ka_cell<LAT, NC, ST, COLL, FORC>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
+    hipLaunchKernelGGL((ka_cell<LAT, NC, ST, COLL, FORC>), dim3(adj_blocks(P.cells)), dim3(kAdjBlock), 0, st, P,
                        make_pops<ST>(state), psi, h, S);
   }
   static void b(const KParams& P, const double* psi, const double* h, const AdjScratch& S, double* hout,
                 double* partials, hipStream_t st) {
-    hipLaunchKernelGGL((kb_cell<LAT, NC, COLL>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P, psi, h, S, hout,
-                       partials);
+    hipLaunchKernelGGL((kb_cell<LAT, NC, COLL>), dim3(adj_blocks(P.cells)), dim3(kAdjBlock), 0, st, P, psi, h, S,
+                       hout, partials);
   }
   static void moles(const KParams& P, const Bufs& state, const unsigned char* mask, double* partials,
                     hipStream_t st) {
-    hipLaunchKernelGGL((k_masked_moles<LAT, NC, ST>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P,
+    hipLaunchKernelGGL((k_masked_moles<LAT, NC, ST>), dim3(adj_blocks(P.cells)), dim3(kAdjBlock), 0, st, P,
                        make_pops<ST>(state), mask, partials);
   }
   static void seed(const KParams& P, const unsigned char* mask, const double* coef, double* h, hipStream_t st) {
-    hipLaunchKernelGGL((k_adj_seed<LAT, NC>), dim3(nblocks_for(P.cells)), dim3(kBlock), 0, st, P, mask, coef[0],
+    hipLaunchKernelGGL((k_adj_seed<LAT, NC>), dim3(adj_blocks(P.cells)), dim3(kAdjBlock), 0, st, P, mask, coef[0],
                        coef[1], coef[2], coef[3], h);
   }
   static AdjOps ops() { return AdjOps{&a, &b, &moles, &seed}; }

@@ -338,8 +338,9 @@ inline unsigned xcd_grid(unsigned blocks) { return (blocks + kXcd - 1) / kXcd * 
 
 // Linear index of the k-th cell of a launch covering `nplanes` planes starting at
 // plane `plane0` (periodic in the plane index); false past the end.
+template <int B = kBlock>   // B: threads per workgroup of the launch
 __device__ __forceinline__ bool launch_cell(const KParams& P, int plane0, int nplanes, unsigned* cell) {
-  const unsigned lin = logical_block() * kBlock + threadIdx.x;
+  const unsigned lin = logical_block() * B + threadIdx.x;
   const unsigned pc = P.plane_cells;
   if (lin >= (unsigned)nplanes * pc) return false;
   const unsigned k = lin / pc;
@@ -738,15 +739,16 @@ __device__ __forceinline__ void pull_row_offset(const View& cv, const RowCoord& 
 
 // pass 1: densities -> EOS -> psi on planes [plane0, plane0 + nplanes)
 // Each wavefront covers 64 cells of one row (as in the collide pass): segment
-// logical_block() * (kBlock / 64) + wavefront; see psi_blocks for the grid.
-template <int LAT, int NC, int ST>
-__global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* __restrict__ psi, int plane0,
-                                               int nplanes) {
+// logical_block() * (B / 64) + wavefront, B the threads per workgroup (kBlock; 64
+// for small launches, see psi_small); see psi_blocks for the grid.
+template <int LAT, int NC, int ST, int B = kBlock>
+__global__ __launch_bounds__(B) void k_psi(KParams P, Pops<ST> in, double* __restrict__ psi, int plane0,
+                                          int nplanes) {
   using V = VS<LAT>;
   using R = typename Pops<ST>::R;
   constexpr int Q = V::Q;
   const unsigned lane = threadIdx.x & 63u;
-  const unsigned seg = logical_block() * (kBlock / 64) + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const unsigned seg = logical_block() * (B / 64) + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   RowCoord c;
   bool in_row = false;
   if (!row_segment<V::D>(P, seg, plane0, nplanes, lane, &c, &in_row)) return;   // uniform per wavefront
@@ -788,10 +790,18 @@ __global__ __launch_bounds__(kBlock) void k_psi(KParams P, Pops<ST> in, double* 
 }
 
 // workgroups of k_psi for planes [plane0, plane0 + np): kBlock / 64 row segments each
-inline unsigned psi_blocks(const KParams& P, int np, int D) {
-  const unsigned segs = (unsigned)np * (D == 3 ? (unsigned)P.ny : 1u) * (((unsigned)P.nx + 63u) / 64u);
-  return xcd_grid((segs + kBlock / 64 - 1) / (kBlock / 64));
+inline unsigned psi_segments(const KParams& P, int np, int D) {
+  return (unsigned)np * (D == 3 ? (unsigned)P.ny : 1u) * (((unsigned)P.nx + 63u) / 64u);
 }
+inline unsigned psi_blocks(const KParams& P, int np, int D, int B = kBlock) {
+  const unsigned per = (unsigned)B / 64u;
+  return xcd_grid((psi_segments(P, np, D) + per - 1) / per);
+}
+// small launches (fewer than 4 segments per CU of the 256) take one-wavefront
+// workgroups, so that their segments spread over all CUs rather than a quarter
+// of them
+constexpr unsigned kSmallPsiSegments = 4u * 256u;
+inline bool psi_small(const KParams& P, int np, int D) { return psi_segments(P, np, D) < kSmallPsiSegments; }
 
 // pass 2: a block is 64 cells x NC wavefronts, wavefront s working on component s.
 // psi at a cell and at the stencil directions a with (a - 1) mod NC == s of the
