@@ -517,7 +517,8 @@ __device__ __forceinline__ void cell_forces(const KParams& P, const double* rb, 
 // MRT : f* = f + src - M^-1 S M (f - feq + h src), h = 1/2 (Guo), 0 (EDM), which
 //       with d = f - feq + h src is the same as
 //       f* = feq + (1 - h) src + M^-1 (I - S) M d
-//       (M^-1 = M^T diag(1/|M_k|^2) for the orthogonal basis).  Rows relaxed at
+//       (M^-1 = M^T diag(1/|M_k|^2) for the orthogonal basis; with EDM, h = 0 and
+//       feq + src = feq(u + du), which is evaluated as such).  Rows relaxed at
 //       rate 1 drop out of the second form, so only the rows with rate != 1 are
 //       transformed (a uniform branch per row; the density row always drops out
 //       because sum_a d_a = 0).
@@ -579,25 +580,62 @@ __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R r
     const R h = (FORC == LBM_GUO) ? (R)0.5 : (R)0;
     const R g1 = (R)1 - h;
     R d0, acc0 = 0;
-    R S[NP], D[NP], accE[NP], accO[NP];
-    {
-      R Ev, Od, sE, sO;
-      parts(std::integral_constant<int, 0>{}, Ev, Od, sE, sO);
-      d0 = f[0] - Ev + h * sE;
-      fo[0] = Ev + g1 * sE;
+    // XE, XO: even / odd parts of feq + (1 - h) src per pair (X0: the rest velocity)
+    R S[NP], D[NP], XE[NP], XO[NP], accE[NP], accO[NP], X0;
+    if constexpr (FORC == LBM_EDM) {
+      // h = 0, and feq(u) + [feq(u + du) - feq(u)] is feq(u + du): formed directly
+      // (fewer operations than the source, no difference taken)
+      const R vx = ux + Fx, vy = uy + Fy, vz = uz + Fz;
+      const R basev = (R)1 - (R)1.5 * (vx * vx + vy * vy + vz * vz);
+      auto eq2 = [&](auto A, R& Ev, R& Od, R& Xv, R& Yv) {   // feq(u) and feq(u + du), even / odd
+        constexpr int a = decltype(A)::value;
+        constexpr R cx = V::cx(a), cy = V::cy(a), cz = V::cz(a);
+        const R wr = (R)V::w(a) * rs;
+        const R eu = cx * ux + cy * uy + cz * uz;
+        const R ev = cx * vx + cy * vy + cz * vz;
+        Ev = wr * (base1 + (R)4.5 * eu * eu);
+        Od = (R)3 * wr * eu;
+        Xv = wr * (basev + (R)4.5 * ev * ev);
+        Yv = (R)3 * wr * ev;
+      };
+      {
+        R Ev, Od, Xv, Yv;
+        eq2(std::integral_constant<int, 0>{}, Ev, Od, Xv, Yv);
+        d0 = f[0] - Ev;
+        X0 = Xv;
+      }
+      static_for<0, NP>([&](auto Pp) {
+        constexpr int p = decltype(Pp)::value;
+        constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
+        R Ev, Od, Xv, Yv;
+        eq2(std::integral_constant<int, a>{}, Ev, Od, Xv, Yv);
+        S[p] = (f[a] + f[b]) - (R)2 * Ev;   // d_a + d_b
+        D[p] = (f[a] - f[b]) - (R)2 * Od;   // d_a - d_b
+        XE[p] = Xv;
+        XO[p] = Yv;
+        accE[p] = 0;
+        accO[p] = 0;
+      });
+    } else {
+      {
+        R Ev, Od, sE, sO;
+        parts(std::integral_constant<int, 0>{}, Ev, Od, sE, sO);
+        d0 = f[0] - Ev + h * sE;
+        X0 = Ev + g1 * sE;
+      }
+      static_for<0, NP>([&](auto Pp) {
+        constexpr int p = decltype(Pp)::value;
+        constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
+        R Ev, Od, sE, sO;
+        parts(std::integral_constant<int, a>{}, Ev, Od, sE, sO);
+        S[p] = (f[a] + f[b]) - (R)2 * Ev + (R)2 * h * sE;   // d_a + d_b
+        D[p] = (f[a] - f[b]) - (R)2 * Od + (R)2 * h * sO;   // d_a - d_b
+        XE[p] = Ev + g1 * sE;                               // feq + (1 - h) src
+        XO[p] = Od + g1 * sO;
+        accE[p] = 0;
+        accO[p] = 0;
+      });
     }
-    static_for<0, NP>([&](auto Pp) {
-      constexpr int p = decltype(Pp)::value;
-      constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
-      R Ev, Od, sE, sO;
-      parts(std::integral_constant<int, a>{}, Ev, Od, sE, sO);
-      S[p] = (f[a] + f[b]) - (R)2 * Ev + (R)2 * h * sE;   // d_a + d_b
-      D[p] = (f[a] - f[b]) - (R)2 * Od + (R)2 * h * sO;   // d_a - d_b
-      fo[a] = (Ev + g1 * sE) + (Od + g1 * sO);            // feq + (1 - h) src
-      fo[b] = (Ev + g1 * sE) - (Od + g1 * sO);
-      accE[p] = 0;
-      accO[p] = 0;
-    });
     static_for<1, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
       const double ck = P.mrt_c[k];
@@ -632,12 +670,13 @@ __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R r
         });
       }
     });
-    fo[0] += acc0;
+    fo[0] = X0 + acc0;
     static_for<0, NP>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value;
       constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
-      fo[a] += accE[p] + accO[p];
-      fo[b] += accE[p] - accO[p];
+      const R e = XE[p] + accE[p], o = XO[p] + accO[p];
+      fo[a] = e + o;
+      fo[b] = e - o;
     });
   }
   sink(fo);
