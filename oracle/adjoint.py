@@ -172,10 +172,7 @@ def step(f, aa, b, base: thermo.Mixture, prm, lat: VelocitySet):
     g = np.zeros(D) if prm.accel is None else np.asarray(prm.accel, dtype=np.float64)
     F_s = torch.stack([torch.stack([gamma[s] * rho_s[s] / Gam * F[d] + rho_s[s] * float(g[d])
                                     for d in range(D)]) for s in range(N)])
-    if prm.forcing == "guo":
-        u = (j + 0.5 * F_s.sum(dim=0)) / rho
-    else:
-        u = j / rho
+    u = (j + 0.5 * F_s.sum(dim=0)) / rho        # barycentric velocity (both forcings)
     if prm.collision == "mrt":
         Mx = mrt_basis(lat)
         Minv = np.linalg.inv(Mx)
@@ -184,7 +181,12 @@ def step(f, aa, b, base: thermo.Mixture, prm, lat: VelocitySet):
         guo_mat = torch.as_tensor(Minv @ (np.eye(lat.Q) - 0.5 * S) @ Mx, dtype=DT)
     posts = []
     for s in range(N):
-        feq = equilibrium(rho_s[s], u, lat)
+        if prm.forcing == "edm":       # jump du_s, equilibrium velocity U - du_s / 2 (oracle.lbm)
+            du = torch.stack([gamma[s] * F[d] / Gam + float(g[d]) for d in range(D)])
+            ueq = u - 0.5 * du
+        else:
+            ueq = u
+        feq = equilibrium(rho_s[s], ueq, lat)
         if prm.collision == "bgk":
             post = f[s] - (f[s] - feq) / prm.tau
         else:
@@ -196,8 +198,7 @@ def step(f, aa, b, base: thermo.Mixture, prm, lat: VelocitySet):
             else:
                 post = post + torch.tensordot(guo_mat, shape, dims=([1], [0]))
         else:
-            du = torch.stack([gamma[s] * F[d] / Gam + float(g[d]) for d in range(D)])
-            post = post + equilibrium(rho_s[s], u + du, lat) - feq
+            post = post + equilibrium(rho_s[s], ueq + du, lat) - feq
         posts.append(post)
     fstar = torch.stack(posts)
     if solid is None:

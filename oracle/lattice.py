@@ -13,7 +13,9 @@ here directly from their defining polynomials in the velocity components.
 Pins: tests/test_oracle_lbm.py checks the isotropy moments of each set
 (sum w = 1, sum w e = 0, sum w e e = c_s^2 I, sum w e e e = 0, fourth moment
 c_s^4 (d_ij d_kl + d_ik d_jl + d_il d_jk)) and the mutual orthogonality of the
-MRT rows.
+MRT rows; tests/test_oracle_mrt.py checks what the rates attached to the rows
+deliver: the shear viscosity of every shear row and the inter-diffusion
+coefficient of the component momentum rows.
 """
 from __future__ import annotations
 
@@ -88,10 +90,3 @@ def mrt_basis(lat: VelocitySet) -> np.ndarray:
                 (ex * ex - ey * ey) * ez]                     # m_z
     return np.array(rows)
 
-
-def mrt_rate_kinds(lat: VelocitySet):
-    """Name of the relaxation rate that applies to each moment row of mrt_basis."""
-    if lat.D == 2:
-        return ["rho", "e", "eps", "j", "q", "j", "q", "nu", "nu"]
-    return ["rho", "e", "eps", "j", "q", "j", "q", "j", "q",
-            "nu", "pi", "nu", "pi", "nu", "nu", "nu", "m", "m", "m"]

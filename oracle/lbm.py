@@ -17,9 +17,20 @@ Step order (Sec. 3.4, the list of implementation steps, and Eq. (LBE) of Sec. 2.
   7. streaming, the left-hand side of Eq. (LBE).
 
 Readings (the paper is silent on these):
-  * u with Guo forcing is the shared barycentric velocity (sum_sigma j_sigma + F/2)/rho;
-    with the exact-difference method u = j/rho and the per-component velocity jump
-    is du_sigma = F_sigma / rbar_sigma = gamma_sigma F / Gamma.
+  * u with Guo forcing is the shared barycentric velocity U = (sum_sigma j_sigma + F/2)/rho.
+  * The exact-difference method (EDM) is not in the paper; for several components it
+    is read so that the per-component balance of Sec. 3.1, Eq. (hydrostatic1), holds
+    as it does with Guo's term: component sigma receives the velocity jump
+    du_sigma = F_sigma / rbar_sigma = gamma_sigma F / Gamma and relaxes towards
+    feq(rbar_sigma, U - du_sigma / 2), followed by the jump
+    feq(rbar_sigma, U + du_sigma / 2) - feq(rbar_sigma, U - du_sigma / 2).  Its
+    component momentum then changes by -(j_sigma - rbar_sigma U)/tau + (1 - 1/(2 tau)) F_sigma
+    (the same first moment as Guo's scheme), so that a resting component whose
+    momentum is -F_sigma/2 gains exactly F_sigma per step; with one component it is
+    the standard EDM (relaxation towards feq(j/rho)).  Relaxing every component
+    towards the shared feq(j/rho) instead would add a drift between the components
+    that depends on their mass fractions and on tau, i.e. a different split than
+    Eq. (distributionforce).
   * psi uses the densities of the populations being collided (no time lag).
   * A negative argument of the square root in Eq. (psicorrected), or b_m rho~ >= 1,
     is an error (DomainError); nothing is clamped.
@@ -245,16 +256,14 @@ def step(f: np.ndarray, mix: thermo.Mixture, prm: StepParams, lat: VelocitySet, 
     F_tot = F_s.sum(axis=0)
     rho_div = rho if solid is None else np.where(solid, 1.0, rho)   # solid cells: u = 0
     # 6. velocity, equilibrium, collision with forcing
-    if prm.forcing == "guo":
-        u = (j + 0.5 * F_tot) / rho_div
-    elif prm.forcing == "edm":
-        u = j / rho_div
+    if prm.forcing not in ("guo", "edm"):
+        raise ValueError(prm.forcing)
+    u = (j + 0.5 * F_tot) / rho_div        # barycentric velocity U (both forcings)
+    if prm.forcing == "edm":
         gamma = np.asarray(prm.gamma, dtype=np.float64)
         Gam = np.sum(gamma.reshape(gshape) * rho_s, axis=0)
         if solid is not None:
             Gam = np.where(solid, 1.0, Gam)
-    else:
-        raise ValueError(prm.forcing)
     if prm.collision == "mrt":
         Mx = mrt_basis(lat)
         Minv = np.linalg.inv(Mx)
@@ -263,7 +272,14 @@ def step(f: np.ndarray, mix: thermo.Mixture, prm: StepParams, lat: VelocitySet, 
         guo_mat = Minv @ (np.eye(lat.Q) - 0.5 * S) @ Mx
     fstar = np.empty_like(f)
     for s in range(N):
-        feq = equilibrium(rho_s[s], u, lat)
+        if prm.forcing == "edm":
+            du = np.empty_like(u)           # velocity jump of component s
+            for d in range(D):
+                du[d] = prm.gamma[s] * F[d] / Gam + g[d]
+            ueq = u - 0.5 * du              # its equilibrium velocity
+        else:
+            ueq = u
+        feq = equilibrium(rho_s[s], ueq, lat)
         if prm.collision == "bgk":
             post = f[s] - (f[s] - feq) / prm.tau
         elif prm.collision == "mrt":
@@ -277,10 +293,7 @@ def step(f: np.ndarray, mix: thermo.Mixture, prm: StepParams, lat: VelocitySet, 
             else:
                 post = post + _apply_matrix(guo_mat, shape)
         else:
-            du = np.empty_like(u)
-            for d in range(D):
-                du[d] = prm.gamma[s] * F[d] / Gam + g[d]
-            post = post + equilibrium(rho_s[s], u + du, lat) - feq
+            post = post + equilibrium(rho_s[s], ueq + du, lat) - feq
         fstar[s] = post
     if solid is not None:
         fstar[:, :, solid] = 0.0

@@ -318,23 +318,64 @@ def test_domain_errors():
     del lat
 
 
+def _default_rates(lat, tau):
+    from paper_1909_12390_amd.inputs import default_mrt_rates
+    return default_mrt_rates(lat.name, tau)
+
+
 @pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
 @pytest.mark.parametrize("forcing", ["guo", "edm"])
-def test_per_component_momentum_change_follows_split(lat, forcing):
-    # Collision moves component momentum j_s toward rbar_s u at rate 1/tau and adds
-    # chi_s F (EDM) or (1 - 1/(2 tau)) chi_s F (Guo), chi_s = gamma_s rbar_s / Gamma.
+def test_per_component_momentum_change_follows_split(lat, collision, forcing):
+    # Sec. 3.1: component s receives chi_s F, chi_s = gamma_s rbar_s / Gamma
+    # (Eq. (distributionforce)).  Both forcings change the component momentum by
+    #   j_s* - j_s = -(j_s - rbar_s U)/tau + (1 - 1/(2 tau)) chi_s F,
+    # U = (j + F/2)/rho the barycentric velocity (Guo's first moment; for EDM the
+    # relaxation towards U - du_s/2 plus the jump du_s give the same).  With MRT the
+    # benchmark rates relax the component momentum rows at 1/tau, so the same holds.
     mix = _binary_mix()
     f = _drop_state(lat, _shape(lat), mix)
     tau = 0.8
     gamma = np.array([0.45, 1.0])
-    prm = _params(lat, "bgk", forcing, tau=tau, gamma=gamma)
+    rates = _default_rates(lat, tau) if collision == "mrt" else None
+    prm = _params(lat, collision, forcing, tau=tau, gamma=gamma, rates=rates)
     _, fld = lbm.step(f, mix, prm, lat, return_fields=True)
     e = lat.e.astype(float)
     Gam = gamma[0] * fld["rho_s"][0] + gamma[1] * fld["rho_s"][1]
+    rho = fld["rho_s"].sum(axis=0)
+    U = (np.einsum("sa...,ai->i...", f, e) + 0.5 * fld["F"]) / rho
     for s in range(2):
         j_s = np.einsum("a...,ai->i...", f[s], e)
         j_post = np.einsum("a...,ai->i...", fld["fstar"][s], e)
         Fs = gamma[s] * fld["rho_s"][s] / Gam * fld["F"]
-        pref = 1.0 if forcing == "edm" else 1.0 - 0.5 / tau
-        want = j_s - (j_s - fld["rho_s"][s] * fld["u"]) / tau + pref * Fs
+        want = j_s - (j_s - fld["rho_s"][s] * U) / tau + (1.0 - 0.5 / tau) * Fs
         assert np.max(np.abs(j_post - want)) < 1e-14
+
+
+@pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+@pytest.mark.parametrize("forcing", ["guo", "edm"])
+def test_resting_components_receive_their_force_share(lat, collision, forcing):
+    # Eq. (hydrostatic1) of Sec. 3.1: at rest every component balances its partial
+    # pressure gradient with its own share chi_s F of the force, which requires the
+    # step to deliver exactly chi_s F to component s.  A resting component
+    # (velocity (j_s + F_s/2)/rbar_s = 0, i.e. j_s = -F_s/2) must leave the
+    # collision with j_s* = +F_s/2, whatever tau, the collision rates or the
+    # composition.
+    mix = _binary_mix()
+    f0 = _drop_state(lat, _shape(lat), mix)
+    tau = 0.7
+    gamma = np.array([0.3, 1.0])
+    rates = _default_rates(lat, tau) if collision == "mrt" else None
+    prm = _params(lat, collision, forcing, tau=tau, gamma=gamma, rates=rates)
+    rho_s = lbm.densities(f0)
+    _, fld = lbm.step(f0, mix, prm, lat, return_fields=True)      # F depends on the densities only
+    Fs = fld["F_s"]
+    f = np.stack([lbm.equilibrium(rho_s[s], -0.5 * Fs[s] / rho_s[s], lat) for s in range(2)])
+    _, fld = lbm.step(f, mix, prm, lat, return_fields=True)
+    scale = np.max(np.abs(Fs))
+    assert np.max(np.abs(fld["F_s"] - Fs)) < 1e-13 * scale
+    e = lat.e.astype(float)
+    for s in range(2):
+        j_post = np.einsum("a...,ai->i...", fld["fstar"][s], e)
+        assert np.max(np.abs(j_post - 0.5 * Fs[s])) < 1e-12 * scale
