@@ -26,7 +26,9 @@
  *       vector field [D][cells]; populations [nc][Q][cells].
  *   - "dev" pointers are device (HBM) pointers owned by the caller; "host" pointers
  *     are host memory, borrowed for the duration of the call.
- *   - Boundaries are periodic in every direction (Sec. 4 uses periodic domains).
+ *   - Boundaries are periodic in every direction (Sec. 4 uses periodic domains),
+ *     except where lbm_set_solid or lbm_box.solid installs solid walls (halfway
+ *     bounce-back, see lbm_set_solid).
  */
 #ifndef LBM_H
 #define LBM_H
@@ -55,7 +57,8 @@ enum { LBM_GUO = 0, LBM_EDM = 1 };
 /* Population storage.  F64: plain float64 populations, float64 collision.
  * F32_OFS / F16_OFS: per cell and component a float32 base b and Q offsets
  * r_a = f_a / b0 - w_a stored in float32 / float16 (round to nearest even), with
- * b0 = sum_a |f_a| and b rescaled after rounding so that the decoded populations
+ * b0 = sum_a |f_a| carrying the sign of the cell's mass of the component, and b
+ * rescaled after rounding so that the decoded populations
  * sum to the component's mass; decode f_a = b (w_a + r_a).  Collision in float32;
  * EOS, psi, the force stencil and the masses stay float64. */
 enum { LBM_F64 = 0, LBM_F32_OFS = 1, LBM_F16_OFS = 2 };
@@ -160,9 +163,13 @@ lbm_status lbm_step(lbm_ctx* ctx, int nsteps);
  *   u_dev       [D][cells]   physical velocity (sum_sigma j_sigma + F_total/2)/rho
  *   p_dev       [cells]      p_EOS (= hydrodynamic pressure of Eq. hydropressure)
  *   psi_dev     [cells]      pseudo-potential, Eq. psicorrected
- *   totals_host [nc + 2*D]   mass of each component, total momentum sum(j + F_total/2),
+ *   totals_host [2*nc + 2*D] mass of each component, total momentum sum(j + F_total/2),
  *                            net interaction force sum(F), as float64 sums in a fixed
- *                            (deterministic) order.
+ *                            (deterministic) order, then per component the number of
+ *                            fluid cells where its cell-volume density is negative (the
+ *                            scheme does not keep partial densities positive and nothing
+ *                            is clamped: a trace component can cross zero in a phase
+ *                            where it is nearly absent; the counts report it).
  * Synchronises the stream when totals_host != NULL; returns LBM_ERR_DOMAIN if the
  * device error flag is set. */
 lbm_status lbm_moments(lbm_ctx* ctx, double* rho_bar_dev, double* u_dev, double* p_dev,

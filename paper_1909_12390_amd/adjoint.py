@@ -80,20 +80,44 @@ def run(theta, spec: AdjointSpec):
     return r["loss"], r["x_liq"], pack_gradient(r["d_k"], r["d_a"], r["d_b"])
 
 
+def loss_only(theta, spec: AdjointSpec):
+    """(loss, x_liq) for theta from the forward steps alone (no reverse pass): the
+    liquid mole fractions over the mask from the final cell-volume densities."""
+    ctx = lbm.LbmContext(mixture_with(theta, spec.mix), spec.lattice, spec.shape, spec.T, spec.tau, spec.beta,
+                         spec.gamma, spec.rho0, collision=spec.collision, forcing=spec.forcing, storage=spec.storage,
+                         mrt_s=spec.mrt_s)
+    try:
+        ctx.step(spec.nsteps)
+        ctx.check()
+        rho = ctx.moments(totals=False)["rho_s"].cpu().numpy()
+    finally:
+        ctx.close()
+    M = np.asarray(spec.mix["M"], dtype=np.float64)
+    mask = np.asarray(spec.mask, dtype=bool)
+    N = np.array([rho[i][mask].sum() / M[i] for i in range(rho.shape[0])])
+    x = N / N.sum()
+    return float(np.sum((x - np.asarray(spec.x_target, dtype=np.float64)) ** 2)), x
+
+
 def _function():
     import torch
 
     class LiquidCompositionLoss(torch.autograd.Function):
         @staticmethod
         def forward(ctx, theta, spec):
-            loss, _, grad = run(theta.detach().cpu().double().numpy(), spec)
-            ctx.save_for_backward(torch.as_tensor(grad, dtype=theta.dtype, device=theta.device))
+            th = theta.detach().cpu().double().numpy()
+            if ctx.needs_input_grad[0]:
+                loss, _, grad = run(th, spec)
+                # the gradient is kept in float64; backward casts only what it returns
+                ctx.save_for_backward(torch.as_tensor(grad, dtype=torch.float64, device=theta.device))
+            else:                      # no gradient wanted: the forward steps only
+                loss, _ = loss_only(th, spec)
             return torch.as_tensor(loss, dtype=theta.dtype, device=theta.device)
 
         @staticmethod
         def backward(ctx, grad_output):
             (g,) = ctx.saved_tensors
-            return grad_output * g, None
+            return (grad_output.to(torch.float64) * g).to(grad_output.dtype), None
 
     return LiquidCompositionLoss
 

@@ -241,7 +241,7 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
   c->prm = *prm;
   c->Q = prm->lattice == LBM_D2Q9 ? 9 : 19;
   c->D = prm->lattice == LBM_D2Q9 ? 2 : 3;
-  c->K = mix->nc + 2 * c->D;
+  c->K = 2 * mix->nc + 2 * c->D;
   c->cells = (size_t)prm->nx * prm->ny * prm->nz;
   c->stream = (hipStream_t)stream;
   char* base = (char*)ws;

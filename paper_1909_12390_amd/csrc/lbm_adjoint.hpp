@@ -4,11 +4,12 @@
 // derivative with respect to the EOS tables (a alpha)_ij (1 - k_ij) and b_i.
 //
 // Forward step at cell x (post-streaming populations f_sa(x), Sec. 3.4 order):
-//   rbar_s = sum_a f_sa, rho = sum_s rbar_s, j = sum_sa e_a f_sa, u = j / rho
+//   rbar_s = sum_a f_sa, rho = sum_s rbar_s, j = sum_sa e_a f_sa, U = (j + F/2) / rho
 //   p = p_EOS(rbar / M) (Eq. MCPengRobinson), X = 6 (p - rho/3) / G, psi = sqrt(X)
 //   F(x) = -G sum_a w_a e_a psi(x+e_a) (beta psi(x) + hb psi(x+e_a)),  hb = (1-beta)/2
-//   Gamma = sum_s gamma_s rbar_s, du_s = gamma_s F / Gamma, v_s = u + du_s + g
-//   f*_sa = (1-omega) f_sa + (omega-1) feq_a(rbar_s, u) + feq_a(rbar_s, v_s)
+//   Gamma = sum_s gamma_s rbar_s, X_s = gamma_s F / Gamma (the jump is du_s = X_s + g),
+//   w_s = U - X_s/2 (equilibrium velocity), v_s = w_s + du_s = U + X_s/2 + g
+//   f*_sa = (1-omega) f_sa + (omega-1) feq_a(rbar_s, w_s) + feq_a(rbar_s, v_s)
 //   f_sa(x + e_a, t+1) = f*_sa(x)
 // with feq_a(r, v) = w_a r (1 + 3 e.v + 9/2 (e.v)^2 - 3/2 v.v).
 //
@@ -18,10 +19,11 @@
 //   A2 = sum_a w_a e_a e_a hs_a give
 //     sum_a hs_a feq_a(r, v) = r Phi(v),  Phi(v) = A0 (1 - 3/2 v.v) + 3 A1.v + 9/2 v.A2.v
 //     d/dv = r gPhi(v),                   gPhi(v) = -3 A0 v + 3 A1 + 9 A2 v
-//   rbar^_s   = (omega-1) Phi_s(u) + Phi_s(v_s) + gamma_s Gamma^ - u^.u / rho + [EOS, psi terms]
-//   u^        = sum_s rbar_s ((omega-1) gPhi_s(u) + gPhi_s(v_s)),  j^ = u^ / rho
-//   du^_s     = rbar_s gPhi_s(v_s),  F^ = sum_s gamma_s du^_s / Gamma
-//   Gamma^    = -sum_s (gamma_s F / Gamma) . du^_s / Gamma
+//   rbar^_s   = (omega-1) Phi_s(w_s) + Phi_s(v_s) + gamma_s Gamma^ - U^.U / rho + [EOS, psi terms]
+//   U^        = sum_s rbar_s ((omega-1) gPhi_s(w_s) + gPhi_s(v_s)),  j^ = U^ / rho
+//   X^_s      = rbar_s (gPhi_s(v_s) - (omega-1) gPhi_s(w_s)) / 2
+//   F^        = sum_s gamma_s X^_s / Gamma + U^ / (2 rho)
+//   Gamma^    = -sum_s X_s . X^_s / Gamma
 //   psi^(y)   = -G beta sum_a w_a (e_a.F^(y)) psi(y+e_a)
 //               - G sum_a w_a (e_a.F^(y-e_a)) (beta psi(y-e_a) + 2 hb psi(y))
 //   X^ = psi^ / (2 psi), p^ = 6 X^ / G, rho^ += -2 X^ / G
@@ -44,7 +46,7 @@
 // K = M^-1 (I - S) M = sum_k (1 - s_k)/|M_k|^2 M_k M_k^T (BGK: K = (1 - omega) I).
 // With g = K hs the adjoint of f is g (instead of (1 - omega) hs), and every
 // equilibrium / source term above takes the moments of the vector that multiplies
-// it: EDM  feq(u): -g, feq(v): hs;   Guo  feq(u): hs - g, src: (hs + g)/2.
+// it: EDM  feq(w_s): -g, feq(v_s): hs;   Guo  feq(u): hs - g, src: (hs + g)/2.
 //
 // Walls (P.bb): the forward pulls with halfway bounce-back, so the adjoint of f*_a(x)
 // at a fluid cell is h_{opp(a)}(x) where x + e_a is solid (bit opp(a) of x's mask)
@@ -255,10 +257,10 @@ __global__ __launch_bounds__(kAdjBlock) void ka_cell(KParams P, Pops<ST> state, 
   double F[3];
   force_at<LAT>(P, psi[cell], [&](int a) { return psi[c.at(V::cx(a), V::cy(a), V::cz(a))]; }, F);
   const double* g = P.accel;
-  double u[3];
+  double u[3];   // Guo: (j + F_total/2) / rho;  EDM: U = (j + F/2) / rho
 #pragma unroll
   for (int d = 0; d < 3; ++d)
-    u[d] = (FORC == LBM_GUO) ? (j[d] + 0.5 * (F[d] + rho * g[d])) * irho : j[d] * irho;
+    u[d] = (FORC == LBM_GUO) ? (j[d] + 0.5 * (F[d] + rho * g[d])) * irho : (j[d] + 0.5 * F[d]) * irho;
   double ub[3] = {0.0, 0.0, 0.0}, Fb[3] = {0.0, 0.0, 0.0}, Gb = 0.0;
   double rbA[NC], FbF[NC];
 #pragma unroll
@@ -269,24 +271,25 @@ __global__ __launch_bounds__(kAdjBlock) void ka_cell(KParams P, Pops<ST> state, 
     apply_K<LAT, COLL>(P, hv, kv);
     const WMom A = wmoments<LAT>(hv), B = wmoments<LAT>(kv);
     if constexpr (FORC == LBM_EDM) {
-      double duF[3], v[3];
+      double Xs[3], w[3], v[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        duF[d] = P.gamma[s] * F[d] * iG;
-        v[d] = u[d] + duF[d] + g[d];
+        Xs[d] = P.gamma[s] * F[d] * iG;
+        w[d] = u[d] - 0.5 * Xs[d];
+        v[d] = u[d] + 0.5 * Xs[d] + g[d];
       }
-      double gAv[3], gBu[3];
+      double gAv[3], gBw[3];
       wgphi(A, v, gAv);
-      wgphi(B, u, gBu);
-      rbA[s] = wphi(A, v) - wphi(B, u);
-      double dub[3];
+      wgphi(B, w, gBw);
+      rbA[s] = wphi(A, v) - wphi(B, w);
+      double Xb[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        ub[d] += rb[s] * (gAv[d] - gBu[d]);
-        dub[d] = rb[s] * gAv[d];
-        Fb[d] += P.gamma[s] * iG * dub[d];
+        ub[d] += rb[s] * (gAv[d] - gBw[d]);
+        Xb[d] = 0.5 * rb[s] * (gAv[d] + gBw[d]);
+        Fb[d] += P.gamma[s] * iG * Xb[d];
       }
-      Gb -= (duF[0] * dub[0] + duF[1] * dub[1] + duF[2] * dub[2]) * iG;
+      Gb -= (Xs[0] * Xb[0] + Xs[1] * Xb[1] + Xs[2] * Xb[2]) * iG;
       FbF[s] = 0.0;
     } else {
       const WMom E = wcomb(A, 1.0, B, -1.0);     // multiplies feq(u)
@@ -317,9 +320,9 @@ __global__ __launch_bounds__(kAdjBlock) void ka_cell(KParams P, Pops<ST> state, 
 #pragma unroll
     for (int s = 0; s < NC; ++s) cs += FbF[s];
     Gb = -cs * iG;                                 // d/d Gamma through chi_s = gamma_s rbar_s / Gamma
-#pragma unroll
-    for (int d = 0; d < 3; ++d) Fb[d] += 0.5 * ub[d] * irho;
   }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) Fb[d] += 0.5 * ub[d] * irho;   // through the F/2 of the velocity
   double uub = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) uub += ub[d] * ((FORC == LBM_GUO) ? (u[d] - 0.5 * g[d]) : u[d]);

@@ -59,14 +59,17 @@ __device__ __forceinline__ void block_partials_add(double* vals, double* partial
 }
 
 // rbar_s, u = (j + F_total/2)/rho, p_EOS and psi of every cell; per-block partial
-// sums of [mass_s (nc), momentum (D), force (D)] in a fixed order.
+// sums of [mass_s (nc), momentum (D), force (D), number of fluid cells with
+// rbar_s < 0 (nc)] in a fixed order.  The scheme does not keep the partial
+// densities positive (nothing is clamped); the counts report where a trace
+// component has crossed zero.
 template <int LAT, int NC, int ST>
 __global__ __launch_bounds__(kBlock) void k_moments(KParams P, Pops<ST> in, const double* __restrict__ psi,
                                                    double* rho_out, double* u_out, double* p_out, double* psi_out,
                                                    double* partials) {
   using V = VS<LAT>;
   using R = typename Pops<ST>::R;
-  constexpr int D = V::D, K = NC + 2 * D;
+  constexpr int D = V::D, K = 2 * NC + 2 * D;
   double vals[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) vals[k] = 0.0;
@@ -119,6 +122,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams P, Pops<ST> in, cons
       vals[NC + d] = j[d] + 0.5 * Ft[d];
       vals[NC + D + d] = F[d];
     }
+#pragma unroll
+    for (int s = 0; s < NC; ++s) vals[NC + 2 * D + s] = rb[s] < 0.0 ? 1.0 : 0.0;
   }
   block_partials<K>(vals, partials);
 }

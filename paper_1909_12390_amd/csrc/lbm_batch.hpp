@@ -286,17 +286,17 @@ __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restr
       const R rhoR = (R)rho, irho = (R)1 / rhoR;
       const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
       R u[3];
+      const R rs = (R)mass;
+      const R ch = (R)B.gamma[s] / (R)Gam;
       if (FORC == LBM_GUO) {
         u[0] = ((R)j[0] + (R)0.5 * (FR[0] + rhoR * g0)) * irho;
         u[1] = ((R)j[1] + (R)0.5 * (FR[1] + rhoR * g1)) * irho;
         u[2] = ((R)j[2] + (R)0.5 * (FR[2] + rhoR * g2)) * irho;
-      } else {
-        u[0] = (R)j[0] * irho;
-        u[1] = (R)j[1] * irho;
-        u[2] = (R)j[2] * irho;
+      } else {   // component s relaxes towards U - du_s / 2 (as in k_collide)
+        u[0] = ((R)j[0] + (R)0.5 * FR[0]) * irho - (R)0.5 * (ch * FR[0]);
+        u[1] = ((R)j[1] + (R)0.5 * FR[1]) * irho - (R)0.5 * (ch * FR[1]);
+        u[2] = ((R)j[2] + (R)0.5 * FR[2]) * irho - (R)0.5 * (ch * FR[2]);
       }
-      const R rs = (R)mass;
-      const R ch = (R)B.gamma[s] / (R)Gam;
       R fs[3];
       if (FORC == LBM_GUO) {
         fs[0] = ch * rs * FR[0] + rs * g0;

@@ -8,7 +8,7 @@
 
 namespace lbmk {
 
-constexpr int kMaxRed = LBM_MAX_NC + 6;   // reduction width: nc masses + 2 * D
+constexpr int kMaxRed = 2 * LBM_MAX_NC + 6;   // reduction width: nc masses + 2 * D + nc negative-density counts
 
 }  // namespace lbmk
 

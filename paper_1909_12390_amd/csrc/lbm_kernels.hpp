@@ -190,11 +190,13 @@ struct OffsetPops {
     }
     // v: post-collision populations; mass: the cell's mass of this component
     // (sum of v, summed exactly in float64); w(a): weights.
-    // The offsets are taken against b0 = sum_a |v_a|, which is the mass wherever
-    // every population is positive; where a trace component's populations change
-    // sign (its density near or below zero) b0 stays of the size of the
-    // populations, so the offsets stay bounded and their rounding stays relative
-    // to the populations themselves.  After rounding the offsets the stored base
+    // The offsets are taken against b0 = +-sum_a |v_a| with the sign of the mass,
+    // which is the mass wherever every population has the sign of the mass (a
+    // positive cell, or a trace component whose density is negative throughout
+    // the cell): the offsets then hold only the small non-equilibrium part.  Where
+    // the populations change sign (a density near zero) |b0| stays of the size of
+    // the populations, so the offsets stay bounded and their rounding stays
+    // relative to the populations themselves.  After rounding the offsets the stored base
     // is set to mass / S with S = sum_a (w_a + r_a), each term formed in float32
     // exactly as the decoder forms it and the sum taken in float64 (exact); a cell
     // at rest is then a fixed point of encode/stream/decode, since the decoder's
@@ -202,7 +204,7 @@ struct OffsetPops {
     // rounding of mass / S absorbs.  Float32 sums instead bias the mass by a
     // fraction of an ulp per step, coherently over a bulk phase, which over
     // thousands of steps shifts phase compositions by ~1e-4.  Where the
-    // populations are far from all positive (S < 1/2) the base stays b0.
+    // populations are far from one sign (S < 1/2) the base stays b0.
     template <int Q, typename W>
     __device__ __forceinline__ void put_all(unsigned idx, const float* v, double mass, W w) const {
       put_all_row<Q>(idx, 0u, v, mass, w);
@@ -214,9 +216,10 @@ struct OffsetPops {
       float b0 = 0.0f;
 #pragma unroll
       for (int a = 0; a < Q; ++a) b0 += fabsf(v[a]);
+      if (mass < 0.0) b0 = -b0;
       // hardware reciprocal (1 ulp): its error is absorbed by the rescaled base
-      const float inv = (b0 > 0.0f) ? __builtin_amdgcn_rcpf(b0) : 0.0f;
-      const float wm = (b0 > 0.0f) ? 1.0f : 0.0f;
+      const float inv = (b0 != 0.0f) ? __builtin_amdgcn_rcpf(b0) : 0.0f;
+      const float wm = (b0 != 0.0f) ? 1.0f : 0.0f;
       double S = 0.0;
       const float one = opaque_one();
 #pragma unroll
@@ -468,51 +471,12 @@ __device__ __forceinline__ R feq(int a, R rho, R ux, R uy, R uz, R uu) {
   return rho * (R)V::w(a) * ((R)1 + (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * uu);
 }
 
-// Velocity shared by the components and the per-component forcing inputs:
-//   Guo: u = (j + F_total/2)/rho, Fs = chi_s F + rbar_s g;
-//   EDM: u = j/rho, du_s = gamma_s F / Gamma + g (= F_s / rbar_s);
-// chi_s = gamma_s rbar_s / Gamma, Gamma = sum gamma_i rbar_i (Eq. distributionforce).
-template <int NC, int FORC>
-__device__ __forceinline__ void cell_forces(const KParams& P, const double* rb, const double* j, const double* F,
-                                            double* u, double (*Fs)[3]) {
-  double rho = 0.0, Gam = 0.0;
-#pragma unroll
-  for (int s = 0; s < NC; ++s) {
-    rho += rb[s];
-    Gam += P.gamma[s] * rb[s];
-  }
-  if (!(Gam > 0.0)) flag_error(P);
-  const double g0 = P.accel[0], g1 = P.accel[1], g2 = P.accel[2];
-  if (FORC == LBM_GUO) {
-    u[0] = (j[0] + 0.5 * (F[0] + rho * g0)) / rho;
-    u[1] = (j[1] + 0.5 * (F[1] + rho * g1)) / rho;
-    u[2] = (j[2] + 0.5 * (F[2] + rho * g2)) / rho;
-  } else {
-    u[0] = j[0] / rho;
-    u[1] = j[1] / rho;
-    u[2] = j[2] / rho;
-  }
-  const double iG = 1.0 / Gam;
-#pragma unroll
-  for (int s = 0; s < NC; ++s) {
-    const double c = P.gamma[s] * iG;
-    if (FORC == LBM_GUO) {
-      Fs[s][0] = c * rb[s] * F[0] + rb[s] * g0;
-      Fs[s][1] = c * rb[s] * F[1] + rb[s] * g1;
-      Fs[s][2] = c * rb[s] * F[2] + rb[s] * g2;
-    } else {
-      Fs[s][0] = c * F[0] + g0;
-      Fs[s][1] = c * F[1] + g1;
-      Fs[s][2] = c * F[2] + g2;
-    }
-  }
-}
-
 // Collision with forcing of one component followed by the store of its Q
 // post-collision populations at `cell` (pull streaming: the next step reads
 // direction a of this cell from the neighbour at cell + e_a).
 //   f   : populations of component s at this cell (time t, post-streaming)
-//   rs  : rbar_s;  u: shared velocity;  Fs: F_s (Guo) or du_s (EDM)
+//   rs  : rbar_s;  u: equilibrium velocity (Guo: the shared (j + F_total/2)/rho;
+//         EDM: that velocity minus du_s/2, per component);  Fs: F_s (Guo) or du_s (EDM)
 // BGK : f* = f - omega (f - feq) + (1 - omega/2) S_guo        | + [feq(u + du) - feq(u)]
 // MRT : f* = f + src - M^-1 S M (f - feq + h src), h = 1/2 (Guo), 0 (EDM), which
 //       with d = f - feq + h src is the same as
@@ -992,17 +956,19 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   const R rhoR = (R)rho, irho = quot((R)1, rhoR);
   const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
   R u[3];
+  const R ch = quot((R)P.gamma[s], (R)Gam);   // chi_s / rbar_s
   if (FORC == LBM_GUO) {
     // u = (j + F_total/2) / rho, F_total = F + rho g
     u[0] = ((R)j[0] + (R)0.5 * (FR[0] + rhoR * g0)) * irho;
     u[1] = ((R)j[1] + (R)0.5 * (FR[1] + rhoR * g1)) * irho;
     u[2] = ((R)j[2] + (R)0.5 * (FR[2] + rhoR * g2)) * irho;
   } else {
-    u[0] = (R)j[0] * irho;
-    u[1] = (R)j[1] * irho;
-    u[2] = (R)j[2] * irho;
+    // equilibrium velocity of component s: U - du_s / 2 with U = (j + F_total/2) / rho
+    // and du_s = gamma_s F / Gamma + g, i.e. (j + F/2) / rho - (gamma_s / Gamma) F / 2
+    u[0] = ((R)j[0] + (R)0.5 * FR[0]) * irho - (R)0.5 * (ch * FR[0]);
+    u[1] = ((R)j[1] + (R)0.5 * FR[1]) * irho - (R)0.5 * (ch * FR[1]);
+    u[2] = ((R)j[2] + (R)0.5 * FR[2]) * irho - (R)0.5 * (ch * FR[2]);
   }
-  const R ch = quot((R)P.gamma[s], (R)Gam);   // chi_s / rbar_s
   R fs[3];
   if (FORC == LBM_GUO) {                // F_s = chi_s F + rbar_s g
     fs[0] = ch * rs * FR[0] + rs * g0;

@@ -401,14 +401,15 @@ class LbmContext:
             out["p"] = torch.empty(self.shape, dtype=torch.float64, device=dev)
             out["psi"] = torch.empty(self.shape, dtype=torch.float64, device=dev)
             ptrs = [c_void_p(out[k].data_ptr()) for k in ("rho_s", "u", "p", "psi")]
-        tot = np.zeros(self.nc + 2 * self.D) if totals else None
+        tot = np.zeros(2 * self.nc + 2 * self.D) if totals else None
         self._inputs_ready()
         _check(lib().lbm_moments(self._ctx, *ptrs, None if tot is None else _dptr(tot)))
         self._outputs_ready()
         if totals:
             out["mass"] = tot[: self.nc].copy()
             out["momentum"] = tot[self.nc: self.nc + self.D].copy()
-            out["force"] = tot[self.nc + self.D:].copy()
+            out["force"] = tot[self.nc + self.D: self.nc + 2 * self.D].copy()
+            out["negative_cells"] = tot[self.nc + 2 * self.D:].astype(np.int64)
         return out
 
     def get_populations(self):

@@ -97,7 +97,9 @@ def test_gradient_run_matches_oracle_gradient(collision, forcing):
     assert np.max(np.abs(gg - g)) <= 1e-9 * np.max(np.abs(g))
     # float32 storage: same gradient to the precision of the stored states
     r32, g32 = gpu_gradient(c, mask, x_tgt, nsteps, K=5, storage="f32", forcing=forcing, collision=collision)
-    assert np.max(np.abs(g32 - g)) <= 1e-4 * np.max(np.abs(g))
+    rel32 = float(np.max(np.abs(g32 - g)) / np.max(np.abs(g)))
+    print(f"  float32-storage gradient vs oracle: max rel {rel32:.2e}", flush=True)
+    assert rel32 <= 1e-5
 
 
 def test_checkpoint_interval_does_not_change_gradient():
@@ -120,6 +122,13 @@ def test_autograd_function_returns_library_gradient():
     (g,) = torch.autograd.grad(3.0 * L, theta)
     _, gg = gpu_gradient(c, mask, x_tgt, nsteps, K=4)
     assert np.allclose(g.numpy(), 3.0 * gg, rtol=0, atol=0)
+    # without a gradient request only the forward steps run; same loss
+    L0 = padj.liquid_composition_loss(theta.detach(), spec)
+    assert abs(float(L0) - float(L)) <= 1e-12 * abs(float(L))
+    # a float32 theta receives the float64 gradient cast once
+    th32 = torch.tensor(padj.theta_of(c["mix"]), dtype=torch.float32, requires_grad=True)
+    (g32,) = torch.autograd.grad(padj.liquid_composition_loss(th32, spec), th32)
+    assert g32.dtype == torch.float32 and torch.isfinite(g32).all()
 
 
 def host_loss(ctx, mask, M, x_tgt):
@@ -162,7 +171,7 @@ def test_full_case_gradient_matches_central_differences():
     L32, _, g32 = padj.run(theta, spec32)
     rel = float(np.max(np.abs(g32 - g)) / np.max(np.abs(g)))
     print(f"  float32-storage gradient vs float64: max rel {rel:.3e}; loss {L32:.6e} vs {L:.6e}", flush=True)
-    assert rel < 1e-2
+    assert rel < 1e-5
 
 
 def porous(shape, seed, frac=0.15):
