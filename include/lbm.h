@@ -175,6 +175,20 @@ lbm_status lbm_step(lbm_ctx* ctx, int nsteps);
 lbm_status lbm_moments(lbm_ctx* ctx, double* rho_bar_dev, double* u_dev, double* p_dev,
                        double* psi_dev, double* totals_host);
 
+/* lbm_moments for callers that cannot allocate device memory or use a workspace
+ * beyond the context's (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same outputs, bitwise, from the same kernels, but the
+ * per-block partial sums and the totals live in a static device array of the library
+ * (1 MiB per GPU, held until the process ends) instead of the context's workspace.
+ * Allocates nothing.  Boxes whose partial sums exceed the array (more than
+ * floor((1 MiB - 256) / (8 (2 nc + 2 D))) * 256 cells rounded to the launch grid:
+ * about 2.4 M cells for D3Q19 with nc = 4) are rejected with LBM_ERR_ARG.  Every call
+ * on a GPU uses that GPU's one array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  Synchronises the stream
+ * when totals_host != NULL, like lbm_moments. */
+lbm_status lbm_moments_noalloc(lbm_ctx* ctx, double* rho_bar_dev, double* u_dev, double* p_dev,
+                               double* psi_dev, double* totals_host);
+
 /* Export / import the populations of the current state as float64 [nc][Q][cells]
  * (dev), post-streaming (the f of Eq. LBE at time t), velocity order:
  *   D2Q9 : (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)

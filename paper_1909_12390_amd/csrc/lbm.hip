@@ -18,6 +18,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "lbm.h"
@@ -27,6 +28,23 @@
 
 namespace {
 thread_local char g_err[512] = "";
+}
+
+// Scratch of lbm_moments_noalloc: the per-block partial sums of the conservation
+// totals and the finished totals, in a file-scope device array instead of the
+// context's workspace.  Every GPU the library runs on holds its own copy until the
+// process ends.  Host code never uses the array's name as an address: lbm_init
+// looks up its device address once per device (hipGetSymbolAddress, with that
+// device current) and lbm_moments_noalloc uses only that address.
+constexpr size_t kNoallocScratchBytes = size_t(1) << 20;
+constexpr size_t kNoallocTotalsBytes = 256;   // totals (<= kMaxRed doubles) at the end of the array
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+static_assert(lbmk::kMaxRed * sizeof(double) <= kNoallocTotalsBytes, "totals do not fit the scratch's tail");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device, null until looked up
 }
 
 lbm_status lbm_fail(lbm_status code, const char* fmt, ...) {
@@ -223,11 +241,32 @@ extern "C" lbm_status lbm_workspace_bytes(const lbm_mixture* mix, const lbm_para
   return LBM_OK;
 }
 
+namespace {
+// The device address of `scratch` on `dev` (the current device), looked up once per
+// device; later calls return the kept address.
+lbm_status noalloc_scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return lbm_fail(LBM_ERR_ARG, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return LBM_OK;
+  void* p = nullptr;
+  lbm_status st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  if (st != LBM_OK) return st;
+  if (!p) return lbm_fail(LBM_ERR_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+  g_scratch_ptr[dev] = p;
+  return LBM_OK;
+}
+}  // namespace
+
 extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, void* ws, size_t ws_bytes,
                                const double* rho0, const double* u0, void* stream, lbm_ctx** out) {
   if (!out) return lbm_fail(LBM_ERR_ARG, "out is NULL");
   *out = nullptr;
   lbm_status st = validate(mix, prm);
+  if (st != LBM_OK) return st;
+  int dev = -1;
+  st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (st != LBM_OK) return st;
+  st = noalloc_scratch_address(dev);
   if (st != LBM_OK) return st;
   if (!ws || ((uintptr_t)ws % kAlign) != 0) return lbm_fail(LBM_ERR_ARG, "workspace must be 256-byte aligned");
   if (!rho0) return lbm_fail(LBM_ERR_ARG, "rho_bar0 is NULL");
@@ -255,6 +294,7 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
   c->totals = (double*)(base + L.totals);
   c->err = (int*)(base + L.err);
   c->cur = 0;
+  c->device = dev;
 
   KParams& kp = c->kp;
   std::memset(&kp, 0, sizeof(kp));
@@ -444,6 +484,41 @@ extern "C" lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p,
     st = hip_check(hipGetLastError(), "finish launch");
     if (st != LBM_OK) return st;
     st = hip_check(hipMemcpyAsync(totals, c->totals, sizeof(double) * c->K, hipMemcpyDeviceToHost, c->stream),
+                   "hipMemcpyAsync(totals)");
+    if (st != LBM_OK) return st;
+    return lbm_check(c);
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_moments_noalloc(lbm_ctx* c, double* rho, double* u, double* p, double* psi,
+                                          double* totals) {
+  if (!c) return lbm_fail(LBM_ERR_ARG, "ctx is NULL");
+  const size_t nb = (size_t)nblocks_for((int)c->cells);
+  const size_t need = nb * (size_t)c->K * sizeof(double);
+  if (need > kNoallocScratchBytes - kNoallocTotalsBytes)
+    return lbm_fail(LBM_ERR_ARG,
+                    "box too large for lbm_moments_noalloc: its partial sums need %zu bytes, the static "
+                    "scratch holds %zu (use lbm_moments)",
+                    need, kNoallocScratchBytes - kNoallocTotalsBytes);
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = g_scratch_ptr[c->device];   // set by lbm_init on this device
+  }
+  if (!base) return lbm_fail(LBM_ERR_HIP, "no scratch address for device %d", c->device);
+  double* partials = (double*)base;
+  double* tot = (double*)((char*)base + kNoallocScratchBytes - kNoallocTotalsBytes);
+  // k_moments writes every block's K partials and k_finish every total: nothing in
+  // the scratch needs clearing (it keeps the last call's values)
+  c->ops.moments(c->kp, c->pops[c->cur], c->sc, rho, u, p, psi, partials, c->stream);
+  lbm_status st = hip_check(hipGetLastError(), "moments launch");
+  if (st != LBM_OK) return st;
+  if (totals) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, c->stream, (const double*)partials, (int)nb, c->K, tot);
+    st = hip_check(hipGetLastError(), "finish launch");
+    if (st != LBM_OK) return st;
+    st = hip_check(hipMemcpyAsync(totals, tot, sizeof(double) * c->K, hipMemcpyDeviceToHost, c->stream),
                    "hipMemcpyAsync(totals)");
     if (st != LBM_OK) return st;
     return lbm_check(c);

@@ -29,6 +29,7 @@ struct lbm_ctx {
   double* totals;
   int* err;
   int cur;
+  int device;             // HIP device current at lbm_init (the workspace's device)
   // OVERLAP schedule: second stream and one event per slab (+ the step boundary)
   hipStream_t aux;
   hipEvent_t* ev;

@@ -32,7 +32,8 @@ Q_OF = {"D2Q9": 9, "D3Q19": 19}
 D_OF = {"D2Q9": 2, "D3Q19": 3}
 
 # every function declared in include/lbm.h
-EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_moments", "lbm_get_populations",
+EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_moments", "lbm_moments_noalloc",
+            "lbm_get_populations",
             "lbm_set_populations", "lbm_check", "lbm_clear_error", "lbm_destroy", "lbm_last_error",
             "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure",
             "lbm_batch_layout", "lbm_batch_init", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_check",
@@ -100,6 +101,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_step.argtypes = [c_void_p, c_int]
         L.lbm_step_timed.argtypes = [c_void_p, c_int, dp]
         L.lbm_moments.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, dp]
+        L.lbm_moments_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, dp]
         L.lbm_get_populations.argtypes = [c_void_p, c_void_p]
         L.lbm_set_populations.argtypes = [c_void_p, c_void_p]
         L.lbm_check.argtypes = [c_void_p]
@@ -390,7 +392,9 @@ class LbmContext:
             raise ValueError(f"gamma must have {self.nc} entries")
         _check(lib().lbm_set_gamma(self._ctx, _dptr(g)))
 
-    def moments(self, fields=True, totals=True):
+    def moments(self, fields=True, totals=True, noalloc=False):
+        """Fields and conservation totals of the current state (lbm_moments, or
+        lbm_moments_noalloc, whose partial sums use the library's static scratch)."""
         torch = self.torch
         dev = self.workspace.device
         out = {}
@@ -403,7 +407,8 @@ class LbmContext:
             ptrs = [c_void_p(out[k].data_ptr()) for k in ("rho_s", "u", "p", "psi")]
         tot = np.zeros(2 * self.nc + 2 * self.D) if totals else None
         self._inputs_ready()
-        _check(lib().lbm_moments(self._ctx, *ptrs, None if tot is None else _dptr(tot)))
+        fn = lib().lbm_moments_noalloc if noalloc else lib().lbm_moments
+        _check(fn(self._ctx, *ptrs, None if tot is None else _dptr(tot)))
         self._outputs_ready()
         if totals:
             out["mass"] = tot[: self.nc].copy()
