@@ -78,8 +78,9 @@ def measured_profile(kernel_key: str):
 
 
 def phase_mole_fractions(rho_s, M, geometry, shape):
-    """Bulk liquid/vapor mole fractions with fixed masks: drop liquid = r <= R0/2,
-    vapor = r >= min(L)/2 (box corners); x_i = sum_mask n_i / sum_mask n."""
+    """Bulk liquid/vapor states with fixed masks: drop liquid = r <= R0/2, vapor =
+    r >= min(L)/2 (box corners); mole fractions x_i = sum_mask n_i / sum_mask n and
+    the mask-mean molar densities (for the fugacities)."""
     import torch
     dev = rho_s.device
     grids = torch.meshgrid(*[torch.arange(n, dtype=torch.float64, device=dev) for n in shape], indexing="ij")
@@ -93,27 +94,54 @@ def phase_mole_fractions(rho_s, M, geometry, shape):
     for name, mask in (("liquid", liq), ("vapor", vap)):
         ni = torch.stack([n[i][mask].sum() for i in range(n.shape[0])])
         out[name] = (ni / ni.sum()).cpu().numpy()
+        out["n_" + name] = (ni / mask.sum()).cpu().numpy()
     return out
 
 
-def copy_bandwidth(torch, nbytes=2 << 30, reps=5):
-    """Device-to-device copy of nbytes (read nbytes, write nbytes): achievable HBM GB/s."""
+def fugacities(lbm, mix, T, n_l, n_v):
+    """Fugacities of the bulk liquid and vapour (Eq. fugacity at each state's own
+    p_EOS, no root choice) and the iso-fugacity residual of Eq. (error)."""
+    f = lbm.lbm_fugacity(mix, T, np.stack([n_l, n_v]))
+    fl, fv = np.asarray(f["fug"][0]), np.asarray(f["fug"][1])
+    return fl, fv, float(np.sum((fl / fv - 1.0) ** 2)), 0.5 * float(f["p"][0] + f["p"][1])
+
+
+def copy_bandwidth(torch, lbm, nbytes=2 << 30, reps=5, grids=(1024, 2048, 4096, 8192)):
+    """Measured HBM ceiling: the library's streaming copy (16-byte non-temporal loads
+    and stores, every byte read once and written once) of nbytes, timed with HIP
+    events over `reps` copies for each workgroup count; GB/s = 2 nbytes / time.
+    Returns the best rate, the per-grid rates and torch's own copy_ for reference."""
     n = nbytes // 4
     a = torch.empty(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
+    st = torch.cuda.current_stream()
+    per = {}
+    for g in grids:
+        lbm.stream_copy(b, a, nbytes, g, st)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(st)
+        for _ in range(reps):
+            lbm.stream_copy(b, a, nbytes, g, st)
+        t1.record(st)
+        t1.synchronize()
+        per[g] = 2.0 * nbytes / (t0.elapsed_time(t1) / reps * 1e-3) / 1e9
+    if not torch.equal(a, b):
+        raise RuntimeError("stream copy produced wrong data")
     b.copy_(a)
-    torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
+    t0.record(st)
     for _ in range(reps):
         b.copy_(a)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / reps
+    t1.record(st)
+    t1.synchronize()
+    torch_copy = 2.0 * nbytes / (t0.elapsed_time(t1) / reps * 1e-3) / 1e9
     del a, b
-    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+    best = max(per, key=per.get)
+    return {"GBps": per[best], "grid": best, "per_grid": per, "bytes_each_way": nbytes,
+            "torch_copy_GBps": torch_copy}
 
 
 def cpu_baseline_worker(side: int, steps: int):
@@ -167,10 +195,20 @@ def cpu_baseline(side: int, steps: int):
         sys.stderr.write(res.stderr)
         return None
     rec = json.loads(res.stdout.strip().splitlines()[-1])
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": rec["value"], "unit": "MLUPS×components", "cores": 1, "kind": "oracle",
             "sample": f"same four-component D3Q19 MRT+EDM mixture on a {side}^3 periodic box, "
                       f"{steps} steps after 1 warm-up step, float64 NumPy, one thread "
-                      f"({rec['seconds']:.1f} s)"}
+                      f"({rec['seconds']:.1f} s)",
+            "cpu_model": model, "host_cpu_count": os.cpu_count()}
 
 
 def batched_section(args, torch, lbm, inputs):
@@ -185,14 +223,15 @@ def batched_section(args, torch, lbm, inputs):
               "rho0": c.rho0, "R0": c.geometry["R0"]} for c in cfgs]
     cells = sum(c.cells for c in cfgs)
     comp_cells = sum(c.cells * c.nc for c in cfgs)
-    tune = autotune.tune_batch(boxes, "D2Q9", "bgk", "edm", "f32", steps=20)
+    tunes = {st: autotune.tune_batch(boxes, "D2Q9", "bgk", "edm", st, steps=20) for st in ("f32", "f16", "f64")}
     res = {"workload": f"{len(boxes)} independent D2Q9 boxes, sides from {{32,48,64,96,128}}, binary or ternary, "
                        f"BGK + exact-difference forcing, own T and composition per box",
-           "boxes": len(boxes), "cells": cells, "component_cells": comp_cells, "autotune": tune}
+           "boxes": len(boxes), "cells": cells, "component_cells": comp_cells, "autotune": tunes}
     graph_steps = 100
     for storage in ("f32", "f16", "f64"):
+        tune = tunes[storage]
         b = lbm.LbmBatch(boxes, "D2Q9", collision="bgk", forcing="edm", storage=storage, tile=tune["tile"],
-                         graph_steps=graph_steps)
+                         grid=tune["grid"], graph_steps=graph_steps)
         b.step(2 * graph_steps)
         b.check()
         start = torch.cuda.Event(enable_timing=True)
@@ -213,8 +252,8 @@ def batched_section(args, torch, lbm, inputs):
     if args.batch_precision_steps > 0:
         fr = {}
         for storage in ("f64", "f32", "f16"):
-            b = lbm.LbmBatch(boxes, "D2Q9", collision="bgk", forcing="edm", storage=storage, tile=tune["tile"],
-                             graph_steps=graph_steps)
+            b = lbm.LbmBatch(boxes, "D2Q9", collision="bgk", forcing="edm", storage=storage,
+                             tile=tunes[storage]["tile"], grid=tunes[storage]["grid"], graph_steps=graph_steps)
             b.step(args.batch_precision_steps)
             bad = b.box_errors()
             if bad.any():
@@ -223,6 +262,12 @@ def batched_section(args, torch, lbm, inputs):
             rho = b.fields()
             fr[storage] = [phase_mole_fractions(r, bx["mix"]["M"], {"R0": bx["R0"]}, bx["shape"])
                            for r, bx in zip(rho, boxes)]
+            for ph, bx in zip(fr[storage], boxes):
+                try:
+                    ph["fl"], ph["fv"], ph["residual"], _ = fugacities(lbm, bx["mix"], bx["T"], ph["n_liquid"],
+                                                                       ph["n_vapor"])
+                except lbm.LbmError:       # a mask state with p_EOS <= 0: no bulk phase there (e.g. the drop left)
+                    ph["fl"] = None
             b.close()
             del b, rho
             torch.cuda.empty_cache()
@@ -233,7 +278,64 @@ def batched_section(args, torch, lbm, inputs):
             res[f"{storage}_median_abs_molefrac_err_vs_f64"] = float(np.median(e))
             res[f"{storage}_boxes_over_1e-4"] = int((e > 1e-4).sum())
             res[f"{storage}_worst_box"] = int(np.argmax(e))
+            ok = [(a, c) for a, c in zip(fr[storage], fr["f64"]) if a["fl"] is not None and c["fl"] is not None]
+            ef = np.array([max(float(np.max(np.abs(a[k] / c[k] - 1.0))) for k in ("fl", "fv")) for a, c in ok])
+            res[f"{storage}_max_rel_fugacity_err_vs_f64"] = float(ef.max())
+            res[f"{storage}_median_rel_fugacity_err_vs_f64"] = float(np.median(ef))
+            res[f"{storage}_max_residual_eq_error"] = float(max(a["residual"] for a, _ in ok))
+        good = [a["residual"] for a in fr["f64"] if a["fl"] is not None]
+        res["boxes_without_two_bulk_phases"] = len(boxes) - len(good)
+        res["f64_max_residual_eq_error"] = float(max(good))
+        res["f64_median_residual_eq_error"] = float(np.median(good))
         res["precision_steps"] = args.batch_precision_steps
+    return res
+
+
+def slab_section(args, torch, lbm, inputs):
+    """The ternary 256^2 slab (MRT + exact-difference forcing) for its configured
+    steps in float64 and float32 storage: bulk phases on fixed masks (liquid
+    |y - y_c| <= H/8, vapour |y - y_c| >= 3H/8) against the flash at the LB's bulk
+    pressure and overall composition, the Eq. (error) residual of the bulk states,
+    and the float32 run's mole-fraction and fugacity errors against float64."""
+    th = lbm.LibThermo()
+    cfg = inputs.config_c2(th)
+    M = np.asarray(cfg.mix["M"], dtype=np.float64)
+    ny = cfg.shape[0]
+    y = np.arange(ny) - ny / 2.0
+    liq, vap = np.abs(y) <= ny / 8.0, np.abs(y) >= 3.0 * ny / 8.0
+    res = {"workload": f"ternary D2Q9 {ny}x{cfg.shape[1]} slab of half the height, MRT + exact-difference "
+                       f"forcing, beta {cfg.beta}, {cfg.steps} steps", "steps": cfg.steps, "beta": cfg.beta}
+    out = {}
+    for storage in ("f64", "f32"):
+        c = lbm.LbmContext(cfg.mix, cfg.lattice, cfg.shape, cfg.T, cfg.tau, cfg.beta, cfg.gamma, cfg.rho0,
+                           collision=cfg.collision, forcing=cfg.forcing, storage=storage, mrt_s=cfg.mrt_s,
+                           graph_steps=1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(cfg.steps)
+        c.check()
+        ms = (time.perf_counter() - t0) * 1e3
+        rho = c.moments(totals=False)["rho_s"].cpu().numpy()
+        c.close()
+        n = rho / M[:, None, None]
+        nl, nv = n[:, liq, :].mean(axis=(1, 2)), n[:, vap, :].mean(axis=(1, 2))
+        fl, fv, resid, p_lb = fugacities(lbm, cfg.mix, cfg.T, nl, nv)
+        nt = n.reshape(cfg.nc, -1).sum(axis=1)
+        out[storage] = {"x": nl / nl.sum(), "y": nv / nv.sum(), "fl": fl, "fv": fv, "residual": resid,
+                        "p": p_lb, "z": nt / nt.sum()}
+        res[storage] = {"ms_total": ms, "ms_per_step": ms / cfg.steps, "x": (nl / nl.sum()).tolist(),
+                        "y": (nv / nv.sum()).tolist(), "residual_eq_error": resid, "p_lb": p_lb}
+    r = out["f64"]
+    fl = lbm.lbm_flash(cfg.mix, cfg.T, r["p"], r["z"])
+    res["flash_at_lb_pressure"] = {"x": list(fl.x), "y": list(fl.y)}
+    for storage in ("f64", "f32"):
+        o = out[storage]
+        res[storage]["max_rel_err_vs_flash"] = float(max(np.max(np.abs(o["x"] - np.asarray(fl.x)) / np.asarray(fl.x)),
+                                                         np.max(np.abs(o["y"] - np.asarray(fl.y)) / np.asarray(fl.y))))
+    f32 = out["f32"]
+    res["f32_max_abs_molefrac_err_vs_f64"] = float(max(np.max(np.abs(f32["x"] - r["x"])),
+                                                       np.max(np.abs(f32["y"] - r["y"]))))
+    res["f32_max_rel_fugacity_err_vs_f64"] = float(max(np.max(np.abs(f32[k] / r[k] - 1.0)) for k in ("fl", "fv")))
     return res
 
 
@@ -344,6 +446,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-slab", dest="slab", action="store_false", help="skip the ternary slab section")
+    ap.add_argument("--tune-single", action="store_true",
+                    help="also time every single-box schedule per storage mode (autotune.tune_single)")
     ap.add_argument("--batch-boxes", type=int, default=512, help="batched section: number of boxes (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--batch-precision-steps", type=int, default=10000)
@@ -400,13 +505,50 @@ def main():
         ctx.check()
         return wall, kms
 
-    # headline: the chosen storage mode
+    def plain(ctx, steps, warmup, diag_every):
+        """Time exactly `steps` plain lbm_step calls (conservation totals every
+        diag_every steps) between two HIP events on the context's stream, bracketed
+        by device synchronisation; returns (wall ms, event ms)."""
+        ctx.step(warmup)
+        ctx.check()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(ctx.stream)
+        done = 0
+        while done < steps:
+            n = min(diag_every, steps - done)
+            ctx.step(n)
+            done += n
+            if done % diag_every == 0:
+                ctx.moments(fields=False, totals=True)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        ctx.check()
+        return wall, e0.elapsed_time(e1)
+
+    def measure(ctx, steps, warmup, diag_every):
+        """Plain-step wall time of `steps` steps, then the per-kernel split from a
+        second pass of the same length: (wall ms, [psi ms, collide ms])."""
+        w, _ = plain(ctx, steps, warmup, diag_every)
+        _, k = timed(ctx, steps, 0, diag_every)
+        return w, k
+
+    # the measured copy ceiling first (it also brings the device out of idle)
+    copy = None if args.no_copy else copy_bandwidth(torch, lbm)
+
+    # headline: the chosen storage mode, plain steps between two events
     ctx = make(args.storage)
     t_start_mass = ctx.moments(fields=False)["mass"]
-    wall_ms, kms = timed(ctx, args.steps, args.warmup, args.diag_every)
+    wall_ms, event_ms = plain(ctx, args.steps, args.warmup, args.diag_every)
     mass_drift = float(np.max(np.abs(ctx.moments(fields=False)["mass"] / t_start_mass - 1)))
     ms_per_step = wall_ms / args.steps
     value = cells * nc * args.steps / (wall_ms * 1e-3) / 1e6
+    # per-kernel split from a separate pass of the same length with HIP events around
+    # every launch on the context's stream
+    split_wall, kms = timed(ctx, args.steps, 0, args.diag_every)
     # dominant kernel: the collide pass (it carries all but the psi write of b_alg)
     kname = "k_collide"
     avg_ms = kms[1] / args.steps                      # collide time per step (all slabs)
@@ -435,19 +577,23 @@ def main():
                      "kernel": kname, "kernel_ms_per_step": avg_ms,
                      "kernel_alg_bytes_per_cell": b_alg_collide(nc, Q, args.storage),
                      "cells_per_step": cells, "traffic_bytes_per_step": traffic,
-                     "pipe_busy": prof.get("pipe_busy")},
+                     "pipe_busy": prof.get("pipe_busy"),
+                     "frac_of_measured_copy": None if copy is None else achieved / copy["GBps"]},
+        "event_ms_per_step": event_ms / args.steps,
         "step_alg_GBps": b_alg(nc, Q, args.storage) * cells / (ms_per_step * 1e-3) / 1e9,
         "step_alg_bytes_per_cell": b_alg(nc, Q, args.storage),
-        "kernel_ms_per_step": {"psi": kms[0] / args.steps, "collide": kms[1] / args.steps},
+        "kernel_ms_per_step": {"psi": kms[0] / args.steps, "collide": kms[1] / args.steps,
+                               "split_pass_wall_ms_per_step": split_wall / args.steps},
         "mass_drift_rel": mass_drift,
     }
+    if copy is not None:
+        out["copy_GBps"] = copy["GBps"]
+        out["copy"] = copy
 
     def progress(what):
         print(f"bench: {what} done", file=sys.stderr, flush=True)
 
     progress("headline")
-    if not args.no_copy:
-        out["copy_GBps_2GiB"] = copy_bandwidth(torch)
 
     modes = [m for m in args.modes.split(",") if m]
     res = {}
@@ -455,7 +601,7 @@ def main():
         for m in modes:
             for sched in ("two_pass", "blocked", "overlap"):
                 c = make(m, sched)
-                w, k = timed(c, args.steps, args.warmup, args.diag_every)
+                w, k = measure(c, args.steps, args.warmup, args.diag_every)
                 res[f"{m}/{sched}"] = {
                     "ms_per_step": w / args.steps, "mlups_x_comp": cells * nc * args.steps / (w * 1e-3) / 1e6,
                     "kernel_ms": [x / args.steps for x in k],
@@ -469,6 +615,13 @@ def main():
         out["modes"] = res
         progress("modes")
 
+    if args.tune_single:
+        from paper_1909_12390_amd import autotune
+        out["single_box_autotune"] = {
+            m: autotune.tune_single(lambda sched, slab, m=m: make(m, sched, slab), steps=args.steps)
+            for m in [x for x in args.modes.split(",") if x]}
+        progress("single-box autotune")
+
     if args.precision_steps > 0:
         prec = {"steps": args.precision_steps}
         fr = {}
@@ -478,19 +631,29 @@ def main():
             mo = c.moments(fields=True, totals=False)
             c.check()
             fr[m] = phase_mole_fractions(mo["rho_s"], cfg.mix["M"], cfg.geometry, cfg.shape)
+            fr[m]["fl"], fr[m]["fv"], fr[m]["residual"], _ = fugacities(lbm, cfg.mix, cfg.T, fr[m]["n_liquid"],
+                                                                        fr[m]["n_vapor"])
             del c, mo
             torch.cuda.empty_cache()
         for m in ("f32", "f16"):
             prec[f"{m}_max_abs_molefrac_err_vs_f64"] = float(max(
                 np.max(np.abs(fr[m][ph] - fr["f64"][ph])) for ph in ("liquid", "vapor")))
+            prec[f"{m}_max_rel_fugacity_err_vs_f64"] = float(max(
+                np.max(np.abs(fr[m][k] / fr["f64"][k] - 1.0)) for k in ("fl", "fv")))
+            prec[f"{m}_residual_eq_error"] = fr[m]["residual"]
+        prec["f64_residual_eq_error"] = fr["f64"]["residual"]
         prec["f64_liquid_x"] = fr["f64"]["liquid"].tolist()
         prec["f64_vapor_y"] = fr["f64"]["vapor"].tolist()
         out["precision"] = prec
         progress("precision")
 
     if args.walls_steps > 0:
-        out["walls"] = walls_section(args, torch, lbm, inputs, cfg, make, timed, res)
+        out["walls"] = walls_section(args, torch, lbm, inputs, cfg, make, measure, res)
         progress("walls")
+
+    if args.slab:
+        out["slab"] = slab_section(args, torch, lbm, inputs)
+        progress("ternary slab")
 
     if args.batch_boxes > 0:
         out["batched"] = batched_section(args, torch, lbm, inputs)

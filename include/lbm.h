@@ -242,6 +242,13 @@ void lbm_destroy(lbm_ctx* ctx);
 /* Thread-local text of the last error (never NULL). */
 const char* lbm_last_error(void);
 
+/* Streaming copy of `bytes` (a multiple of 16; dst and src dev, 16-byte aligned,
+ * not overlapping) with 16-byte non-temporal loads and stores on `stream`, `grid`
+ * workgroups of 256 threads (0 = 2048).  Not part of the model: it measures the
+ * HBM bandwidth a kernel that reads and writes every byte once reaches, the
+ * ceiling the step's kernels are compared with.  Asynchronous. */
+lbm_status lbm_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, int grid, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Thermodynamics (host, float64)
  * ------------------------------------------------------------------------- */

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpaper_lbm.so")
-SOURCES = ["lbm.hip", "lbm_d2q9.hip", "lbm_d3q19.hip", "lbm_batch.hip", "lbm_batch_d2q9.hip", "lbm_batch_d3q19.hip", "lbm_adjoint.hip", "thermo.cpp"]
+SOURCES = ["lbm.hip", "lbm_d2q9.hip", "lbm_d3q19.hip", "lbm_batch.hip", "lbm_batch_d2q9.hip", "lbm_batch_d3q19.hip", "lbm_adjoint.hip", "lbm_copy.hip", "thermo.cpp"]
 ARCH = "gfx950"
 
 

@@ -33,7 +33,7 @@ D_OF = {"D2Q9": 2, "D3Q19": 3}
 
 # every function declared in include/lbm.h
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_moments", "lbm_moments_noalloc",
-            "lbm_get_populations",
+            "lbm_get_populations", "lbm_stream_copy",
             "lbm_set_populations", "lbm_check", "lbm_clear_error", "lbm_destroy", "lbm_last_error",
             "lbm_critical", "lbm_fugacity", "lbm_flash", "lbm_bubble_pressure", "lbm_dew_pressure",
             "lbm_batch_layout", "lbm_batch_init", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_check",
@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_step_timed.argtypes = [c_void_p, c_int, dp]
         L.lbm_moments.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, dp]
         L.lbm_moments_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, dp]
+        L.lbm_stream_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_int, c_void_p]
         L.lbm_get_populations.argtypes = [c_void_p, c_void_p]
         L.lbm_set_populations.argtypes = [c_void_p, c_void_p]
         L.lbm_check.argtypes = [c_void_p]
@@ -235,6 +236,15 @@ def lbm_dew_pressure(mix: dict, T: float, z) -> float:
     out = np.zeros(1)
     _check(lib().lbm_dew_pressure(ctypes.byref(m), float(T), _dptr(zz), _dptr(out)))
     return float(out[0])
+
+
+def stream_copy(dst, src, nbytes: int, grid: int = 0, stream=None):
+    """lbm_stream_copy between two device tensors (the measured bandwidth ceiling);
+    enqueued on `stream` (a torch stream; None = the current one)."""
+    import torch
+    st = torch.cuda.current_stream() if stream is None else stream
+    _check(lib().lbm_stream_copy(c_void_p(dst.data_ptr()), c_void_p(src.data_ptr()), int(nbytes), int(grid),
+                                 c_void_p(st.cuda_stream)))
 
 
 class LibThermo:
