@@ -135,8 +135,12 @@ lbm_status validate(const lbm_mixture* mix, const lbm_params* prm) {
   if (prm->lattice == LBM_D2Q9 && prm->nz != 1) return lbm_fail(LBM_ERR_ARG, "D2Q9 needs nz == 1");
   const double cells = (double)prm->nx * prm->ny * prm->nz;
   const double Qd = prm->lattice == LBM_D2Q9 ? 9.0 : 19.0;
-  if (cells * 8.0 * Qd >= 4294967295.0)   // one component's planes are addressed with 32-bit offsets
-    return lbm_fail(LBM_ERR_ARG, "box too large: one component's population planes must stay below 4 GiB");
+  // population planes are addressed with 32-bit byte offsets: one component's planes
+  // (float64), all components' interleaved planes (offset formats)
+  const double sb = prm->storage == LBM_F64 ? 8.0 : (prm->storage == LBM_F32_OFS ? 4.0 : 2.0);
+  const double span = prm->storage == LBM_F64 ? cells * 8.0 * Qd : cells * sb * Qd * mix->nc;
+  if (span >= 4294967295.0)
+    return lbm_fail(LBM_ERR_ARG, "box too large: the population planes addressed together must stay below 4 GiB");
   if (!(prm->tau > 0.5)) return lbm_fail(LBM_ERR_ARG, "tau must exceed 0.5");
   if (!(prm->G < 0.0)) return lbm_fail(LBM_ERR_ARG, "G must be negative");
   if (!(prm->T > 0.0)) return lbm_fail(LBM_ERR_ARG, "T must be positive");
@@ -287,6 +291,7 @@ extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, vo
   for (int k = 0; k < 2; ++k) {
     c->pops[k].p0 = base + L.pop0[k];
     c->pops[k].p1 = prm->storage == LBM_F64 ? nullptr : base + L.pop1[k];
+    c->pops[k].nc = mix->nc;
   }
   c->psi = (double*)(base + L.psi);
   c->sc.psi = c->psi;

@@ -120,6 +120,7 @@ Bufs slot_at(const lbm_ctx* c, char* p, const StateShape& s) {
   Bufs b;
   b.p0 = p;
   b.p1 = c->prm.storage == LBM_F64 ? nullptr : p + align_up(s.p0_bytes);
+  b.nc = c->mix.nc;
   return b;
 }
 

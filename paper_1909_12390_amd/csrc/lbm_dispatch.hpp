@@ -8,6 +8,7 @@ namespace lbmk {
 struct Bufs {
   void* p0;   // F64: f;  offset formats: base
   void* p1;   // offset formats: r
+  int nc;     // components (the interleaved offset layout's stride)
 };
 
 // scratch field of one step: psi
@@ -40,6 +41,7 @@ inline Pops<LBM_F32_OFS> make_pops<LBM_F32_OFS>(const Bufs& b) {
   Pops<LBM_F32_OFS> p;
   p.base = (float*)b.p0;
   p.r = (float*)b.p1;
+  p.nc = b.nc;
   return p;
 }
 template <>
@@ -47,33 +49,46 @@ inline Pops<LBM_F16_OFS> make_pops<LBM_F16_OFS>(const Bufs& b) {
   Pops<LBM_F16_OFS> p;
   p.base = (float*)b.p0;
   p.r = (__half*)b.p1;
+  p.nc = b.nc;
   return p;
 }
 
 template <int LAT, int NC, int ST, int COLL, int FORC>
 struct OpsImpl {
-  static void psi(const KParams& P, const Bufs& in, const StepScratch& sc, int plane0, int np, hipStream_t st) {
+  // pass 1 over planes [plane0, plane0 + np): k_psi (float64 storage) or k_psi_ilv
+  // (interleaved offsets); one-wavefront workgroups on small launches
+  template <int B>
+  static void psi_launch(const KParams& P, const Bufs& in, double* psi, int plane0, int np, hipStream_t st) {
     constexpr int D = VS<LAT>::D;
-    if (psi_small(P, np, D))
-      hipLaunchKernelGGL((k_psi<LAT, NC, ST, 64>), dim3(psi_blocks(P, np, D, 64)), dim3(64), 0, st, P,
-                         make_pops<ST>(in), sc.psi, plane0, np);
+    if constexpr (ST == LBM_F64)
+      hipLaunchKernelGGL((k_psi<LAT, NC, ST, B>), dim3(psi_blocks(P, np, D, B)), dim3(B), 0, st, P,
+                         make_pops<ST>(in), psi, plane0, np);
     else
-      hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(psi_blocks(P, np, D)), dim3(kBlock), 0, st, P,
-                         make_pops<ST>(in), sc.psi, plane0, np);
+      hipLaunchKernelGGL((k_psi_ilv<LAT, NC, ST, B>), dim3(psi_blocks(P, np, D, B)), dim3(B), 0, st, P,
+                         make_pops<ST>(in), psi, plane0, np);
+  }
+  static void psi(const KParams& P, const Bufs& in, const StepScratch& sc, int plane0, int np, hipStream_t st) {
+    if (psi_small(P, np, VS<LAT>::D)) psi_launch<64>(P, in, sc.psi, plane0, np, st);
+    else psi_launch<kBlock>(P, in, sc.psi, plane0, np, st);
   }
   static void collide(const KParams& P, const Bufs& in, const Bufs& out, const StepScratch& sc, int plane0,
                       int np, hipStream_t st) {
-    // one workgroup per 64-cell segment of a row (y, z) of the slab
+    // 64-cell segments of the rows (y, z) of the slab
     const int rows = np * (VS<LAT>::D == 3 ? P.ny : 1);
-    const int nb = (int)xcd_grid(rows * ((P.nx + kCells - 1) / kCells));
-    hipLaunchKernelGGL((k_collide<LAT, NC, ST, COLL, FORC>), dim3(nb), dim3(kCells * NC), 0, st, P,
-                       make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
+    const int segs = rows * ((P.nx + kCells - 1) / kCells);
+    if constexpr (ST == LBM_F64) {   // one workgroup (nc wavefronts) per segment
+      hipLaunchKernelGGL((k_collide<LAT, NC, ST, COLL, FORC>), dim3(xcd_grid(segs)), dim3(kCells * NC), 0, st, P,
+                         make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
+    } else {                         // kIlvWaves segments per workgroup, one per wavefront
+      const int nb = (int)xcd_grid((segs + kIlvWaves - 1) / kIlvWaves);
+      hipLaunchKernelGGL((k_collide_ilv<LAT, NC, ST, COLL, FORC>), dim3(nb), dim3(64 * kIlvWaves), 0, st, P,
+                         make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
+    }
   }
   static void moments(const KParams& P, const Bufs& in, const StepScratch& sc, double* rho, double* u, double* p,
                       double* psi_out, double* partials, hipStream_t st) {
     const int nb = nblocks_for(P.cells);
-    hipLaunchKernelGGL((k_psi<LAT, NC, ST>), dim3(psi_blocks(P, P.nplanes, VS<LAT>::D)), dim3(kBlock), 0, st, P,
-                       make_pops<ST>(in), sc.psi, 0, P.nplanes);
+    psi_launch<kBlock>(P, in, sc.psi, 0, P.nplanes, st);
     hipLaunchKernelGGL((k_moments<LAT, NC, ST>), dim3(nb), dim3(kBlock), 0, st, P, make_pops<ST>(in),
                        (const double*)sc.psi, rho, u, p, psi_out, partials);
   }

@@ -151,27 +151,70 @@ struct Pops<LBM_F64> {
   }
 };
 
+// float32 -> storage type of an offset (float16: round to nearest even)
+template <typename H>
+__device__ __forceinline__ H enc_offset(float v) {
+  if constexpr (std::is_same<H, __half>::value) return __float2half_rn(v);
+  else return v;
+}
+
+// Offset encoding of the Q post-collision values v of one cell and component.
+// v: the values; mass: the cell's mass of this component (sum of v, summed exactly
+// in float64); w(a): weights.  Writes the offsets r[a] and returns the base to store.
+// The offsets are taken against b0 = +-sum_a |v_a| with the sign of the mass,
+// which is the mass wherever every population has the sign of the mass (a
+// positive cell, or a trace component whose density is negative throughout
+// the cell): the offsets then hold only the small non-equilibrium part.  Where
+// the populations change sign (a density near zero) |b0| stays of the size of
+// the populations, so the offsets stay bounded and their rounding stays
+// relative to the populations themselves.  After rounding the offsets the stored
+// base is mass / S with S = sum_a (w_a + r_a), each term formed in float32
+// exactly as the decoder forms it and the sum taken in float64 (exact); a cell
+// at rest is then a fixed point of encode/stream/decode, since the decoder's
+// product roundings total less than half an ulp of the base, which the
+// rounding of mass / S absorbs.  Float32 sums instead bias the mass by a
+// fraction of an ulp per step, coherently over a bulk phase, which over
+// thousands of steps shifts phase compositions by ~1e-4.  Where the
+// populations are far from one sign (S < 1/2) the base stays b0.
+// MIX: form w + r with the mixed-precision FMA (the same float32 value).
+template <int Q, typename H, bool MIX, typename W>
+__device__ __forceinline__ float encode_offsets(const float* v, double mass, W w, H* r) {
+  float b0 = 0.0f;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) b0 += fabsf(v[a]);
+  if (mass < 0.0) b0 = -b0;
+  // hardware reciprocal (1 ulp): its error is absorbed by the rescaled base
+  const float inv = (b0 != 0.0f) ? __builtin_amdgcn_rcpf(b0) : 0.0f;
+  const float wm = (b0 != 0.0f) ? 1.0f : 0.0f;
+  double S = 0.0;
+  const float one = opaque_one();
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    r[a] = enc_offset<H>(v[a] * inv - wm * w(a));
+    if constexpr (MIX) S += (double)w_plus(w(a), (float)r[a], one);
+    else S += (double)(w(a) + (float)r[a]);
+  }
+  return S >= 0.5 ? (float)(mass / S) : b0;
+}
+
+// Per-component offset planes (the batched boxes): layout [nc][Q][cells] for the
+// offsets, [nc][cells] for the float32 base; comp(s) views component s.
 template <typename H>
 struct OffsetPops {
   using R = float;
   float* base;
   H* r;
-  // LP: cache policy of the offset loads (kPopLoad; the batched kernels choose their own)
+  // LP: cache policy of the offset loads (the batched kernels choose their own)
   template <int LP>
   struct ViewT {
     rsrc_t rb, rr;
     unsigned plane;   // bytes per direction plane of r
-    const float* bp;  // the base array itself (wavefront-uniform scalar loads)
     using Elem = H;
     __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
       return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<LP>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
     }
     __device__ __forceinline__ float get_at(unsigned idx, unsigned pbytes, float w) const {
       return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<LP>(rr, idx * (unsigned)sizeof(H) + pbytes, 0u, H()));
-    }
-    __device__ __forceinline__ float get_row(int a, unsigned xo, unsigned ro, float w) const {
-      return bload(rb, xo * 4u, ro * 4u, 0.0f) *
-             (w + bload<LP>(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), H()));
     }
     // all Q directions, direction a from cell src(a): every load is issued before
     // the first decode, so the wavefront keeps 2Q loads in flight
@@ -189,65 +232,64 @@ struct OffsetPops {
       for (int a = 0; a < Q; ++a) out[a] = bq[a] * (w(a) + rq[a]);
     }
     // v: post-collision populations; mass: the cell's mass of this component
-    // (sum of v, summed exactly in float64); w(a): weights.
-    // The offsets are taken against b0 = +-sum_a |v_a| with the sign of the mass,
-    // which is the mass wherever every population has the sign of the mass (a
-    // positive cell, or a trace component whose density is negative throughout
-    // the cell): the offsets then hold only the small non-equilibrium part.  Where
-    // the populations change sign (a density near zero) |b0| stays of the size of
-    // the populations, so the offsets stay bounded and their rounding stays
-    // relative to the populations themselves.  After rounding the offsets the stored base
-    // is set to mass / S with S = sum_a (w_a + r_a), each term formed in float32
-    // exactly as the decoder forms it and the sum taken in float64 (exact); a cell
-    // at rest is then a fixed point of encode/stream/decode, since the decoder's
-    // product roundings total less than half an ulp of the base, which the
-    // rounding of mass / S absorbs.  Float32 sums instead bias the mass by a
-    // fraction of an ulp per step, coherently over a bulk phase, which over
-    // thousands of steps shifts phase compositions by ~1e-4.  Where the
-    // populations are far from one sign (S < 1/2) the base stays b0.
+    // (sum of v, summed exactly in float64); w(a): weights (encode_offsets)
     template <int Q, typename W>
     __device__ __forceinline__ void put_all(unsigned idx, const float* v, double mass, W w) const {
-      put_all_row<Q>(idx, 0u, v, mass, w);
-    }
-    // MIX: form w + r with the mixed-precision FMA (same values, fewer instructions;
-    // the single-box collide pass, where it does not cost registers)
-    template <int Q, bool MIX = false, typename W>
-    __device__ __forceinline__ void put_all_row(unsigned xo, unsigned ro, const float* v, double mass, W w) const {
-      float b0 = 0.0f;
+      H rq[Q];
+      const float b = encode_offsets<Q, H, false>(v, mass, w, rq);
 #pragma unroll
-      for (int a = 0; a < Q; ++a) b0 += fabsf(v[a]);
-      if (mass < 0.0) b0 = -b0;
-      // hardware reciprocal (1 ulp): its error is absorbed by the rescaled base
-      const float inv = (b0 != 0.0f) ? __builtin_amdgcn_rcpf(b0) : 0.0f;
-      const float wm = (b0 != 0.0f) ? 1.0f : 0.0f;
-      double S = 0.0;
-      const float one = opaque_one();
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        const H r = enc(v[a] * inv - wm * w(a));
-        bstore<kPopStore>(rr, xo * (unsigned)sizeof(H), (unsigned)a * plane + ro * (unsigned)sizeof(H), r);
-        if constexpr (MIX) S += (double)w_plus(w(a), (float)r, one);
-        else S += (double)(w(a) + (float)r);
-      }
-      bstore<kBaseStore>(rb, xo * 4u, ro * 4u, S >= 0.5 ? (float)(mass / S) : b0);
+      for (int a = 0; a < Q; ++a) bstore<kPopStore>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, rq[a]);
+      bstore<kBaseStore>(rb, idx * 4u, 0u, b);
     }
   };
-  using View = ViewT<kPopLoad>;
+};
+
+// Component-interleaved offsets (the single box): the offsets of every component
+// of one direction and cell sit together, r[(a cells + y) nc + s], and so do the
+// bases, base[y nc + s]; one vector access moves all nc components of a cell (the
+// step kernels k_psi_ilv / k_collide_ilv).  comp(s) views component s with strided
+// scalar accesses, for the kernels around the step (moments, export, import, the
+// adjoint).  Same encoding as OffsetPops.
+template <typename H>
+struct IlvPops {
+  using R = float;
+  using Elem = H;
+  float* base;
+  H* r;
+  int nc;
+  struct View {
+    rsrc_t rb, rr;
+    unsigned plane;   // bytes per direction plane of r (cells nc sizeof(H))
+    unsigned rs, ro;  // bytes between cells in r; byte offset of this component
+    unsigned bs, bo;  // the same for the base
+    using Elem = H;
+    __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
+      return bload(rb, idx * bs + bo, 0u, 0.0f) * (w + bload<kPopLoad>(rr, idx * rs + ro, (unsigned)a * plane, H()));
+    }
+    __device__ __forceinline__ float get_at(unsigned idx, unsigned pbytes, float w) const {
+      return bload(rb, idx * bs + bo, 0u, 0.0f) * (w + bload<kPopLoad>(rr, idx * rs + ro + pbytes, 0u, H()));
+    }
+    template <int Q, typename W>
+    __device__ __forceinline__ void put_all(unsigned idx, const float* v, double mass, W w) const {
+      H rq[Q];
+      const float b = encode_offsets<Q, H, false>(v, mass, w, rq);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) bstore<kPopStore>(rr, idx * rs + ro, (unsigned)a * plane, rq[a]);
+      bstore<kBaseStore>(rb, idx * bs + bo, 0u, b);
+    }
+  };
   __device__ __forceinline__ View comp(int s, int Q, int cells) const {
-    const unsigned plane = (unsigned)cells * (unsigned)sizeof(H);
-    return View{make_rsrc(base + (size_t)s * cells, (unsigned)cells * 4u),
-                make_rsrc(r + (size_t)s * Q * cells, (unsigned)Q * plane), plane, base + (size_t)s * cells};
-  }
-  static __device__ __forceinline__ H enc(float v) {
-    if constexpr (std::is_same<H, __half>::value) return __float2half_rn(v);
-    else return v;
+    const unsigned cs = (unsigned)nc * (unsigned)sizeof(H);
+    const unsigned plane = (unsigned)cells * cs;
+    return View{make_rsrc(base, (unsigned)cells * (unsigned)nc * 4u), make_rsrc(r, (unsigned)Q * plane), plane, cs,
+                (unsigned)s * (unsigned)sizeof(H), (unsigned)nc * 4u, (unsigned)s * 4u};
   }
 };
 
 template <>
-struct Pops<LBM_F32_OFS> : OffsetPops<float> {};
+struct Pops<LBM_F32_OFS> : IlvPops<float> {};
 template <>
-struct Pops<LBM_F16_OFS> : OffsetPops<__half> {};
+struct Pops<LBM_F16_OFS> : IlvPops<__half> {};
 
 // Cell coordinates with periodic neighbours; at(dx,dy,dz) is the linear index of
 // the neighbour at offset (dx, dy, dz).
@@ -646,17 +688,37 @@ __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R r
   sink(fo);
 }
 
-template <int LAT, int ST, int COLL, int FORC>
-__device__ __forceinline__ void collide_store(const KParams& P, const Pops<ST>& out, int s, unsigned xo,
-                                              unsigned ro, const typename Pops<ST>::R* f, typename Pops<ST>::R rs,
-                                              const typename Pops<ST>::R* u3, const typename Pops<ST>::R* F3,
-                                              double mass) {
-  using V = VS<LAT>;
-  using R = typename Pops<ST>::R;
-  constexpr int Q = V::Q;
-  collide_values<LAT, R, COLL, FORC>(P, f, rs, u3, F3, [&](const R* fo) {
-    out.comp(s, Q, P.cells).template put_all_row<Q, true>(xo, ro, fo, mass, [](int a) { return (R)V::w(a); });
-  });
+// Equilibrium velocity and forcing input of component s at a cell, in the
+// collision precision R (float64 for float64 storage, float32 otherwise):
+//   Guo: u = (j + F_total/2)/rho (shared), F_s = chi_s F + rbar_s g;
+//   EDM: u_s = (j + F_total/2)/rho - du_s/2, du_s = gamma_s F / Gamma + g (= F_s / rbar_s),
+//        so that component s gains exactly F_s where it rests (Sec. 3.1,
+//        Eq. hydrostatic1), as with Guo's term;
+// chi_s = gamma_s rbar_s / Gamma, Gamma = sum gamma_i rbar_i (Eq. distributionforce).
+template <int FORC, typename R>
+__device__ __forceinline__ void cell_velocity_split(const KParams& P, int s, double rho, double Gam, const double* j,
+                                                    const double* F, R rs, R* u, R* fs) {
+  const R g0 = (R)P.accel[0], g1 = (R)P.accel[1], g2 = (R)P.accel[2];
+  const R rhoR = (R)rho, irho = quot((R)1, rhoR);
+  const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
+  const R ch = quot((R)P.gamma[s], (R)Gam);   // chi_s / rbar_s
+  if (FORC == LBM_GUO) {
+    // u = (j + F_total/2) / rho, F_total = F + rho g
+    u[0] = ((R)j[0] + (R)0.5 * (FR[0] + rhoR * g0)) * irho;
+    u[1] = ((R)j[1] + (R)0.5 * (FR[1] + rhoR * g1)) * irho;
+    u[2] = ((R)j[2] + (R)0.5 * (FR[2] + rhoR * g2)) * irho;
+    fs[0] = ch * rs * FR[0] + rs * g0;
+    fs[1] = ch * rs * FR[1] + rs * g1;
+    fs[2] = ch * rs * FR[2] + rs * g2;
+  } else {
+    // (j + F/2) / rho - (gamma_s / Gamma) F / 2: the g of F_total and of du_s cancel
+    u[0] = ((R)j[0] + (R)0.5 * FR[0]) * irho - (R)0.5 * (ch * FR[0]);
+    u[1] = ((R)j[1] + (R)0.5 * FR[1]) * irho - (R)0.5 * (ch * FR[1]);
+    u[2] = ((R)j[2] + (R)0.5 * FR[2]) * irho - (R)0.5 * (ch * FR[2]);
+    fs[0] = ch * FR[0] + g0;
+    fs[1] = ch * FR[1] + g1;
+    fs[2] = ch * FR[2] + g2;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -693,62 +755,15 @@ __host__ __device__ constexpr bool row_shifted(int r) {
   return false;
 }
 
-// Offset storage, row-structured pull of one component (no walls): the stored
-// base is one value per cell, so the bases of the Q source cells come from one
-// vector load per source row at x; x - 1 and x + 1 follow by lane shifts, and
-// the two values past the wavefront's ends (x0 - 1 and x0 + 64, periodic) from
-// wavefront-uniform scalar loads.  In a row shorter than the wavefront the lanes
-// past its end hold x = 0, so the last cell's right neighbour is the first cell,
-// as periodicity requires.  All lanes must be active; f gets the decoded pulls.
-// MIX: decode w + r with the mixed-precision FMA (fewer instructions, same values;
-// the collide pass); the psi pass, bound by memory, keeps the add, whose schedule
-// needs fewer registers (98 against 91 VGPRs cost it a wave per SIMD).
-template <int LAT, bool MIX, typename View>
-__device__ __forceinline__ void pull_row_offset(const View& cv, const RowCoord& c, unsigned nx, float* f) {
-  using V = VS<LAT>;
-  constexpr int Q = V::Q;
-  using H = typename View::Elem;
-  const unsigned xl = c.x0 == 0 ? nx - 1 : c.x0 - 1;
-  const unsigned xr = c.x0 + 64u < nx ? c.x0 + 64u : 0u;
-  float bq[9], hl[9], hr[9], rq[Q];
-  static_for<0, 9>([&](auto Rr) {
-    constexpr int r = decltype(Rr)::value;
-    if constexpr (row_used<LAT>(r)) {
-      const unsigned ro = c.row(r % 3 - 1, r / 3 - 1);
-      bq[r] = bload(cv.rb, c.x(0) * 4u, ro * 4u, 0.0f);
-      if constexpr (row_shifted<LAT>(r)) {
-        hl[r] = cv.bp[ro + xl];
-        hr[r] = cv.bp[ro + xr];
-      }
-    }
-  });
-#pragma unroll
-  for (int a = 0; a < Q; ++a)
-    rq[a] = bload<kPopLoad>(cv.rr, c.x(-V::cx(a)) * (unsigned)sizeof(H),
-                  (unsigned)a * cv.plane + c.row(-V::cy(a), -V::cz(a)) * (unsigned)sizeof(H), H());
-  __builtin_amdgcn_sched_barrier(0);   // every load ahead of the shifts and the decode
-  const float one = opaque_one();
-  static_for<0, Q>([&](auto A) {
-    constexpr int a = decltype(A)::value;
-    constexpr int r = pull_row<LAT>(a);
-    float b;
-    if constexpr (V::cx(a) == 0) b = bq[r];
-    else if constexpr (V::cx(a) > 0) b = lane_from_left(bq[r], hl[r]);   // source x - 1
-    else b = lane_from_right(bq[r], hr[r]);                              // source x + 1
-    if constexpr (MIX) f[a] = b * w_plus((float)V::w(a), rq[a], one);
-    else f[a] = b * ((float)V::w(a) + rq[a]);
-  });
-}
-
-// pass 1: densities -> EOS -> psi on planes [plane0, plane0 + nplanes)
+// pass 1 (float64 storage): densities -> EOS -> psi on planes [plane0, plane0 + nplanes)
 // Each wavefront covers 64 cells of one row (as in the collide pass): segment
 // logical_block() * (B / 64) + wavefront, B the threads per workgroup (kBlock; 64
 // for small launches, see psi_small); see psi_blocks for the grid.
 template <int LAT, int NC, int ST, int B = kBlock>
 __global__ __launch_bounds__(B) void k_psi(KParams P, Pops<ST> in, double* __restrict__ psi, int plane0,
                                           int nplanes) {
+  static_assert(ST == LBM_F64, "offset storage runs k_psi_ilv");
   using V = VS<LAT>;
-  using R = typename Pops<ST>::R;
   constexpr int Q = V::Q;
   const unsigned lane = threadIdx.x & 63u;
   const unsigned seg = logical_block() * (B / 64) + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -763,29 +778,27 @@ __global__ __launch_bounds__(B) void k_psi(KParams P, Pops<ST> in, double* __res
 #pragma unroll 1
   for (int s = 0; s < NC; ++s) {
     const auto cv = in.comp(s, Q, P.cells);
-    R v[Q];
+    double v[Q];
     // every lane pulls (lanes past the row end at x = 0; all addresses in range)
     if (P.bb) {   // walls: halfway bounce-back for pulls whose source is solid; fluid cells only
       if (in_row && !(bits >> kSolidBit)) {
 #pragma unroll
         for (int a = 0; a < Q; ++a)
-          v[a] = pull_bb<LAT>(cv, a, bits, cell, c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a)), (R)V::w(a));
+          v[a] = pull_bb<LAT>(cv, a, bits, cell, c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a)), V::w(a));
       } else {
 #pragma unroll
         for (int a = 0; a < Q; ++a) v[a] = 0;
       }
-    } else if constexpr (ST != LBM_F64) {
-      pull_row_offset<LAT, false>(cv, c, (unsigned)P.nx, v);
     } else {
 #pragma unroll
-      for (int a = 0; a < Q; ++a) v[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
+      for (int a = 0; a < Q; ++a) v[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), V::w(a));
     }
-    R acc = 0;
+    double acc = 0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) acc += v[a];
 #pragma unroll
     for (int t = 0; t < NC; ++t)
-      if (t == s) rb[t] = (double)acc;
+      if (t == s) rb[t] = acc;
   }
   if (!in_row) return;
   if (bits >> kSolidBit) psi[cell] = P.psi_wall;   // solid: the wall's psi, no EOS
@@ -806,44 +819,20 @@ inline unsigned psi_blocks(const KParams& P, int np, int D, int B = kBlock) {
 constexpr unsigned kSmallPsiSegments = 4u * 256u;
 inline bool psi_small(const KParams& P, int np, int D) { return psi_segments(P, np, D) < kSmallPsiSegments; }
 
-// pass 2: a block is 64 cells x NC wavefronts, wavefront s working on component s.
-// psi at a cell and at the stencil directions a with (a - 1) mod NC == s of the
-// wavefront of component s; a uniform branch on s keeps every direction's offsets
-// compile-time constants (all addresses in range).
-template <int LAT, int NC>
-struct PsiShare {
-  double ps;
-  double pn[(VS<LAT>::Q - 1 + NC - 1) / NC];
-};
-template <int LAT, int NC>
-__device__ __forceinline__ PsiShare<LAT, NC> load_psi_share(rsrc_t psr, const RowCoord& c, int s) {
-  using V = VS<LAT>;
-  PsiShare<LAT, NC> v;
-  v.ps = bload(psr, c.x(0) * 8u, c.row(0, 0) * 8u, 0.0);
-  static_for<0, NC>([&](auto S_) {
-    constexpr int S = decltype(S_)::value;
-    if (s == S) {
-      static_for<1, V::Q>([&](auto A) {
-        constexpr int a = decltype(A)::value;
-        if constexpr ((a - 1) % NC == S)
-          v.pn[(a - 1) / NC] = bload(psr, c.x(V::cx(a)) * 8u, c.row(V::cy(a), V::cz(a)) * 8u, 0.0);
-      });
-    }
-  });
-  return v;
-}
-
-// Each wavefront pulls its component (rbar_s, j_s) and sums the psi stencil over
-// the directions a with (a - 1) mod NC == s; the block combines the per-component
-// sums through LDS in a fixed component order (rho, Gamma, j, F identical in every
-// wavefront), then each wavefront splits the force, collides and stores component s.
+// pass 2 (float64 storage): a block is 64 cells x NC wavefronts, wavefront s
+// working on component s.  Each wavefront pulls its component (rbar_s, j_s) and
+// sums the psi stencil over the directions a with (a - 1) mod NC == s; the block
+// combines the per-component sums through LDS in a fixed component order (rho,
+// Gamma, j, F identical in every wavefront), then each wavefront splits the
+// force, collides and stores component s.
 constexpr int kCells = 64;
 
 template <int LAT, int NC, int ST, int COLL, int FORC>
 __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, Pops<ST> out,
                                                        const double* __restrict__ psi, int plane0, int nplanes) {
+  static_assert(ST == LBM_F64, "offset storage runs k_collide_ilv");
   using V = VS<LAT>;
-  using R = typename Pops<ST>::R;
+  using R = double;
   constexpr int Q = V::Q;
   __shared__ double red[NC][7][kCells];
   const int lane = threadIdx.x & (kCells - 1);
@@ -858,15 +847,9 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   const rsrc_t psr = make_rsrc(psi, (unsigned)P.cells * 8u);
   const unsigned own = c.row(0, 0) + c.x(0);
   const unsigned bits = P.bb ? P.bb[own] : 0u;   // walls: per-cell direction mask
-  // psi at the cell and at this wavefront's stencil directions: the offset formats
-  // load them ahead of the pulls, so that their latency overlaps the pulls'
-  // (float16 collide -5 %); the float64 kernel, bound by HBM bandwidth, loads them
-  // after its pulls (ahead: +1.6 %)
-  PsiShare<LAT, NC> pv{};
-  if constexpr (ST != LBM_F64) pv = load_psi_share<LAT, NC>(psr, c, s);
   R f[Q];
-  R rs = 0, jx = 0, jy = 0, jz = 0;
-  double mass = 0.0;   // the component's mass, summed exactly (rs in float64 storage)
+  R jx = 0, jy = 0, jz = 0;
+  double mass = 0.0;
   double Fp[3] = {0.0, 0.0, 0.0};
   // every lane pulls (lanes past the row end at x = 0; all addresses in range)
   if (P.bb) {
@@ -883,8 +866,6 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
 #pragma unroll
       for (int a = 0; a < Q; ++a) f[a] = 0;
     }
-  } else if constexpr (ST != LBM_F64) {
-    pull_row_offset<LAT, true>(cv, c, (unsigned)P.nx, f);
   } else {
 #pragma unroll
     for (int a = 0; a < Q; ++a) f[a] = cv.get_row(a, c.x(-V::cx(a)), c.row(-V::cy(a), -V::cz(a)), (R)V::w(a));
@@ -892,43 +873,30 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   if (valid) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      mass += (double)f[a];
+      mass += f[a];
       if (V::cx(a)) jx += (R)V::cx(a) * f[a];
       if (V::cy(a)) jy += (R)V::cy(a) * f[a];
       if (V::cz(a)) jz += (R)V::cz(a) * f[a];
     }
-    rs = (R)mass;
     // partial stencil of Eq. (coupledMCforce) over this wavefront's directions
     const double hb = 0.5 * (1.0 - P.beta);
-    auto term = [&](auto A, double ps, double pn) {
+    const double ps = bload(psr, c.x(0) * 8u, c.row(0, 0) * 8u, 0.0);
+    static_for<1, Q>([&](auto A) {
       constexpr int a = decltype(A)::value;
-      const double t = V::w(a) * pn * (P.beta * ps + hb * pn);
-      if constexpr (V::cx(a) != 0) Fp[0] += V::cx(a) * t;
-      if constexpr (V::cy(a) != 0) Fp[1] += V::cy(a) * t;
-      if constexpr (V::cz(a) != 0) Fp[2] += V::cz(a) * t;
-    };
-    if constexpr (ST == LBM_F64) {   // each psi loaded where it is used
-      const double ps = bload(psr, c.x(0) * 8u, c.row(0, 0) * 8u, 0.0);
-      static_for<1, Q>([&](auto A) {
-        constexpr int a = decltype(A)::value;
-        if ((a - 1) % NC == s) term(A, ps, bload(psr, c.x(V::cx(a)) * 8u, c.row(V::cy(a), V::cz(a)) * 8u, 0.0));
-      });
-    } else {
-      static_for<0, NC>([&](auto S_) {
-        constexpr int S = decltype(S_)::value;
-        if (s == S) {
-          static_for<1, Q>([&](auto A) {
-            constexpr int a = decltype(A)::value;
-            if constexpr ((a - 1) % NC == S) term(A, pv.ps, pv.pn[(a - 1) / NC]);
-          });
-        }
-      });
-    }
+      if ((a - 1) % NC == s) {
+        const double pn = bload(psr, c.x(V::cx(a)) * 8u, c.row(V::cy(a), V::cz(a)) * 8u, 0.0);
+        const double t = V::w(a) * pn * (P.beta * ps + hb * pn);
+        if constexpr (V::cx(a) != 0) Fp[0] += V::cx(a) * t;
+        if constexpr (V::cy(a) != 0) Fp[1] += V::cy(a) * t;
+        if constexpr (V::cz(a) != 0) Fp[2] += V::cz(a) * t;
+      }
+    });
   }
+  const R rs = mass;
   red[s][0][lane] = mass;
-  red[s][1][lane] = (double)jx;
-  red[s][2][lane] = (double)jy;
-  red[s][3][lane] = (double)jz;
+  red[s][1][lane] = jx;
+  red[s][2][lane] = jy;
+  red[s][3][lane] = jz;
   red[s][4][lane] = Fp[0];
   red[s][5][lane] = Fp[1];
   red[s][6][lane] = Fp[2];
@@ -951,39 +919,362 @@ __global__ __launch_bounds__(kCells * 4) void k_collide(KParams P, Pops<ST> in, 
   F[1] *= -P.G;
   F[2] *= -P.G;
   if (valid && !(Gam > 0.0)) flag_error(P);
-  // velocity and split in the collision precision R (float64 storage: double)
-  const R g0 = (R)P.accel[0], g1 = (R)P.accel[1], g2 = (R)P.accel[2];
-  const R rhoR = (R)rho, irho = quot((R)1, rhoR);
-  const R FR[3] = {(R)F[0], (R)F[1], (R)F[2]};
-  R u[3];
-  const R ch = quot((R)P.gamma[s], (R)Gam);   // chi_s / rbar_s
-  if (FORC == LBM_GUO) {
-    // u = (j + F_total/2) / rho, F_total = F + rho g
-    u[0] = ((R)j[0] + (R)0.5 * (FR[0] + rhoR * g0)) * irho;
-    u[1] = ((R)j[1] + (R)0.5 * (FR[1] + rhoR * g1)) * irho;
-    u[2] = ((R)j[2] + (R)0.5 * (FR[2] + rhoR * g2)) * irho;
-  } else {
-    // equilibrium velocity of component s: U - du_s / 2 with U = (j + F_total/2) / rho
-    // and du_s = gamma_s F / Gamma + g, i.e. (j + F/2) / rho - (gamma_s / Gamma) F / 2
-    u[0] = ((R)j[0] + (R)0.5 * FR[0]) * irho - (R)0.5 * (ch * FR[0]);
-    u[1] = ((R)j[1] + (R)0.5 * FR[1]) * irho - (R)0.5 * (ch * FR[1]);
-    u[2] = ((R)j[2] + (R)0.5 * FR[2]) * irho - (R)0.5 * (ch * FR[2]);
-  }
-  R fs[3];
-  if (FORC == LBM_GUO) {                // F_s = chi_s F + rbar_s g
-    fs[0] = ch * rs * FR[0] + rs * g0;
-    fs[1] = ch * rs * FR[1] + rs * g1;
-    fs[2] = ch * rs * FR[2] + rs * g2;
-  } else {                              // du_s = F_s / rbar_s = gamma_s F / Gamma + g
-    fs[0] = ch * FR[0] + g0;
-    fs[1] = ch * FR[1] + g1;
-    fs[2] = ch * FR[2] + g2;
-  }
+  R u[3], fs[3];
+  cell_velocity_split<FORC>(P, s, rho, Gam, j, F, rs, u, fs);
   if (!valid) {   // a solid cell (walls): f = 0, rbar = 0 and u = du = 0 collide to zeros
     u[0] = u[1] = u[2] = 0;
     fs[0] = fs[1] = fs[2] = 0;
   }
-  collide_store<LAT, ST, COLL, FORC>(P, out, s, c.x(0), c.row(0, 0), f, rs, u, fs, mass);
+  collide_values<LAT, R, COLL, FORC>(P, f, rs, u, fs, [&](const R* fo) {
+    out.comp(s, Q, P.cells).template put_all_row<Q>(c.x(0), c.row(0, 0), fo, mass, [](int a) { return V::w(a); });
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Component-interleaved offset storage (IlvPops): one lane = one cell with all
+// its components.  Each direction's nc offsets are one vector load (float16: 2 nc
+// bytes, float32: 4 nc bytes) and so are a cell's nc bases; per wavefront of 64
+// cells the pull takes Q offset loads and one base load per source row, where the
+// per-component layout took nc times as many.
+// ---------------------------------------------------------------------------
+
+// Dwords holding the nc values of H of one cell.
+template <typename H, int NC>
+struct IlvWords {
+  static constexpr int N = std::is_same<H, __half>::value ? (NC + 1) / 2 : NC;
+};
+
+// Load / store the nc values of H of one cell at byte offset voff + soff.
+// Float16 with nc = 3 (6 bytes) takes a dword and a 16-bit access.
+template <int CP, typename H, int NC>
+__device__ __forceinline__ void ilv_load(rsrc_t r, unsigned voff, unsigned soff, unsigned* w) {
+  constexpr int N = IlvWords<H, NC>::N;
+  if constexpr (std::is_same<H, __half>::value && NC == 3) {
+    w[0] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, CP);
+    w[1] = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, voff + 4u, soff, CP);
+  } else if constexpr (std::is_same<H, __half>::value && NC == 1) {
+    w[0] = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, CP);
+  } else if constexpr (N == 1) {
+    w[0] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, CP);
+  } else if constexpr (N == 2) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, CP);
+    w[0] = (unsigned)v[0];
+    w[1] = (unsigned)v[1];
+  } else if constexpr (N == 3) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, CP);
+    w[0] = (unsigned)v[0];
+    w[1] = (unsigned)v[1];
+    w[2] = (unsigned)v[2];
+  } else {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, CP);
+    w[0] = (unsigned)v[0];
+    w[1] = (unsigned)v[1];
+    w[2] = (unsigned)v[2];
+    w[3] = (unsigned)v[3];
+  }
+}
+template <int CP, typename H, int NC>
+__device__ __forceinline__ void ilv_store(rsrc_t r, unsigned voff, unsigned soff, const unsigned* w) {
+  constexpr int N = IlvWords<H, NC>::N;
+  if constexpr (std::is_same<H, __half>::value && NC == 3) {
+    __builtin_amdgcn_raw_buffer_store_b32(w[0], r, voff, soff, CP);
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)w[1], r, voff + 4u, soff, CP);
+  } else if constexpr (std::is_same<H, __half>::value && NC == 1) {
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)w[0], r, voff, soff, CP);
+  } else if constexpr (N == 1) {
+    __builtin_amdgcn_raw_buffer_store_b32(w[0], r, voff, soff, CP);
+  } else if constexpr (N == 2) {
+    decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) v;
+    v[0] = w[0];
+    v[1] = w[1];
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, CP);
+  } else if constexpr (N == 3) {
+    decltype(__builtin_amdgcn_raw_buffer_load_b96(r, 0, 0, 0)) v;
+    v[0] = w[0];
+    v[1] = w[1];
+    v[2] = w[2];
+    __builtin_amdgcn_raw_buffer_store_b96(v, r, voff, soff, CP);
+  } else {
+    decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) v;
+    v[0] = w[0];
+    v[1] = w[1];
+    v[2] = w[2];
+    v[3] = w[3];
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, CP);
+  }
+}
+// value s of H packed in the dwords w, widened to float32
+template <typename H>
+__device__ __forceinline__ float ilv_get(const unsigned* w, int s) {
+  if constexpr (std::is_same<H, __half>::value) {
+    const unsigned short b = (unsigned short)((s & 1) ? (w[s >> 1] >> 16) : (w[s >> 1] & 0xffffu));
+    return __half2float(__builtin_bit_cast(__half, b));
+  } else {
+    return __builtin_bit_cast(float, w[s]);
+  }
+}
+template <typename H>
+__device__ __forceinline__ void ilv_set(unsigned* w, int s, H v) {
+  if constexpr (std::is_same<H, __half>::value) {
+    const unsigned b = (unsigned)__builtin_bit_cast(unsigned short, v);
+    if (s & 1) w[s >> 1] |= b << 16;
+    else w[s >> 1] = b;
+  } else {
+    w[s] = __builtin_bit_cast(unsigned, v);
+  }
+}
+
+// Buffer resources and strides of the interleaved planes of a box.
+template <typename H, int NC, int Q>
+struct IlvBufs {
+  rsrc_t rb, rr;
+  unsigned plane;                                   // bytes per direction plane
+  static constexpr unsigned cs = NC * sizeof(H);    // bytes per cell in a plane
+  static constexpr unsigned bs = NC * 4u;           // bytes per cell of the base
+  __device__ __forceinline__ IlvBufs(const IlvPops<H>& p, int cells) {
+    plane = (unsigned)cells * cs;
+    rb = make_rsrc(p.base, (unsigned)cells * bs);
+    rr = make_rsrc(p.r, (unsigned)Q * plane);
+  }
+};
+
+// Pull of all components at one cell, decoded: f[s][a] = b_s(src) (w_a + r_a,s(src)).
+// Row-structured (no walls): the bases of the Q sources come from one vector load
+// per source row at x, with x - 1 and x + 1 taken from the neighbouring lanes (DPP
+// wave shifts) and the two values past the wavefront's ends from wavefront-uniform
+// scalar loads (see row_segment: lanes past a short row's end hold x = 0, the
+// periodic right neighbour of its last cell).  Every lane must be active.
+template <int LAT, int NC, typename H>
+__device__ __forceinline__ void ilv_pull_row(const IlvPops<H>& in, const IlvBufs<H, NC, VS<LAT>::Q>& B,
+                                             const RowCoord& c, unsigned nx, float (&f)[NC][VS<LAT>::Q]) {
+  using V = VS<LAT>;
+  constexpr int Q = V::Q;
+  constexpr int NW = IlvWords<H, NC>::N;
+  using IB = IlvBufs<H, NC, Q>;
+  const unsigned xl = c.x0 == 0 ? nx - 1 : c.x0 - 1;
+  const unsigned xr = c.x0 + 64u < nx ? c.x0 + 64u : 0u;
+  unsigned bq[9][NC];
+  float hl[9][NC], hr[9][NC];
+  unsigned rw[Q][NW];
+  static_for<0, 9>([&](auto Rr) {
+    constexpr int r = decltype(Rr)::value;
+    if constexpr (row_used<LAT>(r)) {
+      const unsigned ro = c.row(r % 3 - 1, r / 3 - 1);
+      ilv_load<0, float, NC>(B.rb, c.x(0) * IB::bs, ro * IB::bs, bq[r]);
+      if constexpr (row_shifted<LAT>(r)) {
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+          hl[r][s] = in.base[(size_t)(ro + xl) * NC + s];
+          hr[r][s] = in.base[(size_t)(ro + xr) * NC + s];
+        }
+      }
+    }
+  });
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+    ilv_load<kPopLoad, H, NC>(B.rr, c.x(-V::cx(a)) * IB::cs, (unsigned)a * B.plane + c.row(-V::cy(a), -V::cz(a)) * IB::cs,
+                              rw[a]);
+  __builtin_amdgcn_sched_barrier(0);   // every load ahead of the shifts and the decode
+  const float one = opaque_one();
+  static_for<0, Q>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    constexpr int r = pull_row<LAT>(a);
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+      const float b0 = __builtin_bit_cast(float, bq[r][s]);
+      float b;
+      if constexpr (V::cx(a) == 0) b = b0;
+      else if constexpr (V::cx(a) > 0) b = lane_from_left(b0, hl[r][s]);   // source x - 1
+      else b = lane_from_right(b0, hr[r][s]);                              // source x + 1
+      f[s][a] = b * w_plus((float)V::w(a), ilv_get<H>(rw[a], s), one);
+    }
+  });
+}
+
+// Pull with walls (halfway bounce-back, see pull_bb): per lane, direction a comes
+// from the neighbour x - e_a, or, where that is solid, from the cell's own slot of
+// the opposite direction; the source's bases are loaded per direction.
+template <int LAT, int NC, typename H>
+__device__ __forceinline__ void ilv_pull_bb(const IlvBufs<H, NC, VS<LAT>::Q>& B, const RowCoord& c, unsigned bits,
+                                            float (&f)[NC][VS<LAT>::Q]) {
+  using V = VS<LAT>;
+  constexpr int Q = V::Q;
+  constexpr int NW = IlvWords<H, NC>::N;
+  using IB = IlvBufs<H, NC, Q>;
+  const unsigned own = c.row(0, 0) + c.x(0);
+  unsigned bw[Q][NC], rw[Q][NW];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const bool back = (bits >> a) & 1u;
+    const unsigned src = back ? own : c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a));
+    const unsigned dir = back ? (unsigned)V::opp(a) : (unsigned)a;
+    ilv_load<0, float, NC>(B.rb, src * IB::bs, 0u, bw[a]);
+    ilv_load<kPopLoad, H, NC>(B.rr, src * IB::cs + dir * B.plane, 0u, rw[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+#pragma unroll
+    for (int s = 0; s < NC; ++s)
+      f[s][a] = __builtin_bit_cast(float, bw[a][s]) * ((float)V::w(a) + ilv_get<H>(rw[a], s));
+}
+
+// pass 1 (interleaved offset storage): densities -> EOS -> psi, one cell per lane
+// with all its components; row segments as in k_psi.
+template <int LAT, int NC, int ST, int B = kBlock>
+__global__ __launch_bounds__(B) void k_psi_ilv(KParams P, Pops<ST> in, double* __restrict__ psi, int plane0,
+                                              int nplanes) {
+  using V = VS<LAT>;
+  using H = typename Pops<ST>::Elem;
+  constexpr int Q = V::Q;
+  const unsigned lane = threadIdx.x & 63u;
+  const unsigned seg = logical_block() * (B / 64) + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  RowCoord c;
+  bool in_row = false;
+  if (!row_segment<V::D>(P, seg, plane0, nplanes, lane, &c, &in_row)) return;   // uniform per wavefront
+  const unsigned cell = c.row(0, 0) + c.x(0);
+  const unsigned bits = P.bb ? P.bb[cell] : 0u;
+  const IlvBufs<H, NC, Q> Bf(in, P.cells);
+  float f[NC][Q];
+  if (P.bb) {
+    if (in_row && !(bits >> kSolidBit)) {
+      ilv_pull_bb<LAT, NC, H>(Bf, c, bits, f);
+    } else {
+#pragma unroll
+      for (int s = 0; s < NC; ++s)
+#pragma unroll
+        for (int a = 0; a < Q; ++a) f[s][a] = 0.0f;
+    }
+  } else {
+    ilv_pull_row<LAT, NC, H>(in, Bf, c, (unsigned)P.nx, f);   // every lane pulls
+  }
+  if (!in_row) return;
+  if (bits >> kSolidBit) {   // solid: the wall's psi, no EOS
+    psi[cell] = P.psi_wall;
+    return;
+  }
+  double rb[NC];
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) acc += (double)f[s][a];
+    rb[s] = acc;
+  }
+  psi[cell] = eos_psi<NC>(P, rb);
+}
+
+// pass 2 (interleaved offset storage): one cell per lane with all its components.
+// Loads psi at the cell and its Q - 1 neighbours and the pulls of every component,
+// sums the stencil of Eq. (coupledMCforce), the densities and momenta, forms the
+// velocity and the split, then collides and encodes each component in turn and
+// stores each direction's nc offsets with one vector store.  Workgroups of 4 row
+// segments (wavefronts), each independent.
+constexpr int kIlvWaves = 4;
+
+template <int LAT, int NC, int ST, int COLL, int FORC>
+__global__ __launch_bounds__(64 * kIlvWaves) void k_collide_ilv(KParams P, Pops<ST> in, Pops<ST> out,
+                                                               const double* __restrict__ psi, int plane0,
+                                                               int nplanes) {
+  using V = VS<LAT>;
+  using H = typename Pops<ST>::Elem;
+  using R = float;
+  constexpr int Q = V::Q;
+  constexpr int NW = IlvWords<H, NC>::N;
+  using IB = IlvBufs<H, NC, Q>;
+  const unsigned lane = threadIdx.x & 63u;
+  const unsigned seg = logical_block() * kIlvWaves + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  RowCoord c;
+  bool in_row = false;
+  if (!row_segment<V::D>(P, seg, plane0, nplanes, lane, &c, &in_row)) return;   // uniform per wavefront
+  const unsigned own = c.row(0, 0) + c.x(0);
+  const unsigned bits = P.bb ? P.bb[own] : 0u;
+  const bool valid = in_row && !(bits >> kSolidBit);
+  // psi at the cell and its neighbours first: their latency overlaps the pulls'
+  const rsrc_t psr = make_rsrc(psi, (unsigned)P.cells * 8u);
+  double pn[Q];
+  static_for<0, Q>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    pn[a] = bload(psr, c.x(V::cx(a)) * 8u, c.row(V::cy(a), V::cz(a)) * 8u, 0.0);
+  });
+  const IB Bi(in, P.cells);
+  float f[NC][Q];
+  if (P.bb) {
+    // walls: solid cells do not pull and do not collide; their slots are never
+    // read and hold zeros, which their lanes store again (whole rows written)
+    if (valid) {
+      ilv_pull_bb<LAT, NC, H>(Bi, c, bits, f);
+    } else {
+#pragma unroll
+      for (int s = 0; s < NC; ++s)
+#pragma unroll
+        for (int a = 0; a < Q; ++a) f[s][a] = 0.0f;
+    }
+  } else {
+    ilv_pull_row<LAT, NC, H>(in, Bi, c, (unsigned)P.nx, f);   // every lane pulls
+  }
+  if (!in_row) return;
+  // total force of Eq. (coupledMCforce) (float64)
+  double F[3] = {0.0, 0.0, 0.0};
+  {
+    const double hb = 0.5 * (1.0 - P.beta);
+    static_for<1, Q>([&](auto A) {
+      constexpr int a = decltype(A)::value;
+      const double t = V::w(a) * pn[a] * (P.beta * pn[0] + hb * pn[a]);
+      if constexpr (V::cx(a) != 0) F[0] += V::cx(a) * t;
+      if constexpr (V::cy(a) != 0) F[1] += V::cy(a) * t;
+      if constexpr (V::cz(a) != 0) F[2] += V::cz(a) * t;
+    });
+    F[0] *= -P.G;
+    F[1] *= -P.G;
+    F[2] *= -P.G;
+  }
+  // densities (float64 masses, exact for the encoding) and momentum
+  double mass[NC], rho = 0.0, Gam = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    double m = 0.0;
+    R jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      m += (double)f[s][a];
+      if (V::cx(a)) jx += (R)V::cx(a) * f[s][a];
+      if (V::cy(a)) jy += (R)V::cy(a) * f[s][a];
+      if (V::cz(a)) jz += (R)V::cz(a) * f[s][a];
+    }
+    mass[s] = valid ? m : 0.0;
+    rho += mass[s];
+    Gam += P.gamma[s] * mass[s];
+    j[0] += (double)jx;
+    j[1] += (double)jy;
+    j[2] += (double)jz;
+  }
+  if (valid && !(Gam > 0.0)) flag_error(P);
+  unsigned ro[Q][NW];
+  float bo[NC];
+  static_for<0, NC>([&](auto S_) {
+    constexpr int s = decltype(S_)::value;
+    const R rs = (R)mass[s];
+    R u[3], fs[3];
+    cell_velocity_split<FORC>(P, s, rho, Gam, j, F, rs, u, fs);
+    if (!valid) {   // a solid cell (walls): f = 0, rbar = 0 and u = du = 0 collide to zeros
+      u[0] = u[1] = u[2] = 0;
+      fs[0] = fs[1] = fs[2] = 0;
+    }
+    collide_values<LAT, R, COLL, FORC>(P, f[s], rs, u, fs, [&](const R* fo) {
+      H rq[Q];
+      bo[s] = encode_offsets<Q, H, true>(fo, mass[s], [](int a) { return (R)V::w(a); }, rq);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) ilv_set<H>(ro[a], s, rq[a]);
+    });
+  });
+  const IB Bo(out, P.cells);
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+    ilv_store<kPopStore, H, NC>(Bo.rr, c.x(0) * IB::cs, (unsigned)a * Bo.plane + c.row(0, 0) * IB::cs, ro[a]);
+  unsigned bw[NC];
+#pragma unroll
+  for (int s = 0; s < NC; ++s) bw[s] = __builtin_bit_cast(unsigned, bo[s]);
+  ilv_store<kBaseStore, float, NC>(Bo.rb, c.x(0) * IB::bs, c.row(0, 0) * IB::bs, bw);
 }
 
 }  // namespace lbmk
