@@ -1043,52 +1043,66 @@ struct IlvBufs {
 // per source row at x, with x - 1 and x + 1 taken from the neighbouring lanes (DPP
 // wave shifts) and the two values past the wavefront's ends from wavefront-uniform
 // scalar loads (see row_segment: lanes past a short row's end hold x = 0, the
-// periodic right neighbour of its last cell).  Every lane must be active.
+// periodic right neighbour of its last cell).  issue() starts every load, decode()
+// shifts and decodes; every lane of the wavefront must be active in decode().
 template <int LAT, int NC, typename H>
-__device__ __forceinline__ void ilv_pull_row(const IlvPops<H>& in, const IlvBufs<H, NC, VS<LAT>::Q>& B,
-                                             const RowCoord& c, unsigned nx, float (&f)[NC][VS<LAT>::Q]) {
-  using V = VS<LAT>;
-  constexpr int Q = V::Q;
-  constexpr int NW = IlvWords<H, NC>::N;
-  using IB = IlvBufs<H, NC, Q>;
-  const unsigned xl = c.x0 == 0 ? nx - 1 : c.x0 - 1;
-  const unsigned xr = c.x0 + 64u < nx ? c.x0 + 64u : 0u;
+struct IlvRowPull {
+  static constexpr int Q = VS<LAT>::Q;
+  static constexpr int NW = IlvWords<H, NC>::N;
   unsigned bq[9][NC];
   float hl[9][NC], hr[9][NC];
   unsigned rw[Q][NW];
-  static_for<0, 9>([&](auto Rr) {
-    constexpr int r = decltype(Rr)::value;
-    if constexpr (row_used<LAT>(r)) {
-      const unsigned ro = c.row(r % 3 - 1, r / 3 - 1);
-      ilv_load<0, float, NC>(B.rb, c.x(0) * IB::bs, ro * IB::bs, bq[r]);
-      if constexpr (row_shifted<LAT>(r)) {
+  __device__ __forceinline__ void issue(const IlvPops<H>& in, const IlvBufs<H, NC, Q>& B, const RowCoord& c,
+                                        unsigned nx) {
+    using V = VS<LAT>;
+    using IB = IlvBufs<H, NC, Q>;
+    const unsigned xl = c.x0 == 0 ? nx - 1 : c.x0 - 1;
+    const unsigned xr = c.x0 + 64u < nx ? c.x0 + 64u : 0u;
+    static_for<0, 9>([&](auto Rr) {
+      constexpr int r = decltype(Rr)::value;
+      if constexpr (row_used<LAT>(r)) {
+        const unsigned ro = c.row(r % 3 - 1, r / 3 - 1);
+        ilv_load<0, float, NC>(B.rb, c.x(0) * IB::bs, ro * IB::bs, bq[r]);
+        if constexpr (row_shifted<LAT>(r)) {
 #pragma unroll
-        for (int s = 0; s < NC; ++s) {
-          hl[r][s] = in.base[(size_t)(ro + xl) * NC + s];
-          hr[r][s] = in.base[(size_t)(ro + xr) * NC + s];
+          for (int s = 0; s < NC; ++s) {
+            hl[r][s] = in.base[(size_t)(ro + xl) * NC + s];
+            hr[r][s] = in.base[(size_t)(ro + xr) * NC + s];
+          }
         }
       }
-    }
-  });
+    });
 #pragma unroll
-  for (int a = 0; a < Q; ++a)
-    ilv_load<kPopLoad, H, NC>(B.rr, c.x(-V::cx(a)) * IB::cs, (unsigned)a * B.plane + c.row(-V::cy(a), -V::cz(a)) * IB::cs,
-                              rw[a]);
+    for (int a = 0; a < Q; ++a)
+      ilv_load<kPopLoad, H, NC>(B.rr, c.x(-V::cx(a)) * IB::cs,
+                                (unsigned)a * B.plane + c.row(-V::cy(a), -V::cz(a)) * IB::cs, rw[a]);
+  }
+  __device__ __forceinline__ void decode(float (&f)[NC][Q]) const {
+    using V = VS<LAT>;
+    const float one = opaque_one();
+    static_for<0, Q>([&](auto A) {
+      constexpr int a = decltype(A)::value;
+      constexpr int r = pull_row<LAT>(a);
+#pragma unroll
+      for (int s = 0; s < NC; ++s) {
+        const float b0 = __builtin_bit_cast(float, bq[r][s]);
+        float b;
+        if constexpr (V::cx(a) == 0) b = b0;
+        else if constexpr (V::cx(a) > 0) b = lane_from_left(b0, hl[r][s]);   // source x - 1
+        else b = lane_from_right(b0, hr[r][s]);                              // source x + 1
+        f[s][a] = b * w_plus((float)V::w(a), ilv_get<H>(rw[a], s), one);
+      }
+    });
+  }
+};
+
+template <int LAT, int NC, typename H>
+__device__ __forceinline__ void ilv_pull_row(const IlvPops<H>& in, const IlvBufs<H, NC, VS<LAT>::Q>& B,
+                                             const RowCoord& c, unsigned nx, float (&f)[NC][VS<LAT>::Q]) {
+  IlvRowPull<LAT, NC, H> p;
+  p.issue(in, B, c, nx);
   __builtin_amdgcn_sched_barrier(0);   // every load ahead of the shifts and the decode
-  const float one = opaque_one();
-  static_for<0, Q>([&](auto A) {
-    constexpr int a = decltype(A)::value;
-    constexpr int r = pull_row<LAT>(a);
-#pragma unroll
-    for (int s = 0; s < NC; ++s) {
-      const float b0 = __builtin_bit_cast(float, bq[r][s]);
-      float b;
-      if constexpr (V::cx(a) == 0) b = b0;
-      else if constexpr (V::cx(a) > 0) b = lane_from_left(b0, hl[r][s]);   // source x - 1
-      else b = lane_from_right(b0, hr[r][s]);                              // source x + 1
-      f[s][a] = b * w_plus((float)V::w(a), ilv_get<H>(rw[a], s), one);
-    }
-  });
+  p.decode(f);
 }
 
 // Pull with walls (halfway bounce-back, see pull_bb): per lane, direction a comes
@@ -1213,13 +1227,15 @@ __global__ __launch_bounds__(64 * kIlvWaves) void k_collide_ilv(KParams P, Pops<
     ilv_pull_row<LAT, NC, H>(in, Bi, c, (unsigned)P.nx, f);   // every lane pulls
   }
   if (!in_row) return;
-  // total force of Eq. (coupledMCforce) (float64)
+  // total force of Eq. (coupledMCforce) (float64), summed over opposite pairs:
+  // w psi_a (b psi + h psi_a) - w psi_b (b psi + h psi_b) = w (psi_a - psi_b) (b psi + h (psi_a + psi_b))
   double F[3] = {0.0, 0.0, 0.0};
   {
     const double hb = 0.5 * (1.0 - P.beta);
-    static_for<1, Q>([&](auto A) {
-      constexpr int a = decltype(A)::value;
-      const double t = V::w(a) * pn[a] * (P.beta * pn[0] + hb * pn[a]);
+    const double bps = P.beta * pn[0];
+    static_for<0, (Q - 1) / 2>([&](auto Pp) {
+      constexpr int a = V::pair_first(decltype(Pp)::value), b = V::opp(a);
+      const double t = V::w(a) * (pn[a] - pn[b]) * (bps + hb * (pn[a] + pn[b]));
       if constexpr (V::cx(a) != 0) F[0] += V::cx(a) * t;
       if constexpr (V::cy(a) != 0) F[1] += V::cy(a) * t;
       if constexpr (V::cz(a) != 0) F[2] += V::cz(a) * t;
@@ -1228,25 +1244,32 @@ __global__ __launch_bounds__(64 * kIlvWaves) void k_collide_ilv(KParams P, Pops<
     F[1] *= -P.G;
     F[2] *= -P.G;
   }
-  // densities (float64 masses, exact for the encoding) and momentum
-  double mass[NC], rho = 0.0, Gam = 0.0, j[3] = {0.0, 0.0, 0.0};
+  // densities (float64 masses, exact for the encoding) and the momentum, summed
+  // over the components of each direction first (float32, then widened)
+  double mass[NC], rho = 0.0, Gam = 0.0, j[3];
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
     double m = 0.0;
-    R jx = 0, jy = 0, jz = 0;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      m += (double)f[s][a];
-      if (V::cx(a)) jx += (R)V::cx(a) * f[s][a];
-      if (V::cy(a)) jy += (R)V::cy(a) * f[s][a];
-      if (V::cz(a)) jz += (R)V::cz(a) * f[s][a];
-    }
+    for (int a = 0; a < Q; ++a) m += (double)f[s][a];
     mass[s] = valid ? m : 0.0;
     rho += mass[s];
     Gam += P.gamma[s] * mass[s];
-    j[0] += (double)jx;
-    j[1] += (double)jy;
-    j[2] += (double)jz;
+  }
+  {
+    R jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      R g = f[0][a];
+#pragma unroll
+      for (int s = 1; s < NC; ++s) g += f[s][a];
+      if (V::cx(a)) jx += (R)V::cx(a) * g;
+      if (V::cy(a)) jy += (R)V::cy(a) * g;
+      if (V::cz(a)) jz += (R)V::cz(a) * g;
+    }
+    j[0] = (double)jx;
+    j[1] = (double)jy;
+    j[2] = (double)jz;
   }
   if (valid && !(Gam > 0.0)) flag_error(P);
   unsigned ro[Q][NW];
