@@ -5,9 +5,11 @@
 // Storage: the boxes' population planes are concatenated; box b owns the
 // elements [pop_off, pop_off + nc Q cells) of the population array(s) (and
 // [base_off, base_off + nc cells) of the float32 base in the offset formats),
-// plus [psi_off, psi_off + cells) of the psi scratch.  The per-step arithmetic is
-// the single-box one (lbm_kernels.hpp), with the component count read from the
-// box descriptor instead of a template parameter.
+// plus [psi_off, psi_off + cells) of the psi scratch.  float64 boxes keep
+// per-component planes [nc][Q][cells] (kb_psi / kb_collide); the offset formats
+// interleave the components, [Q][cells][nc] (kb_psi_ilv / kb_collide_ilv).  The
+// per-step arithmetic is the single-box one (lbm_kernels.hpp), with the
+// component count read from the box descriptor.
 //
 // Launch: a persistent grid (a multiple of the 8 XCDs, sized to the resident
 // workgroups); XCD x sweeps tiles [x T/8, (x+1) T/8) of the work list in order, so
@@ -62,27 +64,33 @@ struct BatchPops<LBM_F64> {
     return Pops<LBM_F64>::View{make_rsrc(f + B.pop_off + (size_t)s * Q * B.cells, (unsigned)Q * plane), plane};
   }
 };
+// Component-interleaved offsets of the boxes (as IlvPops for the single box): box
+// b's offsets [Q][cells_b][nc_b] at elements [pop_off, pop_off + nc Q cells) of r,
+// its bases [cells_b][nc_b] at [base_off, base_off + nc cells) of base; comp(s)
+// views component s (the kernels around the step), bufs() gives the all-component
+// planes (kb_psi_ilv, kb_collide_ilv).
 template <typename H>
-struct BatchOffsetPops {
+struct BatchIlvPops {
   using R = float;
+  using Elem = H;
   float* base;
   H* r;
-  // float16 offsets load with the default cache policy: a 64-cell tile spans
-  // several short rows, and the shifted pulls of the neighbouring tiles read the
-  // same lines again (measured: non-temporal loads slow the float16 batch by 3 %,
-  // while they speed up the float32 and float64 batches)
-  static constexpr int kLoad = std::is_same<H, __half>::value ? 0 : kPopLoad;
-  using View = typename OffsetPops<H>::template ViewT<kLoad>;
+  using View = typename IlvPops<H>::View;
   __device__ __forceinline__ View comp(const BoxK& B, int s, int Q) const {
-    const unsigned plane = B.cells * (unsigned)sizeof(H);
-    return View{make_rsrc(base + B.base_off + (size_t)s * B.cells, B.cells * 4u),
-                make_rsrc(r + B.pop_off + (size_t)s * Q * B.cells, (unsigned)Q * plane), plane};
+    const unsigned cs = (unsigned)B.nc * (unsigned)sizeof(H);
+    const unsigned plane = B.cells * cs;
+    return View{make_rsrc(base + B.base_off, B.cells * (unsigned)B.nc * 4u), make_rsrc(r + B.pop_off, (unsigned)Q * plane),
+                plane, cs, (unsigned)s * (unsigned)sizeof(H), (unsigned)B.nc * 4u, (unsigned)s * 4u};
+  }
+  template <int NC, int Q>
+  __device__ __forceinline__ IlvBufs<H, NC, Q> bufs(const BoxK& B) const {
+    return IlvBufs<H, NC, Q>(base + B.base_off, r + B.pop_off, B.cells);
   }
 };
 template <>
-struct BatchPops<LBM_F32_OFS> : BatchOffsetPops<float> {};
+struct BatchPops<LBM_F32_OFS> : BatchIlvPops<float> {};
 template <>
-struct BatchPops<LBM_F16_OFS> : BatchOffsetPops<__half> {};
+struct BatchPops<LBM_F16_OFS> : BatchIlvPops<__half> {};
 
 __device__ __forceinline__ void batch_flag(const BatchK& K, int box) {
   K.err[0] = 1;
@@ -136,10 +144,11 @@ __device__ __forceinline__ double box_psi(const BatchK& K, const BoxK& B, int bo
   return sqrt(X);
 }
 
-// pass 1 over every tile: densities -> EOS -> psi
+// pass 1 over every tile (float64 planes): densities -> EOS -> psi
 template <int LAT, int ST>
 __global__ __launch_bounds__(1024) void kb_psi(BatchK K, const BoxK* __restrict__ boxes, const int* __restrict__ tile_box,
                                               BatchPops<ST> in, double* __restrict__ psi) {
+  static_assert(ST == LBM_F64, "the offset formats use kb_psi_ilv");
   using V = VS<LAT>;
   using R = typename BatchPops<ST>::R;
   const TileRange tr = tile_range(K.ntiles);
@@ -180,7 +189,7 @@ __global__ __launch_bounds__(1024) void kb_psi(BatchK K, const BoxK* __restrict_
   }
 }
 
-// pass 2 over every tile.  A workgroup is NCMAX groups of `tile` threads (the
+// pass 2 over every tile (float64 planes).  A workgroup is NCMAX groups of `tile` threads (the
 // largest component count of the batch); group s owns component s of the tile's
 // cells, as in the single-box k_collide: it pulls and decodes that component,
 // adds a share of the psi stencil (directions a with (a - 1) mod NCMAX = s, also
@@ -191,6 +200,7 @@ template <int LAT, int NCMAX, int ST, int COLL, int FORC>
 __global__ __launch_bounds__(1024) void kb_collide(BatchK K, const BoxK* __restrict__ boxes,
                                                   const int* __restrict__ tile_box, BatchPops<ST> in,
                                                   BatchPops<ST> out, const double* __restrict__ psi) {
+  static_assert(ST == LBM_F64, "the offset formats use kb_collide_ilv");
   using V = VS<LAT>;
   using R = typename BatchPops<ST>::R;
   constexpr int Q = V::Q;
@@ -391,6 +401,224 @@ __global__ __launch_bounds__(1024) void kb_init(BatchK K, const BoxK* __restrict
       }
       out.comp(B, s, Q).template put_all<Q>(cell, v, sum, [](int a) { return (R)V::w(a); });
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Interleaved offset storage: one cell per thread with all its components (the
+// box's component count selects the instantiation, uniform per tile)
+// ---------------------------------------------------------------------------
+
+// pull of all components at a cell of a box: per direction one vector load of the
+// source's nc offsets and one of its nc bases; with walls, halfway bounce-back
+// (the source x - e_a when fluid, else the cell's own slot of the opposite direction)
+template <int LAT, int NC, typename H, int CP>
+__device__ __forceinline__ void kbi_pull(const IlvBufs<H, NC, VS<LAT>::Q>& Bf, const Coord& c, unsigned cell,
+                                         unsigned bits, bool walls, float (&f)[NC][VS<LAT>::Q]) {
+  using V = VS<LAT>;
+  constexpr int Q = V::Q;
+  constexpr int NW = IlvWords<H, NC>::N;
+  using IB = IlvBufs<H, NC, Q>;
+  unsigned bw[Q][NC], rw[Q][NW];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const bool back = walls && ((bits >> a) & 1u);
+    const unsigned src = back ? cell : c.at(-V::cx(a), -V::cy(a), -V::cz(a));
+    const unsigned dir = back ? (unsigned)V::opp(a) : (unsigned)a;
+    ilv_load<0, float, NC>(Bf.rb, src * IB::bs, 0u, bw[a]);
+    ilv_load<CP, H, NC>(Bf.rr, src * IB::cs + dir * Bf.plane, 0u, rw[a]);
+  }
+  __builtin_amdgcn_sched_barrier(0);   // every load ahead of the decode
+  const float one = opaque_one();
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+#pragma unroll
+    for (int s = 0; s < NC; ++s)
+      f[s][a] = __builtin_bit_cast(float, bw[a][s]) * w_plus((float)V::w(a), ilv_get<H>(rw[a], s), one);
+}
+
+// cache policy of the batched offset loads: float16 keeps the default (a 64-cell
+// tile spans several short rows, whose shifted pulls read lines of the
+// neighbouring tile again), float32 streams them
+template <typename H>
+constexpr int kbi_load_policy() { return std::is_same<H, __half>::value ? 0 : kPopLoad; }
+
+template <int LAT, int NC, typename H>
+__device__ __forceinline__ void kbi_psi_cell(const BatchK& K, const BoxK& B, int bx, const BatchIlvPops<H>& in,
+                                             const Coord& c, unsigned cell, unsigned bits, double* psi) {
+  constexpr int Q = VS<LAT>::Q;
+  const auto Bf = in.template bufs<NC, Q>(B);
+  float f[NC][Q];
+  kbi_pull<LAT, NC, H, kbi_load_policy<H>()>(Bf, c, cell, bits, B.walls != 0, f);
+  double rb[LBM_MAX_NC];
+#pragma unroll
+  for (int s = 0; s < LBM_MAX_NC; ++s) rb[s] = 0.0;
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) acc += (double)f[s][a];
+    rb[s] = acc;
+  }
+  psi[B.psi_off + cell] = box_psi(K, B, bx, rb);
+}
+
+// pass 1 over every tile (interleaved offsets): densities -> EOS -> psi
+template <int LAT, int NCMAX, int ST>
+__global__ __launch_bounds__(256) void kb_psi_ilv(BatchK K, const BoxK* __restrict__ boxes,
+                                                  const int* __restrict__ tile_box, BatchPops<ST> in,
+                                                  double* __restrict__ psi) {
+  using H = typename BatchPops<ST>::Elem;
+  const TileRange tr = tile_range(K.ntiles);
+  for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
+    const int bx = __builtin_amdgcn_readfirstlane(tile_box[t]);
+    const BoxK& B = boxes[bx];
+    const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
+    if (cell >= B.cells) continue;
+    const Coord c = box_coord(cell, B);
+    const unsigned bits = B.walls ? K.bb[B.bb_off + cell] : 0u;
+    if (bits >> kSolidBit) {           // solid cell: the wall's psi
+      psi[B.psi_off + cell] = B.psi_wall;
+      continue;
+    }
+    const int nc = B.nc;
+    if (nc == 1) kbi_psi_cell<LAT, 1, H>(K, B, bx, in, c, cell, bits, psi);
+    if constexpr (NCMAX >= 2)
+      if (nc == 2) kbi_psi_cell<LAT, 2, H>(K, B, bx, in, c, cell, bits, psi);
+    if constexpr (NCMAX >= 3)
+      if (nc == 3) kbi_psi_cell<LAT, 3, H>(K, B, bx, in, c, cell, bits, psi);
+    if constexpr (NCMAX >= 4)
+      if (nc == 4) kbi_psi_cell<LAT, 4, H>(K, B, bx, in, c, cell, bits, psi);
+  }
+}
+
+template <int LAT, int NC, typename H, int COLL, int FORC>
+__device__ __forceinline__ void kbi_collide_cell(const BatchK& K, const KParams& P, const BoxK& B, int bx,
+                                                 const BatchIlvPops<H>& in, const BatchIlvPops<H>& out,
+                                                 const Coord& c, unsigned cell, unsigned bits,
+                                                 const double* __restrict__ psi) {
+  using V = VS<LAT>;
+  using R = float;
+  constexpr int Q = V::Q;
+  constexpr int NW = IlvWords<H, NC>::N;
+  using IB = IlvBufs<H, NC, Q>;
+  const bool valid = !(bits >> kSolidBit);
+  const double* ps = psi + B.psi_off;
+  double pn[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) pn[a] = ps[c.at(V::cx(a), V::cy(a), V::cz(a))];
+  const IB Bi = in.template bufs<NC, Q>(B);
+  float f[NC][Q];
+  if (valid) {
+    kbi_pull<LAT, NC, H, kbi_load_policy<H>()>(Bi, c, cell, bits, B.walls != 0, f);
+  } else {   // solid cells: no pull, no collision; their lanes store zeros into never-read slots
+#pragma unroll
+    for (int s = 0; s < NC; ++s)
+#pragma unroll
+      for (int a = 0; a < Q; ++a) f[s][a] = 0.0f;
+  }
+  // total force of Eq. (coupledMCforce) (float64), summed over opposite pairs
+  double F[3] = {0.0, 0.0, 0.0};
+  {
+    const double hb = 0.5 * (1.0 - B.beta);
+    const double bps = B.beta * pn[0];
+    static_for<0, (Q - 1) / 2>([&](auto Pp) {
+      constexpr int a = V::pair_first(decltype(Pp)::value), b = V::opp(a);
+      const double t = V::w(a) * (pn[a] - pn[b]) * (bps + hb * (pn[a] + pn[b]));
+      if constexpr (V::cx(a) != 0) F[0] += V::cx(a) * t;
+      if constexpr (V::cy(a) != 0) F[1] += V::cy(a) * t;
+      if constexpr (V::cz(a) != 0) F[2] += V::cz(a) * t;
+    });
+    F[0] *= -B.G;
+    F[1] *= -B.G;
+    F[2] *= -B.G;
+  }
+  double mass[NC], rho = 0.0, Gam = 0.0, j[3];
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    double m = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) m += (double)f[s][a];
+    mass[s] = m;
+    rho += m;
+    Gam += B.gamma[s] * m;
+  }
+  {
+    R jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      R g = f[0][a];
+#pragma unroll
+      for (int s = 1; s < NC; ++s) g += f[s][a];
+      if (V::cx(a)) jx += (R)V::cx(a) * g;
+      if (V::cy(a)) jy += (R)V::cy(a) * g;
+      if (V::cz(a)) jz += (R)V::cz(a) * g;
+    }
+    j[0] = (double)jx;
+    j[1] = (double)jy;
+    j[2] = (double)jz;
+  }
+  if (valid && !(Gam > 0.0)) batch_flag(K, bx);
+  unsigned ro[Q][NW];
+  float bo[NC];
+  static_for<0, NC>([&](auto S_) {
+    constexpr int s = decltype(S_)::value;
+    const R rs = (R)mass[s];
+    R u[3], fs[3];
+    cell_velocity_split<FORC>(P, s, rho, Gam, j, F, rs, u, fs);
+    if (!valid) {   // a solid cell: f = 0, rbar = 0 and u = du = 0 collide to zeros
+      u[0] = u[1] = u[2] = 0;
+      fs[0] = fs[1] = fs[2] = 0;
+    }
+    collide_values<LAT, R, COLL, FORC>(P, f[s], rs, u, fs, [&](const R* fo) {
+      H rq[Q];
+      bo[s] = encode_offsets<Q, H, true>(fo, mass[s], [](int a) { return (R)V::w(a); }, rq);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) ilv_set<H>(ro[a], s, rq[a]);
+    });
+  });
+  const IB Bo = out.template bufs<NC, Q>(B);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) ilv_store<kPopStore, H, NC>(Bo.rr, cell * IB::cs, (unsigned)a * Bo.plane, ro[a]);
+  unsigned bw[NC];
+#pragma unroll
+  for (int s = 0; s < NC; ++s) bw[s] = __builtin_bit_cast(unsigned, bo[s]);
+  ilv_store<kBaseStore, float, NC>(Bo.rb, cell * IB::bs, 0u, bw);
+}
+
+// pass 2 over every tile (interleaved offsets): one cell per thread with all its
+// components (no LDS, no idle component groups for boxes with fewer components)
+template <int LAT, int NCMAX, int ST, int COLL, int FORC>
+__global__ __launch_bounds__(256) void kb_collide_ilv(BatchK K, const BoxK* __restrict__ boxes,
+                                                     const int* __restrict__ tile_box, BatchPops<ST> in,
+                                                     BatchPops<ST> out, const double* __restrict__ psi) {
+  using H = typename BatchPops<ST>::Elem;
+  KParams P;
+#pragma unroll
+  for (int k = 0; k < LBM_MAX_Q; ++k) P.mrt_c[k] = K.mrt_c[k];
+  P.mrt_rows = K.mrt_rows;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) P.accel[d] = K.accel[d];
+  const TileRange tr = tile_range(K.ntiles);
+  for (unsigned t = tr.t; t < tr.end; t += tr.stride) {
+    const int bx = __builtin_amdgcn_readfirstlane(tile_box[t]);
+    const BoxK& B = boxes[bx];
+    const unsigned cell = (t - B.first_tile) * (unsigned)K.tile + threadIdx.x;
+    if (cell >= B.cells) continue;
+    const Coord c = box_coord(cell, B);
+    const unsigned bits = B.walls ? K.bb[B.bb_off + cell] : 0u;
+    P.cells = (int)B.cells;
+    P.omega = B.omega;
+#pragma unroll
+    for (int s = 0; s < LBM_MAX_NC; ++s) P.gamma[s] = B.gamma[s];
+    const int nc = B.nc;
+    if (nc == 1) kbi_collide_cell<LAT, 1, H, COLL, FORC>(K, P, B, bx, in, out, c, cell, bits, psi);
+    if constexpr (NCMAX >= 2)
+      if (nc == 2) kbi_collide_cell<LAT, 2, H, COLL, FORC>(K, P, B, bx, in, out, c, cell, bits, psi);
+    if constexpr (NCMAX >= 3)
+      if (nc == 3) kbi_collide_cell<LAT, 3, H, COLL, FORC>(K, P, B, bx, in, out, c, cell, bits, psi);
+    if constexpr (NCMAX >= 4)
+      if (nc == 4) kbi_collide_cell<LAT, 4, H, COLL, FORC>(K, P, B, bx, in, out, c, cell, bits, psi);
   }
 }
 

@@ -51,15 +51,27 @@ struct BOps {
 
 template <int LAT, int NCMAX, int ST, int COLL, int FORC>
 struct BOpsImpl {
-  static size_t lds(int tile) { return (size_t)NCMAX * 7 * tile * sizeof(double); }
+  // float64: kb_psi / kb_collide (nc_max component groups of tile threads, LDS
+  // combine); offset storage: kb_psi_ilv / kb_collide_ilv (tile threads, one cell each)
+  static constexpr bool kIlv = ST != LBM_F64;
+  static size_t lds(int tile) { return kIlv ? 0 : (size_t)NCMAX * 7 * tile * sizeof(double); }
+  static int collide_threads(int tile) { return kIlv ? tile : tile * NCMAX; }
   static void psi(const BatchK& K, int grid, const BBufs& in, double* psi, hipStream_t st) {
-    hipLaunchKernelGGL((kb_psi<LAT, ST>), dim3(grid), dim3(K.tile), 0, st, K, K.boxes, K.tile_box, bpops<ST>(in),
-                       psi);
+    if constexpr (kIlv)
+      hipLaunchKernelGGL((kb_psi_ilv<LAT, NCMAX, ST>), dim3(grid), dim3(K.tile), 0, st, K, K.boxes, K.tile_box,
+                         bpops<ST>(in), psi);
+    else
+      hipLaunchKernelGGL((kb_psi<LAT, ST>), dim3(grid), dim3(K.tile), 0, st, K, K.boxes, K.tile_box, bpops<ST>(in),
+                         psi);
   }
   static void collide(const BatchK& K, int grid, const BBufs& in, const BBufs& out, const double* psi,
                       hipStream_t st) {
-    hipLaunchKernelGGL((kb_collide<LAT, NCMAX, ST, COLL, FORC>), dim3(grid), dim3(K.tile * NCMAX), lds(K.tile), st,
-                       K, K.boxes, K.tile_box, bpops<ST>(in), bpops<ST>(out), psi);
+    if constexpr (kIlv)
+      hipLaunchKernelGGL((kb_collide_ilv<LAT, NCMAX, ST, COLL, FORC>), dim3(grid), dim3(K.tile), 0, st, K, K.boxes,
+                         K.tile_box, bpops<ST>(in), bpops<ST>(out), psi);
+    else
+      hipLaunchKernelGGL((kb_collide<LAT, NCMAX, ST, COLL, FORC>), dim3(grid), dim3(K.tile * NCMAX), lds(K.tile), st,
+                         K, K.boxes, K.tile_box, bpops<ST>(in), bpops<ST>(out), psi);
   }
   static void exp(const BatchK& K, int grid, const BBufs& in, const unsigned long long* off, double* rho,
                   double* f, hipStream_t st) {
@@ -73,12 +85,17 @@ struct BOpsImpl {
   }
   static void occupancy(int tile, int* per_cu) {
     int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kb_psi<LAT, ST>, tile, 0) != hipSuccess) a = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb_collide<LAT, NCMAX, ST, COLL, FORC>, tile * NCMAX,
-                                                     lds(tile)) != hipSuccess)
-      b = 1;
-    per_cu[0] = std::max(1, a);
-    per_cu[1] = std::max(1, b);
+    hipError_t ea, eb;
+    if constexpr (kIlv) {
+      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kb_psi_ilv<LAT, NCMAX, ST>, tile, 0);
+      eb = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb_collide_ilv<LAT, NCMAX, ST, COLL, FORC>, tile, 0);
+    } else {
+      ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kb_psi<LAT, ST>, tile, 0);
+      eb = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb_collide<LAT, NCMAX, ST, COLL, FORC>, tile * NCMAX,
+                                                        lds(tile));
+    }
+    per_cu[0] = ea == hipSuccess ? std::max(1, a) : 1;
+    per_cu[1] = eb == hipSuccess ? std::max(1, b) : 1;
   }
   static BOps ops() { return BOps{&psi, &collide, &exp, &init, &occupancy, NCMAX}; }
 };

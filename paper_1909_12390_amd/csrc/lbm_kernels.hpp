@@ -197,59 +197,12 @@ __device__ __forceinline__ float encode_offsets(const float* v, double mass, W w
   return S >= 0.5 ? (float)(mass / S) : b0;
 }
 
-// Per-component offset planes (the batched boxes): layout [nc][Q][cells] for the
-// offsets, [nc][cells] for the float32 base; comp(s) views component s.
-template <typename H>
-struct OffsetPops {
-  using R = float;
-  float* base;
-  H* r;
-  // LP: cache policy of the offset loads (the batched kernels choose their own)
-  template <int LP>
-  struct ViewT {
-    rsrc_t rb, rr;
-    unsigned plane;   // bytes per direction plane of r
-    using Elem = H;
-    __device__ __forceinline__ float get(int a, unsigned idx, float w) const {
-      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<LP>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H()));
-    }
-    __device__ __forceinline__ float get_at(unsigned idx, unsigned pbytes, float w) const {
-      return bload(rb, idx * 4u, 0u, 0.0f) * (w + bload<LP>(rr, idx * (unsigned)sizeof(H) + pbytes, 0u, H()));
-    }
-    // all Q directions, direction a from cell src(a): every load is issued before
-    // the first decode, so the wavefront keeps 2Q loads in flight
-    template <int Q, typename Src, typename W>
-    __device__ __forceinline__ void get_all(Src src, float* out, W w) const {
-      float bq[Q], rq[Q];   // rq: offsets already widened to float32
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        const unsigned idx = src(a);
-        bq[a] = bload(rb, idx * 4u, 0u, 0.0f);
-        rq[a] = bload<LP>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, H());
-      }
-      __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the decode
-#pragma unroll
-      for (int a = 0; a < Q; ++a) out[a] = bq[a] * (w(a) + rq[a]);
-    }
-    // v: post-collision populations; mass: the cell's mass of this component
-    // (sum of v, summed exactly in float64); w(a): weights (encode_offsets)
-    template <int Q, typename W>
-    __device__ __forceinline__ void put_all(unsigned idx, const float* v, double mass, W w) const {
-      H rq[Q];
-      const float b = encode_offsets<Q, H, false>(v, mass, w, rq);
-#pragma unroll
-      for (int a = 0; a < Q; ++a) bstore<kPopStore>(rr, idx * (unsigned)sizeof(H), (unsigned)a * plane, rq[a]);
-      bstore<kBaseStore>(rb, idx * 4u, 0u, b);
-    }
-  };
-};
-
-// Component-interleaved offsets (the single box): the offsets of every component
-// of one direction and cell sit together, r[(a cells + y) nc + s], and so do the
-// bases, base[y nc + s]; one vector access moves all nc components of a cell (the
-// step kernels k_psi_ilv / k_collide_ilv).  comp(s) views component s with strided
-// scalar accesses, for the kernels around the step (moments, export, import, the
-// adjoint).  Same encoding as OffsetPops.
+// Component-interleaved offsets: the offsets of every component of one direction
+// and cell sit together, r[(a cells + y) nc + s], and so do the bases,
+// base[y nc + s]; one vector access moves all nc components of a cell (the step
+// kernels k_psi_ilv / k_collide_ilv, and kb_psi_ilv / kb_collide_ilv per box).
+// comp(s) views component s with strided scalar accesses, for the kernels around
+// the step (moments, export, import, the adjoint).  Decoding: f_a = b (w_a + r_a).
 template <typename H>
 struct IlvPops {
   using R = float;
@@ -1031,10 +984,11 @@ struct IlvBufs {
   unsigned plane;                                   // bytes per direction plane
   static constexpr unsigned cs = NC * sizeof(H);    // bytes per cell in a plane
   static constexpr unsigned bs = NC * 4u;           // bytes per cell of the base
-  __device__ __forceinline__ IlvBufs(const IlvPops<H>& p, int cells) {
-    plane = (unsigned)cells * cs;
-    rb = make_rsrc(p.base, (unsigned)cells * bs);
-    rr = make_rsrc(p.r, (unsigned)Q * plane);
+  __device__ __forceinline__ IlvBufs(const IlvPops<H>& p, int cells) : IlvBufs(p.base, p.r, (unsigned)cells) {}
+  __device__ __forceinline__ IlvBufs(const float* base, const H* r, unsigned cells) {
+    plane = cells * cs;
+    rb = make_rsrc(base, cells * bs);
+    rr = make_rsrc(r, (unsigned)Q * plane);
   }
 };
 
