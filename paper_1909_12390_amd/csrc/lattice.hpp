@@ -125,6 +125,57 @@ __host__ __device__ constexpr double mrow_norm2(int k) {
 template <int LAT>
 __host__ __device__ constexpr bool row_odd(int k) { return row_odd_impl<LAT>(k); }
 
+template <int LAT>
+__host__ __device__ constexpr int vel(int a, int i) {
+  return i == 0 ? VS<LAT>::cx(a) : (i == 1 ? VS<LAT>::cy(a) : VS<LAT>::cz(a));
+}
+
+// Row k's moment of the second-order equilibrium feq_a = w_a rho (1 + 3 e.u +
+// 9/2 (e.u)^2 - 3/2 u.u), a quadratic in u:
+//   sum_a mrow(k, a) feq_a = rho (eq_c0(k) + sum_i eq_c1(k, i) u_i + sum_{i<=j} eq_c2(k, i, j) u_i u_j)
+template <int LAT>
+__host__ __device__ constexpr double eq_c0(int k) {
+  double s = 0.0;
+  for (int a = 0; a < VS<LAT>::Q; ++a) s += VS<LAT>::mrow(k, a) * VS<LAT>::w(a);
+  return s;
+}
+template <int LAT>
+__host__ __device__ constexpr double eq_c1(int k, int i) {
+  double s = 0.0;
+  for (int a = 0; a < VS<LAT>::Q; ++a) s += 3.0 * VS<LAT>::mrow(k, a) * VS<LAT>::w(a) * vel<LAT>(a, i);
+  return s;
+}
+template <int LAT>
+__host__ __device__ constexpr double eq_c2(int k, int i, int j) {
+  double s = 0.0;
+  for (int a = 0; a < VS<LAT>::Q; ++a) {
+    const double cc = (i == j ? 4.5 : 9.0) * vel<LAT>(a, i) * vel<LAT>(a, j) - (i == j ? 1.5 : 0.0);
+    s += VS<LAT>::mrow(k, a) * VS<LAT>::w(a) * cc;
+  }
+  return s;
+}
+
+// squared speed class of velocity a (0 rest, 1 axis, 2 diagonal)
+template <int LAT>
+__host__ __device__ constexpr int speed2(int a) {
+  return VS<LAT>::cx(a) * VS<LAT>::cx(a) + VS<LAT>::cy(a) * VS<LAT>::cy(a) + VS<LAT>::cz(a) * VS<LAT>::cz(a);
+}
+// row k's entry on speed class c (the entry of the first velocity of that class)
+template <int LAT>
+__host__ __device__ constexpr double mrow_class(int k, int c) {
+  for (int a = 0; a < VS<LAT>::Q; ++a)
+    if (speed2<LAT>(a) == c) return VS<LAT>::mrow(k, a);
+  return 0.0;
+}
+// true if row k's entries depend on |e_a|^2 only (the energy rows e and epsilon):
+// such a row is a combination of the class sums of the populations
+template <int LAT>
+__host__ __device__ constexpr bool row_isotropic(int k) {
+  for (int a = 0; a < VS<LAT>::Q; ++a)
+    if (VS<LAT>::mrow(k, a) != mrow_class<LAT>(k, speed2<LAT>(a))) return false;
+  return true;
+}
+
 // compile-time checks of the tables: opp is an involution that reverses e_a, the
 // pairs cover every moving velocity once, every MRT row is even or odd.
 template <int LAT>
@@ -150,5 +201,23 @@ constexpr bool tables_consistent() {
 }
 static_assert(tables_consistent<LBM_D2Q9>(), "D2Q9 tables");
 static_assert(tables_consistent<LBM_D3Q19>(), "D3Q19 tables");
+// equilibrium moments: density row rho, momentum rows rho u, the energy row e of
+// D3Q19 -11 rho + 19 rho u.u, its shear row 3p_xx rho (2u_x^2 - u_y^2 - u_z^2)
+constexpr bool near(double a, double b) { return a - b < 1e-12 && b - a < 1e-12; }
+static_assert(near(eq_c0<LBM_D3Q19>(0), 1.0) && near(eq_c1<LBM_D3Q19>(3, 0), 1.0) &&
+                  near(eq_c1<LBM_D3Q19>(3, 1), 0.0) && near(eq_c0<LBM_D2Q9>(0), 1.0),
+              "eq rho, j");
+static_assert(near(eq_c0<LBM_D2Q9>(1), -2.0) && near(eq_c2<LBM_D2Q9>(1, 0, 0), 3.0) &&
+                  near(eq_c2<LBM_D2Q9>(7, 0, 0), 1.0) && near(eq_c2<LBM_D2Q9>(8, 0, 1), 1.0),
+              "eq D2Q9 e, p_xx, p_xy");
+static_assert(near(eq_c0<LBM_D3Q19>(1), -11.0) && near(eq_c2<LBM_D3Q19>(1, 0, 0), 19.0) &&
+                  near(eq_c2<LBM_D3Q19>(1, 0, 1), 0.0),
+              "eq e");
+static_assert(near(eq_c2<LBM_D3Q19>(9, 0, 0), 2.0) && near(eq_c2<LBM_D3Q19>(9, 1, 1), -1.0) &&
+                  near(eq_c2<LBM_D3Q19>(13, 0, 1), 1.0) && near(eq_c0<LBM_D3Q19>(9), 0.0),
+              "eq 3p_xx, p_xy");
+static_assert(row_isotropic<LBM_D3Q19>(1) && row_isotropic<LBM_D3Q19>(2) && !row_isotropic<LBM_D3Q19>(9) &&
+                  row_isotropic<LBM_D2Q9>(1) && row_isotropic<LBM_D2Q9>(2) && !row_isotropic<LBM_D2Q9>(7),
+              "isotropic rows");
 
 }  // namespace lbmk

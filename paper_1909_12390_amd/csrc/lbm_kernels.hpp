@@ -151,6 +151,16 @@ struct Pops<LBM_F64> {
   }
 };
 
+// n / d for d in [1/2, 2] (float64): hardware reciprocal, one Newton step on it
+// and one residual correction of the quotient -- far below the float32 rounding
+// the result goes through
+__device__ __forceinline__ double div_refined(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  const double q = n * r;
+  return fma(fma(-d, q, n), r, q);
+}
+
 // float32 -> storage type of an offset (float16: round to nearest even)
 template <typename H>
 __device__ __forceinline__ H enc_offset(float v) {
@@ -194,7 +204,7 @@ __device__ __forceinline__ float encode_offsets(const float* v, double mass, W w
     if constexpr (MIX) S += (double)w_plus(w(a), (float)r[a], one);
     else S += (double)(w(a) + (float)r[a]);
   }
-  return S >= 0.5 ? (float)(mass / S) : b0;
+  return S >= 0.5 ? (float)div_refined(mass, S) : b0;
 }
 
 // Component-interleaved offsets: the offsets of every component of one direction
@@ -487,7 +497,11 @@ __device__ __forceinline__ R feq(int a, R rho, R ux, R uy, R uz, R uu) {
 //   Guo : w[3(e - u).F + 9 (e.u)(e.F)]  -> even w(9 (e.u)(e.F) - 3 u.F), odd 3 w e.F,
 //   EDM : feq(u + du) - feq(u) = w rs [3 e.du + 9/2 (e.du)(2 e.u + e.du) - 3/2 du.(2u + du)]
 //         -> even w rs (9/2 (e.du)(2 e.u + e.du) - 3/2 du.(2u + du)), odd 3 w rs e.du;
-// MRT even rows act on d_a + d_opp, odd rows on d_a - d_opp.
+// MRT even rows act on d_a + d_opp, odd rows on d_a - d_opp.  With EDM the rows
+// take the raw pair sums of f and subtract the equilibrium's moments, quadratic in
+// u with compile-time coefficients (feq(u) is never formed per velocity); rows
+// whose entries depend on |e_a|^2 alone (e, epsilon) are taken on the speed-class
+// sums and relaxed back onto the classes.
 template <int LAT, typename R, int COLL, int FORC, typename Sink>
 __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R rs, const R* u3, const R* F3,
                                                Sink sink) {
@@ -536,97 +550,132 @@ __device__ __forceinline__ void collide_values(const KParams& P, const R* f, R r
       fo[b] = f[b] - om * (f[b] - (Ev - Od)) + gpre * (sE - sO);
     });
   } else {
-    const R h = (FORC == LBM_GUO) ? (R)0.5 : (R)0;
-    const R g1 = (R)1 - h;
-    R d0, acc0 = 0;
-    // XE, XO: even / odd parts of feq + (1 - h) src per pair (X0: the rest velocity)
-    R S[NP], D[NP], XE[NP], XO[NP], accE[NP], accO[NP], X0;
+    // Z0, ZE[p], ZO[p]: rest, even and odd pair values whose row projections, plus
+    // moff(k), are the moments of the deviation d; X0, XE[p], XO[p]: the state the
+    // relaxed deviations are added to (feq + (1 - h) src)
+    R Z0, X0, ZE[NP], ZO[NP], XE[NP], XO[NP];
     if constexpr (FORC == LBM_EDM) {
-      // h = 0, and feq(u) + [feq(u + du) - feq(u)] is feq(u + du): formed directly
-      // (fewer operations than the source, no difference taken)
+      // h = 0, d = f - feq(u): only d's moments enter, the raw moments of f minus
+      // those of feq(u) (moff); feq(u) + [feq(u + du) - feq(u)] = feq(u + du) is
+      // formed directly
       const R vx = ux + Fx, vy = uy + Fy, vz = uz + Fz;
       const R basev = (R)1 - (R)1.5 * (vx * vx + vy * vy + vz * vz);
-      auto eq2 = [&](auto A, R& Ev, R& Od, R& Xv, R& Yv) {   // feq(u) and feq(u + du), even / odd
-        constexpr int a = decltype(A)::value;
-        constexpr R cx = V::cx(a), cy = V::cy(a), cz = V::cz(a);
-        const R wr = (R)V::w(a) * rs;
-        const R eu = cx * ux + cy * uy + cz * uz;
-        const R ev = cx * vx + cy * vy + cz * vz;
-        Ev = wr * (base1 + (R)4.5 * eu * eu);
-        Od = (R)3 * wr * eu;
-        Xv = wr * (basev + (R)4.5 * ev * ev);
-        Yv = (R)3 * wr * ev;
-      };
-      {
-        R Ev, Od, Xv, Yv;
-        eq2(std::integral_constant<int, 0>{}, Ev, Od, Xv, Yv);
-        d0 = f[0] - Ev;
-        X0 = Xv;
-      }
+      Z0 = f[0];
+      X0 = (R)V::w(0) * rs * basev;
       static_for<0, NP>([&](auto Pp) {
         constexpr int p = decltype(Pp)::value;
         constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
-        R Ev, Od, Xv, Yv;
-        eq2(std::integral_constant<int, a>{}, Ev, Od, Xv, Yv);
-        S[p] = (f[a] + f[b]) - (R)2 * Ev;   // d_a + d_b
-        D[p] = (f[a] - f[b]) - (R)2 * Od;   // d_a - d_b
-        XE[p] = Xv;
-        XO[p] = Yv;
-        accE[p] = 0;
-        accO[p] = 0;
+        constexpr R cx = V::cx(a), cy = V::cy(a), cz = V::cz(a);
+        const R wr = (R)V::w(a) * rs;
+        const R ev = cx * vx + cy * vy + cz * vz;
+        ZE[p] = f[a] + f[b];
+        ZO[p] = f[a] - f[b];
+        XE[p] = wr * (basev + (R)4.5 * ev * ev);
+        XO[p] = (R)3 * wr * ev;
       });
     } else {
-      {
-        R Ev, Od, sE, sO;
-        parts(std::integral_constant<int, 0>{}, Ev, Od, sE, sO);
-        d0 = f[0] - Ev + h * sE;
-        X0 = Ev + g1 * sE;
-      }
+      const R h = (R)0.5, g1 = (R)0.5;
+      R Ev, Od, sE, sO;
+      parts(std::integral_constant<int, 0>{}, Ev, Od, sE, sO);
+      Z0 = f[0] - Ev + h * sE;
+      X0 = Ev + g1 * sE;
       static_for<0, NP>([&](auto Pp) {
         constexpr int p = decltype(Pp)::value;
         constexpr int a = V::pair_first(p), b = V::opp(V::pair_first(p));
         R Ev, Od, sE, sO;
         parts(std::integral_constant<int, a>{}, Ev, Od, sE, sO);
-        S[p] = (f[a] + f[b]) - (R)2 * Ev + (R)2 * h * sE;   // d_a + d_b
-        D[p] = (f[a] - f[b]) - (R)2 * Od + (R)2 * h * sO;   // d_a - d_b
+        ZE[p] = (f[a] + f[b]) - (R)2 * Ev + (R)2 * h * sE;   // d_a + d_b
+        ZO[p] = (f[a] - f[b]) - (R)2 * Od + (R)2 * h * sO;   // d_a - d_b
         XE[p] = Ev + g1 * sE;                               // feq + (1 - h) src
         XO[p] = Od + g1 * sO;
-        accE[p] = 0;
-        accO[p] = 0;
       });
     }
+    // EDM: minus row k's moment of feq(u), rs times a quadratic in u (eq_c0/1/2)
+    auto moff = [&](auto K) -> R {
+      constexpr int k = decltype(K)::value;
+      if constexpr (FORC == LBM_EDM) {
+        const R uv[3] = {ux, uy, uz};
+        R m = (R)eq_c0<LAT>(k);
+        static_for<0, V::D>([&](auto I) {
+          constexpr int ii = decltype(I)::value;
+          if constexpr (eq_c1<LAT>(k, ii) != 0.0) m += (R)eq_c1<LAT>(k, ii) * uv[ii];
+          static_for<ii, V::D>([&](auto J) {
+            constexpr int jj = decltype(J)::value;
+            constexpr double c2 = eq_c2<LAT>(k, ii, jj);
+            if constexpr (c2 > 1e-12 || c2 < -1e-12) m += (R)c2 * (uv[ii] * uv[jj]);
+          });
+        });
+        return -rs * m;
+      } else {
+        return (R)0;
+      }
+    };
+    // skip rows relaxed at rate 1 (a uniform branch on a scalar bit mask); in
+    // float64 the kernel streams at HBM speed and the branches cost more than the
+    // skipped rows
+    auto active = [&](int k) { return std::is_same<R, double>::value || ((P.mrt_rows >> k) & 1u); };
+    // isotropic even rows (e, epsilon): projections of the speed-class sums of ZE,
+    // relaxed onto the classes (the first contributions to the accumulators)
+    R Zc1 = 0, Zc2 = 0;
+    static_for<0, NP>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      if constexpr (speed2<LAT>(V::pair_first(p)) == 1) Zc1 += ZE[p];
+      else Zc2 += ZE[p];
+    });
+    R acc0 = 0, inc1 = 0, inc2 = 0;
     static_for<1, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      const double ck = P.mrt_c[k];
-      // skip rows relaxed at rate 1 (a uniform branch on a scalar bit mask); in
-      // float64 the kernel streams at HBM speed and the branches cost more than
-      // the skipped rows
-      if (std::is_same<R, double>::value || ((P.mrt_rows >> k) & 1u)) {
-        R m = 0;
-        if constexpr (!row_odd<LAT>(k)) {
-          if constexpr (V::mrow(k, 0) != 0.0) m += (R)V::mrow(k, 0) * d0;
+      if constexpr (row_isotropic<LAT>(k) && !row_odd<LAT>(k)) {
+        if (active(k)) {
+          constexpr double c0 = mrow_class<LAT>(k, 0), c1 = mrow_class<LAT>(k, 1), c2 = mrow_class<LAT>(k, 2);
+          R m = moff(K);
+          if constexpr (c0 != 0.0) m += (R)c0 * Z0;
+          if constexpr (c1 != 0.0) m += (R)c1 * Zc1;
+          if constexpr (c2 != 0.0) m += (R)c2 * Zc2;
+          m *= (R)P.mrt_c[k];
+          if constexpr (c0 != 0.0) acc0 += (R)c0 * m;
+          if constexpr (c1 != 0.0) inc1 += (R)c1 * m;
+          if constexpr (c2 != 0.0) inc2 += (R)c2 * m;
+        }
+      }
+    });
+    R accE[NP], accO[NP];
+    static_for<0, NP>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      accE[p] = speed2<LAT>(V::pair_first(p)) == 1 ? inc1 : inc2;
+      accO[p] = 0;
+    });
+    // the other rows, one at a time: m = (row . Z + moff) c_k, back-projected
+    static_for<1, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      if constexpr (!(row_isotropic<LAT>(k) && !row_odd<LAT>(k))) {
+        if (active(k)) {
+          R m = moff(K);
+          if constexpr (!row_odd<LAT>(k)) {
+            if constexpr (V::mrow(k, 0) != 0.0) m += (R)V::mrow(k, 0) * Z0;
+            static_for<0, NP>([&](auto Pp) {
+              constexpr int p = decltype(Pp)::value;
+              constexpr double mk = V::mrow(k, V::pair_first(p));
+              if constexpr (mk != 0.0) m += (R)mk * ZE[p];
+            });
+          } else {
+            static_for<0, NP>([&](auto Pp) {
+              constexpr int p = decltype(Pp)::value;
+              constexpr double mk = V::mrow(k, V::pair_first(p));
+              if constexpr (mk != 0.0) m += (R)mk * ZO[p];
+            });
+          }
+          m *= (R)P.mrt_c[k];
+          if constexpr (!row_odd<LAT>(k) && V::mrow(k, 0) != 0.0) acc0 += (R)V::mrow(k, 0) * m;
           static_for<0, NP>([&](auto Pp) {
             constexpr int p = decltype(Pp)::value;
             constexpr double mk = V::mrow(k, V::pair_first(p));
-            if constexpr (mk != 0.0) m += (R)mk * S[p];
-          });
-        } else {
-          static_for<0, NP>([&](auto Pp) {
-            constexpr int p = decltype(Pp)::value;
-            constexpr double mk = V::mrow(k, V::pair_first(p));
-            if constexpr (mk != 0.0) m += (R)mk * D[p];
+            if constexpr (mk != 0.0) {
+              if constexpr (row_odd<LAT>(k)) accO[p] += (R)mk * m;
+              else accE[p] += (R)mk * m;
+            }
           });
         }
-        m *= (R)ck;
-        if constexpr (!row_odd<LAT>(k) && V::mrow(k, 0) != 0.0) acc0 += (R)V::mrow(k, 0) * m;
-        static_for<0, NP>([&](auto Pp) {
-          constexpr int p = decltype(Pp)::value;
-          constexpr double mk = V::mrow(k, V::pair_first(p));
-          if constexpr (mk != 0.0) {
-            if constexpr (row_odd<LAT>(k)) accO[p] += (R)mk * m;
-            else accE[p] += (R)mk * m;
-          }
-        });
       }
     });
     fo[0] = X0 + acc0;
