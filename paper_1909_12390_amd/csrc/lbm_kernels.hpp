@@ -739,6 +739,25 @@ __device__ __forceinline__ float lane_from_right(float v, float fill) {
                                                                __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
 }
 
+__device__ __forceinline__ double lane_from_left(double v, double fill) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned long long g = __builtin_bit_cast(unsigned long long, fill);
+  const float lo = lane_from_left(__builtin_bit_cast(float, (unsigned)u), __builtin_bit_cast(float, (unsigned)g));
+  const float hi = lane_from_left(__builtin_bit_cast(float, (unsigned)(u >> 32)),
+                                  __builtin_bit_cast(float, (unsigned)(g >> 32)));
+  return __builtin_bit_cast(double, (unsigned long long)__builtin_bit_cast(unsigned, lo) |
+                                        ((unsigned long long)__builtin_bit_cast(unsigned, hi) << 32));
+}
+__device__ __forceinline__ double lane_from_right(double v, double fill) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned long long g = __builtin_bit_cast(unsigned long long, fill);
+  const float lo = lane_from_right(__builtin_bit_cast(float, (unsigned)u), __builtin_bit_cast(float, (unsigned)g));
+  const float hi = lane_from_right(__builtin_bit_cast(float, (unsigned)(u >> 32)),
+                                   __builtin_bit_cast(float, (unsigned)(g >> 32)));
+  return __builtin_bit_cast(double, (unsigned long long)__builtin_bit_cast(unsigned, lo) |
+                                        ((unsigned long long)__builtin_bit_cast(unsigned, hi) << 32));
+}
+
 // Source rows of a pull: (dy, dz) = (-c_y, -c_z) as index (dy + 1) + 3 (dz + 1).
 template <int LAT>
 __host__ __device__ constexpr int pull_row(int a) {
@@ -1206,13 +1225,28 @@ __global__ __launch_bounds__(64 * kIlvWaves) void k_collide_ilv(KParams P, Pops<
   const unsigned own = c.row(0, 0) + c.x(0);
   const unsigned bits = P.bb ? P.bb[own] : 0u;
   const bool valid = in_row && !(bits >> kSolidBit);
-  // psi at the cell and its neighbours first: their latency overlaps the pulls'
+  // psi at the cell and its neighbours first (their latency overlaps the pulls'):
+  // one load per neighbour row (dy, dz), the x-neighbours by lane shifts, the
+  // values past the segment's ends from scalar loads (lanes past a short row's end
+  // hold x = 0, the periodic neighbour of the row's last cell)
   const rsrc_t psr = make_rsrc(psi, (unsigned)P.cells * 8u);
-  double pn[Q];
-  static_for<0, Q>([&](auto A) {
-    constexpr int a = decltype(A)::value;
-    pn[a] = bload(psr, c.x(V::cx(a)) * 8u, c.row(V::cy(a), V::cz(a)) * 8u, 0.0);
-  });
+  double prow[9], pfl[9], pfr[9];
+  {
+    const unsigned nx = P.nx;
+    const unsigned xl = c.x0 == 0 ? nx - 1 : c.x0 - 1;
+    const unsigned xr = c.x0 + 64u < nx ? c.x0 + 64u : 0u;
+    static_for<0, 9>([&](auto Rr) {
+      constexpr int r = decltype(Rr)::value;
+      if constexpr (row_used<LAT>(r)) {
+        const unsigned ro = c.row(r % 3 - 1, r / 3 - 1);
+        prow[r] = bload(psr, c.x(0) * 8u, ro * 8u, 0.0);
+        if constexpr (row_shifted<LAT>(r)) {
+          pfl[r] = psi[ro + xl];
+          pfr[r] = psi[ro + xr];
+        }
+      }
+    });
+  }
   const IB Bi(in, P.cells);
   float f[NC][Q];
   if (P.bb) {
@@ -1229,6 +1263,15 @@ __global__ __launch_bounds__(64 * kIlvWaves) void k_collide_ilv(KParams P, Pops<
   } else {
     ilv_pull_row<LAT, NC, H>(in, Bi, c, (unsigned)P.nx, f);   // every lane pulls
   }
+  // psi at x + e_a: row (c_y, c_z) (the pull row of the opposite velocity), shifted by c_x
+  double pn[Q];
+  static_for<0, Q>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    constexpr int r = pull_row<LAT>(V::opp(a));
+    if constexpr (V::cx(a) == 0) pn[a] = prow[r];
+    else if constexpr (V::cx(a) > 0) pn[a] = lane_from_right(prow[r], pfr[r]);   // x + 1
+    else pn[a] = lane_from_left(prow[r], pfl[r]);                                // x - 1
+  });
   if (!in_row) return;
   // total force of Eq. (coupledMCforce) (float64), summed over opposite pairs:
   // w psi_a (b psi + h psi_a) - w psi_b (b psi + h psi_b) = w (psi_a - psi_b) (b psi + h (psi_a + psi_b))
