@@ -18,6 +18,13 @@ Readings taken where the printed text is garbled (each one pinned by a test):
 Pins (tests/test_oracle_thermo.py): the Maxwell densities quoted in Sec. 4.1,
 Table 2 (Sec. 4.2) with Table 1 data, the Gibbs-difference identity, the
 Gibbs-Duhem/finite-difference check of ln(phi), the EOS-vs-cubic identity.
+
+Parity unpinned (no value the paper prints and no identity separates them from a
+plausible mistake): the omega > 0.49 branch of m(omega) (Table 1's components and
+every synthetic workload lie below 0.49; its test only retypes the formula), and
+the sign of the interaction factor (1 - zeta_ij) for zeta_ij != 0 (Table 2 has
+zeta = 0; the ln(phi) identity holds for either sign, since the pressure and
+ln(phi) share the mixing rule).
 """
 from __future__ import annotations
 
