@@ -102,10 +102,13 @@ typedef struct {
   double tau;                /* relaxation time, > 0.5 (Sec. 2.1)               */
   double G;                  /* interaction strength, < 0 (Sec. 4.1: only its sign matters) */
   double beta;               /* blending parameter of Eq. coupledMCforce        */
-  double gamma[LBM_MAX_NC];  /* volatility coefficients, Eq. distributionforce, each in (0, 1] */
+  double gamma[LBM_MAX_NC];  /* volatility coefficients, Eq. distributionforce, each in (0, 1];
+                                all zero: taken from lbm_flash at (T, p_flash, z_flash) */
   double mrt_s[LBM_MAX_Q];   /* MRT: relaxation rate of each moment row (rows of the orthogonal
                                 Lallemand-Luo D2Q9 / d'Humieres D3Q19 bases, in their order) */
   double accel[3];           /* uniform body acceleration g; adds rbar_sigma g to F_sigma */
+  double p_flash;            /* gamma all zero: pressure and overall composition of the   */
+  double z_flash[LBM_MAX_NC];/* two-phase flash whose gamma (Eq. gamma) is used           */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -140,7 +143,11 @@ lbm_status lbm_workspace_bytes(const lbm_mixture* mix, const lbm_params* prm, si
  * velocity u0 (dev, float64 [D][cells], or NULL for rest).  All work is enqueued
  * on `stream` (a hipStream_t; NULL = default stream).  Host-side rejections:
  * nc outside 1..4, tau <= 0.5, G >= 0, gamma outside (0, 1], non-positive a, b, M,
- * box sides < 1, nz != 1 for D2Q9, unknown enums -> LBM_ERR_ARG. */
+ * box sides < 1, nz != 1 for D2Q9, unknown enums -> LBM_ERR_ARG.  With gamma all
+ * zero the flash at (T, p_flash, z_flash) supplies it (Sec. 3.1 Eq. gamma on the
+ * phases of Sec. 3.2); its failures (LBM_ERR_SINGLEPHASE, LBM_ERR_NOCONVERGE, or
+ * LBM_ERR_ARG for a bad p_flash / z_flash) are returned as they are.  For nc = 1
+ * gamma does not enter the split; pass 1. */
 lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, void* workspace_dev,
                     size_t workspace_bytes, const double* rho_bar0_dev, const double* u0_dev,
                     void* stream, lbm_ctx** out);

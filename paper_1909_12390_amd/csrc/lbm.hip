@@ -233,10 +233,29 @@ int launches_per_step(const lbm_ctx* c) {
   return 2 * ((np + c->slab - 1) / c->slab);
 }
 
+// A copy of prm whose gamma, when given as all zero, is the two-phase flash's at
+// (T, p_flash, z_flash): Eq. (gamma) on the phases of Sec. 3.2.
+lbm_status resolve_gamma(const lbm_mixture* mix, const lbm_params* prm, lbm_params* out) {
+  if (!mix || !prm) return lbm_fail(LBM_ERR_ARG, "mixture or params is NULL");
+  if (mix->nc < 1 || mix->nc > LBM_MAX_NC) return lbm_fail(LBM_ERR_ARG, "nc must be in 1..4");
+  *out = *prm;
+  for (int i = 0; i < mix->nc; ++i)
+    if (prm->gamma[i] != 0.0) return LBM_OK;
+  lbm_flash_result fr;
+  const lbm_status st = lbm_flash(mix, prm->T, prm->p_flash, prm->z_flash, &fr);
+  if (st != LBM_OK) return st;
+  for (int i = 0; i < mix->nc; ++i) out->gamma[i] = fr.gamma[i];
+  return LBM_OK;
+}
+
 }  // namespace
 
-extern "C" lbm_status lbm_workspace_bytes(const lbm_mixture* mix, const lbm_params* prm, size_t* bytes) {
-  lbm_status st = validate(mix, prm);
+extern "C" lbm_status lbm_workspace_bytes(const lbm_mixture* mix, const lbm_params* prm_in, size_t* bytes) {
+  lbm_params resolved;
+  lbm_status st = resolve_gamma(mix, prm_in, &resolved);
+  if (st != LBM_OK) return st;
+  const lbm_params* prm = &resolved;
+  st = validate(mix, prm);
   if (st != LBM_OK) return st;
   if (!bytes) return lbm_fail(LBM_ERR_ARG, "bytes is NULL");
   Layout L;
@@ -261,11 +280,15 @@ lbm_status noalloc_scratch_address(int dev) {
 }
 }  // namespace
 
-extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm, void* ws, size_t ws_bytes,
+extern "C" lbm_status lbm_init(const lbm_mixture* mix, const lbm_params* prm_in, void* ws, size_t ws_bytes,
                                const double* rho0, const double* u0, void* stream, lbm_ctx** out) {
   if (!out) return lbm_fail(LBM_ERR_ARG, "out is NULL");
   *out = nullptr;
-  lbm_status st = validate(mix, prm);
+  lbm_params resolved;
+  lbm_status st = resolve_gamma(mix, prm_in, &resolved);
+  if (st != LBM_OK) return st;
+  const lbm_params* prm = &resolved;
+  st = validate(mix, prm);
   if (st != LBM_OK) return st;
   int dev = -1;
   st = hip_check(hipGetDevice(&dev), "hipGetDevice");

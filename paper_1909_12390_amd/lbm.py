@@ -57,7 +57,8 @@ class LbmParams(ctypes.Structure):
     _fields_ = [("lattice", c_int), ("nx", c_int), ("ny", c_int), ("nz", c_int), ("collision", c_int),
                 ("forcing", c_int), ("storage", c_int), ("schedule", c_int), ("slab_planes", c_int), ("T", c_double),
                 ("tau", c_double), ("G", c_double), ("beta", c_double), ("gamma", c_double * MAX_NC),
-                ("mrt_s", c_double * MAX_Q), ("accel", c_double * 3)]
+                ("mrt_s", c_double * MAX_Q), ("accel", c_double * 3), ("p_flash", c_double),
+                ("z_flash", c_double * MAX_NC)]
 
 
 class LbmFlashResult(ctypes.Structure):
@@ -271,7 +272,9 @@ class LibThermo:
 # ---------------------------------------------------------------------------
 
 def params_struct(lattice, shape, T, tau, beta, gamma, collision="bgk", forcing="guo", storage="f64",
-                  schedule="two_pass", mrt_s=None, accel=None, G=-1.0, slab_planes=0) -> LbmParams:
+                  schedule="two_pass", mrt_s=None, accel=None, G=-1.0, slab_planes=0, p_flash=None,
+                  z_flash=None) -> LbmParams:
+    """gamma None: left zero, so that lbm_init takes it from the flash at (T, p_flash, z_flash)."""
     p = LbmParams()
     p.lattice = LATTICES[lattice]
     if lattice == "D2Q9":
@@ -289,8 +292,15 @@ def params_struct(lattice, shape, T, tau, beta, gamma, collision="bgk", forcing=
     p.tau = float(tau)
     p.G = float(G)
     p.beta = float(beta)
-    for i, g in enumerate(gamma):
-        p.gamma[i] = float(g)
+    if gamma is None:
+        if p_flash is None or z_flash is None:
+            raise ValueError("gamma=None needs p_flash and z_flash (the flash that supplies gamma)")
+        p.p_flash = float(p_flash)
+        for i, z in enumerate(z_flash):
+            p.z_flash[i] = float(z)
+    else:
+        for i, g in enumerate(gamma):
+            p.gamma[i] = float(g)
     if mrt_s is not None:
         for k, s in enumerate(mrt_s):
             p.mrt_s[k] = float(s)
@@ -305,6 +315,8 @@ class LbmContext:
 
     rho0: initial cell-volume densities (nc, *shape), float64 (NumPy or torch).
     u0  : optional initial velocity (D, *shape).
+    gamma: volatility coefficients, or None to have lbm_init take them from the
+    two-phase flash at (T, p_flash, z_flash) (Eq. gamma).
     solid, psi_wall: optional solid-cell mask (*shape, bool) and the wetting psi of
     the walls (lbm_set_solid), applied right after the initial state.
     graph_steps > 0: step() replays HIP graphs of that many steps (lbm_set_graph_steps);
@@ -314,7 +326,8 @@ class LbmContext:
 
     def __init__(self, mix: dict, lattice: str, shape, T, tau, beta, gamma, rho0, u0=None,
                  collision="bgk", forcing="guo", storage="f64", schedule="two_pass", mrt_s=None,
-                 accel=None, G=-1.0, slab_planes=0, device="cuda", solid=None, psi_wall=0.0, graph_steps=0):
+                 accel=None, G=-1.0, slab_planes=0, device="cuda", solid=None, psi_wall=0.0, graph_steps=0,
+                 p_flash=None, z_flash=None):
         import torch
         self.torch = torch
         self.lattice = lattice
@@ -325,7 +338,7 @@ class LbmContext:
         self.cells = int(np.prod(self.shape))
         self._mix = mixture_struct(mix)
         self._prm = params_struct(lattice, self.shape, T, tau, beta, gamma, collision, forcing, storage,
-                                  schedule, mrt_s, accel, G, slab_planes)
+                                  schedule, mrt_s, accel, G, slab_planes, p_flash, z_flash)
         nbytes = c_size_t(0)
         _check(lib().lbm_workspace_bytes(ctypes.byref(self._mix), ctypes.byref(self._prm), ctypes.byref(nbytes)))
         self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=device)

@@ -198,3 +198,26 @@ def test_blocked_schedule_equals_two_pass(lattice, shape, slab, storage, schedul
     a.check()
     b.check()
     assert np.array_equal(fa, fb)
+
+
+def test_gamma_from_the_flash_at_init():
+    # gamma left to lbm_init: the library's flash at (T, p*, z) (Eq. gamma) gives the
+    # same run as passing that flash's gamma explicitly, bitwise; it agrees with the
+    # oracle's flash
+    print("case gamma from the flash at init", flush=True)
+    from cases import BACKEND
+    from paper_1909_12390_amd import inputs
+    lbm = _lbm()
+    mix, T, z, p, fl = inputs.pick_state(inputs.rng_for(777, 0), BACKEND, 3, 0.7, 0.95, 0.05, {})
+    lib_fl = lbm.lbm_flash(mix, T, p, z)
+    assert np.allclose(lib_fl.gamma[:3], fl.gamma, rtol=1e-9)
+    shape = (40, 52)
+    rho0 = inputs.drop_profile(shape, 10.0, 4.0, fl.rbar_l, fl.rbar_v)
+    runs = []
+    for gamma, kw in ((list(lib_fl.gamma[:3]), {}), (None, {"p_flash": p, "z_flash": z})):
+        ctx = lbm.LbmContext(mix, "D2Q9", shape, T, 0.8, 1.3, gamma, rho0, collision="bgk", forcing="edm",
+                             storage="f64", **kw)
+        ctx.step(20)
+        runs.append(ctx.get_populations().cpu().numpy())
+        ctx.check()
+    assert np.array_equal(runs[0], runs[1])

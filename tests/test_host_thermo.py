@@ -87,3 +87,30 @@ def test_c3_four_component_state_agrees():
     assert np.allclose(a.rbar_l, b.rbar_l, rtol=1e-9)
     mix = to_mixture(a.mix)
     assert int(np.sum(a.T > mix.Tc)) == 1          # exactly one supercritical component
+
+
+def _workspace_bytes(d, prm):
+    import ctypes
+    n = ctypes.c_size_t(0)
+    mix = lbm.mixture_struct(d)
+    lbm._check(lbm.lib().lbm_workspace_bytes(ctypes.byref(mix), ctypes.byref(prm), ctypes.byref(n)))
+    return int(n.value)
+
+
+def test_gamma_left_zero_is_taken_from_the_flash():
+    # host part of lbm_init / lbm_workspace_bytes: gamma all zero -> the two-phase
+    # flash at (T, p_flash, z_flash) supplies it (Sec. 3.1 Eq. gamma); a pressure
+    # outside the envelope is the flash's single-phase error
+    d, _ = c3_nc5_dict()
+    T, p, z = 666.06, 200.0, [0.4, 0.6]
+    fl = lbm.lbm_flash(d, T, p, z)
+    explicit = lbm.params_struct("D2Q9", (4, 6), T, 0.8, 1.945, fl.gamma)
+    implicit = lbm.params_struct("D2Q9", (4, 6), T, 0.8, 1.945, None, p_flash=p, z_flash=z)
+    assert list(implicit.gamma)[:2] == [0.0, 0.0]
+    assert _workspace_bytes(d, implicit) == _workspace_bytes(d, explicit) > 0
+    bad = lbm.params_struct("D2Q9", (4, 6), T, 0.8, 1.945, None, p_flash=400.0, z_flash=z)
+    with pytest.raises(lbm.LbmError) as e:
+        _workspace_bytes(d, bad)
+    assert e.value.code == lbm.LBM_ERR_SINGLEPHASE
+    with pytest.raises(ValueError):
+        lbm.params_struct("D2Q9", (4, 6), T, 0.8, 1.945, None)
