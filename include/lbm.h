@@ -60,7 +60,11 @@ enum { LBM_GUO = 0, LBM_EDM = 1 };
  * b0 = sum_a |f_a| carrying the sign of the cell's mass of the component, and b
  * rescaled after rounding so that the decoded populations
  * sum to the component's mass; decode f_a = b (w_a + r_a).  Collision in float32;
- * EOS, psi, the force stencil and the masses stay float64. */
+ * EOS, psi, the force stencil and the masses stay float64.  In the workspace the
+ * offset formats keep the components of a cell side by side (offsets
+ * [Q][cells][nc], bases [cells][nc]), float64 keeps [nc][Q][cells];
+ * lbm_get_populations / lbm_set_populations convert from / to the float64
+ * [nc][Q][cells] layout of the conventions above. */
 enum { LBM_F64 = 0, LBM_F32_OFS = 1, LBM_F16_OFS = 2 };
 /* Kernel schedule of one step (identical results).
  * TWO_PASS: a density/EOS/psi pass over the whole box, then a collide pass.

@@ -96,15 +96,15 @@ __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, _
 }
 
 // ---------------------------------------------------------------------------
-// Population storage.  Layout [nc][Q][cells] for the per-direction planes; the
-// offset formats add a float base [nc][cells] per cell and component:
-//   stored value of direction a at cell y (the post-collision population that
-//   streams to y + e_a) = base(y) * (w_a + r_a(y)).
-// comp(s) returns a view of component s; get(a, idx) decodes direction a at
-// cell idx, put_all stores the Q post-collision values (and the base) of a cell.
-// Both offset formats rescale the stored base after rounding the offsets so that
-// the cell's decoded mass equals its mass before encoding (put_all); the caller
-// passes that mass summed in float64.
+// Population storage.  float64: planes [nc][Q][cells], the stored value of
+// direction a at cell y being the post-collision population that streams to
+// y + e_a.  The offset formats (IlvPops below) store base(y) (w_a + r_a(y)) with
+// the components of a cell side by side.  comp(s) returns a view of component s;
+// get(a, idx) decodes direction a at cell idx, put_all stores the Q
+// post-collision values (and, for the offset formats, the base) of a cell.  The
+// offset formats rescale the stored base after rounding the offsets so that the
+// cell's decoded mass equals its mass before encoding (encode_offsets); the
+// caller passes that mass summed in float64.
 // ---------------------------------------------------------------------------
 template <int ST>
 struct Pops;
