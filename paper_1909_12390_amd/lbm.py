@@ -243,6 +243,11 @@ def stream_copy(dst, src, nbytes: int, grid: int = 0, stream=None):
     """lbm_stream_copy between two device tensors (the measured bandwidth ceiling);
     enqueued on `stream` (a torch stream; None = the current one)."""
     import torch
+    for name, t in (("dst", dst), ("src", src)):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"stream_copy: {name} must be a contiguous device tensor")
+        if int(nbytes) > t.numel() * t.element_size():
+            raise ValueError(f"stream_copy: {nbytes} bytes exceed {name} ({t.numel() * t.element_size()} bytes)")
     st = torch.cuda.current_stream() if stream is None else stream
     _check(lib().lbm_stream_copy(c_void_p(dst.data_ptr()), c_void_p(src.data_ptr()), int(nbytes), int(grid),
                                  c_void_p(st.cuda_stream)))
