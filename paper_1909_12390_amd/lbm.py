@@ -575,8 +575,11 @@ class LbmBatch:
                 masks.append(m)
                 arr[i].solid = m.ctypes.data
                 arr[i].psi_wall = float(bx.get("psi_wall", 0.0))
+            nc_b = len(bx["mix"]["a"])
+            if tuple(np.shape(bx["rho0"])) != (nc_b,) + shape:
+                raise ValueError(f"box {i}: rho0 must have shape {(nc_b,) + shape}, got {tuple(np.shape(bx['rho0']))}")
             self.shapes.append(shape)
-            self.ncs.append(len(bx["mix"]["a"]))
+            self.ncs.append(nc_b)
         self._boxes = arr
         prm = LbmBatchParams()
         prm.lattice = LATTICES[lattice]
@@ -602,7 +605,8 @@ class LbmBatch:
         self.workspace = torch.empty(int(ws.value) + 256, dtype=torch.uint8, device=device)
         wsp = (self.workspace.data_ptr() + 255) // 256 * 256
         rho0 = torch.cat([torch.as_tensor(bx["rho0"], dtype=torch.float64).reshape(-1) for bx in boxes]).to(device)
-        assert rho0.numel() == self.field_elems
+        if rho0.numel() != self.field_elems:
+            raise ValueError(f"initial fields hold {rho0.numel()} values, the batch layout {self.field_elems}")
         self.stream.wait_stream(cur)
         ctx = c_void_p()
         _check(lib().lbm_batch_init(arr, n, ctypes.byref(prm), c_void_p(wsp), c_size_t(int(ws.value)),

@@ -152,3 +152,15 @@ def test_context_calls_reject_null_handles():
     assert L.lbm_set_graph_steps(None, 4) == lbm.LBM_ERR_ARG
     assert L.lbm_set_gamma(None, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == lbm.LBM_ERR_ARG
     assert L.lbm_step(None, 1) == lbm.LBM_ERR_ARG
+
+
+def test_batch_binding_checks_initial_field_shapes():
+    """A box whose rho0 does not have (nc_b, *shape) is refused by the binding before
+    anything reaches the library or the device."""
+    mix = _mix()
+    nc = len(mix["a"])
+    good = {"mix": mix, "shape": (8, 16), "T": 0.07, "tau": 0.8, "beta": 1.3, "gamma": [0.5] * nc,
+            "rho0": np.ones((nc, 8, 16))}
+    bad = dict(good, rho0=np.ones((nc, 16, 8)))
+    with pytest.raises(ValueError, match="box 1: rho0"):
+        lbm.LbmBatch([good, bad], "D2Q9", storage="f16")
