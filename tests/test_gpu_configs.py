@@ -4,7 +4,7 @@ configurations bench.py times.
 * C1 (binary D2Q9 64^2 drop, float64, BGK + exact-difference forcing) and C2
   (ternary D2Q9 256^2 slab, MRT) are small enough for the oracle to step the whole
   field: element by element, float64 to 1e-12 after 1 and 10 steps, float32 offset
-  storage to the reduced-precision budget.
+  storage to the reduced-precision budget; C1 also over its full 1000 steps.
 * C3 (four-component D3Q19 128^3 drop, MRT + exact-difference forcing): every cell
   after one step from the GPU's own state, against the oracle stepping the whole
   field; float64 to 1e-12, the benchmarked float16 two-pass configuration to 1e-4
@@ -69,6 +69,24 @@ def test_small_configs_whole_field(which, storage, tol1, tol10):
     ctx.check()
     print(f"  1 step {e1:.2e}  10 steps {e10:.2e}", flush=True)
     assert e1 < tol1 and e10 < tol10, (e1, e10)
+
+
+def test_c1_full_length_whole_field():
+    """C1 over its whole length (1000 steps) against the oracle stepping the same
+    field (about 2 s on the host): float64, every population of every cell."""
+    cfg = inputs.config_c1(BACKEND)
+    print(f"case C1 {cfg.shape} nc={cfg.nc} {cfg.collision}+{cfg.forcing} f64, {cfg.steps} steps", flush=True)
+    ctx = context(cfg, "f64")
+    m = to_mixture(cfg.mix)
+    f = olbm.init_populations(cfg.rho0, LAT[cfg.lattice])
+    prm = oracle_prm(cfg)
+    for _ in range(cfg.steps):
+        f = olbm.step(f, m, prm, LAT[cfg.lattice])
+    ctx.step(cfg.steps)
+    ctx.check()
+    e = rel_err(ctx.get_populations().cpu().numpy(), f)
+    print(f"  {cfg.steps} steps {e:.2e}", flush=True)
+    assert e < 1e-12, e
 
 
 def c3_state_pair(cfg, storage, solid=None):
