@@ -54,7 +54,12 @@ lbm_status batch_validate(const lbm_box* boxes, int nboxes, const lbm_batch_para
     if (m.nc < 1 || m.nc > LBM_MAX_NC) return lbm_fail(LBM_ERR_ARG, "box %d: nc must be in 1..4", i);
     if (B.nx < 1 || B.ny < 1 || B.nz < 1) return lbm_fail(LBM_ERR_ARG, "box %d: sides must be >= 1", i);
     if (prm->lattice == LBM_D2Q9 && B.nz != 1) return lbm_fail(LBM_ERR_ARG, "box %d: D2Q9 needs nz == 1", i);
-    if ((double)B.nx * B.ny * B.nz * Q * 8.0 >= 4294967295.0) return lbm_fail(LBM_ERR_ARG, "box %d too large", i);
+    // a box's population planes are addressed with 32-bit byte offsets: one
+    // component's planes (float64), all components' interleaved planes (offsets)
+    const double sb = prm->storage == LBM_F64 ? 8.0 : (prm->storage == LBM_F32_OFS ? 4.0 : 2.0);
+    const double span = (double)B.nx * B.ny * B.nz * Q * (prm->storage == LBM_F64 ? 8.0 : sb * m.nc);
+    if (span >= 4294967295.0)
+      return lbm_fail(LBM_ERR_ARG, "box %d too large: its population planes must stay below 4 GiB", i);
     if (!(B.tau > 0.5) || !(B.G < 0.0) || !(B.T > 0.0) || !std::isfinite(B.beta) || !(m.R > 0.0))
       return lbm_fail(LBM_ERR_ARG, "box %d: need tau > 0.5, G < 0, T > 0, finite beta, R > 0", i);
     if (B.solid && !(std::isfinite(B.psi_wall) && B.psi_wall >= 0.0))

@@ -76,23 +76,28 @@ def test_mrt_rates_checked():
     assert _bytes(collision="mrt", mrt_s=[1.0] * 8 + [2.5])[0] == lbm.LBM_ERR_ARG
 
 
+def _mix4():
+    return {"a": [2 / 49, 0.08, 0.05, 0.06], "b": [2 / 21, 0.15, 0.1, 0.12], "omega": [0.1, 0.2, 0.15, 0.25],
+            "M": [1.0, 1.6, 1.1, 1.3], "k": np.zeros((4, 4)).tolist(), "R": 1.0}
+
+
 def _batch_layout(nboxes=2, tile=0, grid=0, graph_steps=0, nc=2, lattice="D2Q9", shape=(8, 16), gamma=None,
-                  solid=None, psi_wall=0.0):
+                  solid=None, psi_wall=0.0, storage=2):
     n = nboxes
     arr = (lbm.LbmBox * max(n, 1))()
     for i in range(n):
-        m = _mix()
+        m = _mix() if nc == 2 else _mix4()
         arr[i].mix = lbm.mixture_struct(m)
         arr[i].nx, arr[i].ny, arr[i].nz = shape[1], shape[0], 1
         arr[i].T, arr[i].tau, arr[i].G, arr[i].beta = 0.06, 0.8, -1.0, 1.16
-        for k, g in enumerate(gamma if gamma is not None else [0.5, 1.0]):
+        for k, g in enumerate(gamma if gamma is not None else [0.5] * (nc - 1) + [1.0]):
             arr[i].gamma[k] = g
         if solid is not None and i == 0:
             arr[i].solid = solid.ctypes.data
             arr[i].psi_wall = psi_wall
     prm = lbm.LbmBatchParams()
     prm.lattice = lbm.LATTICES[lattice]
-    prm.collision, prm.forcing, prm.storage = 0, 1, 2
+    prm.collision, prm.forcing, prm.storage = 0, 1, storage
     prm.tile, prm.grid, prm.graph_steps = tile, grid, graph_steps
     ws, fe, pe = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
     code = lbm.lib().lbm_batch_layout(arr, n, ctypes.byref(prm), ctypes.byref(ws), ctypes.byref(fe),
@@ -164,3 +169,14 @@ def test_batch_binding_checks_initial_field_shapes():
     bad = dict(good, rho0=np.ones((nc, 16, 8)))
     with pytest.raises(ValueError, match="box 1: rho0"):
         lbm.LbmBatch([good, bad], "D2Q9", storage="f16")
+
+
+def test_batch_box_planes_past_4gib_refused():
+    """A box's planes are addressed with 32-bit byte offsets: float64 one component's
+    planes, the offset formats all components' interleaved planes. A box whose
+    float64 planes fit but whose four-component float32 offsets would not is
+    refused for float32 storage only."""
+    shape = (6000, 6000)            # 9 x 8 x 3.6e7 B = 2.6 GB; x 4 components x 4 B = 5.2 GB
+    assert _batch_layout(nboxes=1, nc=4, shape=shape, storage=lbm.STORAGES["f64"])[0] == lbm.LBM_OK
+    assert _batch_layout(nboxes=1, nc=4, shape=shape, storage=lbm.STORAGES["f16"])[0] == lbm.LBM_OK
+    assert _batch_layout(nboxes=1, nc=4, shape=shape, storage=lbm.STORAGES["f32"])[0] == lbm.LBM_ERR_ARG
