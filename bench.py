@@ -51,14 +51,19 @@ def b_alg_collide(nc: int, Q: int, storage: str) -> int:
     return b_alg(nc, Q, storage) - 8
 
 
+# the sources that define the single-box step kernels and their launches: a change
+# to any of them voids the stored counters (host-only code elsewhere does not)
+STEP_KERNEL_SOURCES = ("lattice.hpp", "lbm_kernels.hpp", "lbm_dispatch.hpp", "lbm_internal.hpp", "lbm_ctx.hpp",
+                       "lbm.hip", "lbm_d2q9.hip", "lbm_d3q19.hip")
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1909_12390_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
