@@ -59,22 +59,43 @@ extern "C" const char* lbm_last_error(void) { return g_err; }
 
 namespace lbmk {
 
-// sum of the per-block partials in a fixed order (one block)
+// sum of the per-block partials (total-major [K][nblocks], see block_partials) in a
+// fixed order, one block: thread t adds blocks t, t + kBlock, ... of every total in
+// turn (coalesced across the threads, eight blocks' values loaded before they are
+// added in that same order), then a fixed tree over the threads, all K at once
 __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ partials, int nblocks, int K,
                                                   double* totals) {
-  __shared__ double red[kBlock];
-  for (int k = 0; k < K; ++k) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[(size_t)b * K + k];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) totals[k] = red[0];
+  __shared__ double red[kMaxRed][kBlock];
+  double s[kMaxRed];
+#pragma unroll
+  for (int k = 0; k < kMaxRed; ++k) s[k] = 0.0;
+  constexpr int U = 8;
+  int b = threadIdx.x;
+  for (; b + (U - 1) * kBlock < nblocks; b += U * kBlock) {
+    double v[U][kMaxRed];
+#pragma unroll
+    for (int k = 0; k < kMaxRed; ++k)
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u][k] = k < K ? partials[(size_t)k * nblocks + b + u * kBlock] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < kMaxRed; ++k) s[k] += v[u][k];
+  }
+  for (; b < nblocks; b += kBlock)
+#pragma unroll
+    for (int k = 0; k < kMaxRed; ++k)
+      if (k < K) s[k] += partials[(size_t)k * nblocks + b];
+#pragma unroll
+  for (int k = 0; k < kMaxRed; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < kMaxRed; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
     __syncthreads();
   }
+  if ((int)threadIdx.x < K) totals[threadIdx.x] = red[threadIdx.x][0];
 }
 
 }  // namespace lbmk

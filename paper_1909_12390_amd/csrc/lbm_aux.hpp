@@ -22,6 +22,8 @@ __device__ __forceinline__ void wave_sums(double* v) {
   }
 }
 
+// The block's sums of vals[0..K) into partials[k][block] (total-major, gridDim.x
+// blocks: the final pass reads each total's partials contiguously).
 template <int K, int B = kBlock>   // B: threads per workgroup
 __device__ __forceinline__ void block_partials(double* vals, double* partials) {
   __shared__ double red[B / 64][K];
@@ -35,11 +37,11 @@ __device__ __forceinline__ void block_partials(double* vals, double* partials) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < B / 64; ++w) s += red[w][threadIdx.x];
-    partials[(size_t)blockIdx.x * K + threadIdx.x] = s;
+    partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
 }
 
-// as block_partials, but adds the block's sums to partials[block][k] (a running
+// the block's sums of vals[0..K) added to partials[block][k] (block-major: a running
 // per-block accumulator across launches on one stream; each block owns its row)
 template <int K, int B = kBlock>
 __device__ __forceinline__ void block_partials_add(double* vals, double* partials) {
