@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_masked_moles(KParams P, Pops<ST> 
       for (int s = 0; s < NC; ++s) vals[s] = pull_moments<LAT, ST>(P, state, s, c, jr, cell, bits) * P.invM[s];
     }
   }
-  block_partials<NC, kAdjBlock>(vals, partials);
+  block_partials<NC, kAdjBlock, false>(vals, partials);   // block-major, for k_accumulate
 }
 
 // Adjoint seed of L(N): dL/df_sa(y) = mask(y) * coef_s for every direction.

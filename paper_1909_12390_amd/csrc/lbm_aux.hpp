@@ -22,9 +22,11 @@ __device__ __forceinline__ void wave_sums(double* v) {
   }
 }
 
-// The block's sums of vals[0..K) into partials[k][block] (total-major, gridDim.x
-// blocks: the final pass reads each total's partials contiguously).
-template <int K, int B = kBlock>   // B: threads per workgroup
+// The block's sums of vals[0..K) into partials[k][block] (ByTotal: total-major over
+// gridDim.x blocks, so that the moments' final pass reads each total's partials
+// contiguously) or partials[block][k] (block-major, read by the adjoint's
+// accumulator pass, k_accumulate).
+template <int K, int B = kBlock, bool ByTotal = true>   // B: threads per workgroup
 __device__ __forceinline__ void block_partials(double* vals, double* partials) {
   __shared__ double red[B / 64][K];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -37,7 +39,8 @@ __device__ __forceinline__ void block_partials(double* vals, double* partials) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < B / 64; ++w) s += red[w][threadIdx.x];
-    partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    if constexpr (ByTotal) partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    else partials[(size_t)blockIdx.x * K + threadIdx.x] = s;
   }
 }
 
@@ -91,10 +94,33 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams P, Pops<ST> in, cons
     const Coord c = make_coord(cell, P);
     double rb[NC], rho = 0.0;
     R jr[3] = {0, 0, 0};
+    if constexpr (ST == LBM_F64) {
 #pragma unroll
-    for (int s = 0; s < NC; ++s) {
-      rb[s] = pull_moments<LAT, ST>(P, in, s, c, jr, cell, bits);
-      rho += rb[s];
+      for (int s = 0; s < NC; ++s) {
+        rb[s] = pull_moments<LAT, ST>(P, in, s, c, jr, cell, bits);
+        rho += rb[s];
+      }
+    } else {   // every component of a direction by one vector load (ilv_pull_cell)
+      using H = typename Pops<ST>::Elem;
+      float f[NC][V::Q];
+      ilv_pull_cell<LAT, NC, H, kPopLoad>(IlvBufs<H, NC, V::Q>(in, P.cells), c, cell, bits, P.bb != nullptr, f);
+#pragma unroll
+      for (int s = 0; s < NC; ++s) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < V::Q; ++q) acc += (double)f[s][q];
+        rb[s] = acc;
+        rho += acc;
+      }
+#pragma unroll
+      for (int q = 1; q < V::Q; ++q) {
+        R g = f[0][q];
+#pragma unroll
+        for (int s = 1; s < NC; ++s) g += f[s][q];
+        if (V::cx(q)) jr[0] += (R)V::cx(q) * g;
+        if (V::cy(q)) jr[1] += (R)V::cy(q) * g;
+        if (V::cz(q)) jr[2] += (R)V::cz(q) * g;
+      }
     }
     const double j[3] = {(double)jr[0], (double)jr[1], (double)jr[2]};
     double F[3];

@@ -409,34 +409,6 @@ __global__ __launch_bounds__(1024) void kb_init(BatchK K, const BoxK* __restrict
 // box's component count selects the instantiation, uniform per tile)
 // ---------------------------------------------------------------------------
 
-// pull of all components at a cell of a box: per direction one vector load of the
-// source's nc offsets and one of its nc bases; with walls, halfway bounce-back
-// (the source x - e_a when fluid, else the cell's own slot of the opposite direction)
-template <int LAT, int NC, typename H, int CP>
-__device__ __forceinline__ void kbi_pull(const IlvBufs<H, NC, VS<LAT>::Q>& Bf, const Coord& c, unsigned cell,
-                                         unsigned bits, bool walls, float (&f)[NC][VS<LAT>::Q]) {
-  using V = VS<LAT>;
-  constexpr int Q = V::Q;
-  constexpr int NW = IlvWords<H, NC>::N;
-  using IB = IlvBufs<H, NC, Q>;
-  unsigned bw[Q][NC], rw[Q][NW];
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const bool back = walls && ((bits >> a) & 1u);
-    const unsigned src = back ? cell : c.at(-V::cx(a), -V::cy(a), -V::cz(a));
-    const unsigned dir = back ? (unsigned)V::opp(a) : (unsigned)a;
-    ilv_load<0, float, NC>(Bf.rb, src * IB::bs, 0u, bw[a]);
-    ilv_load<CP, H, NC>(Bf.rr, src * IB::cs + dir * Bf.plane, 0u, rw[a]);
-  }
-  __builtin_amdgcn_sched_barrier(0);   // every load ahead of the decode
-  const float one = opaque_one();
-#pragma unroll
-  for (int a = 0; a < Q; ++a)
-#pragma unroll
-    for (int s = 0; s < NC; ++s)
-      f[s][a] = __builtin_bit_cast(float, bw[a][s]) * w_plus((float)V::w(a), ilv_get<H>(rw[a], s), one);
-}
-
 // cache policy of the batched offset loads: float16 keeps the default (a 64-cell
 // tile spans several short rows, whose shifted pulls read lines of the
 // neighbouring tile again), float32 streams them
@@ -449,7 +421,7 @@ __device__ __forceinline__ void kbi_psi_cell(const BatchK& K, const BoxK& B, int
   constexpr int Q = VS<LAT>::Q;
   const auto Bf = in.template bufs<NC, Q>(B);
   float f[NC][Q];
-  kbi_pull<LAT, NC, H, kbi_load_policy<H>()>(Bf, c, cell, bits, B.walls != 0, f);
+  ilv_pull_cell<LAT, NC, H, kbi_load_policy<H>()>(Bf, c, cell, bits, B.walls != 0, f);
   double rb[LBM_MAX_NC];
 #pragma unroll
   for (int s = 0; s < LBM_MAX_NC; ++s) rb[s] = 0.0;
@@ -510,7 +482,7 @@ __device__ __forceinline__ void kbi_collide_cell(const BatchK& K, const KParams&
   const IB Bi = in.template bufs<NC, Q>(B);
   float f[NC][Q];
   if (valid) {
-    kbi_pull<LAT, NC, H, kbi_load_policy<H>()>(Bi, c, cell, bits, B.walls != 0, f);
+    ilv_pull_cell<LAT, NC, H, kbi_load_policy<H>()>(Bi, c, cell, bits, B.walls != 0, f);
   } else {   // solid cells: no pull, no collision; their lanes store zeros into never-read slots
 #pragma unroll
     for (int s = 0; s < NC; ++s)

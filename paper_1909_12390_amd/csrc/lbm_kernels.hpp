@@ -1154,6 +1154,35 @@ __device__ __forceinline__ void ilv_pull_bb(const IlvBufs<H, NC, VS<LAT>::Q>& B,
       f[s][a] = __builtin_bit_cast(float, bw[a][s]) * ((float)V::w(a) + ilv_get<H>(rw[a], s));
 }
 
+// Pull of all components at one cell (one cell per lane, any lane layout): per
+// direction one vector load of the source's nc offsets and one of its nc bases;
+// with walls, halfway bounce-back (the source x - e_a when fluid, else the cell's
+// own slot of the opposite direction).  The batched kernels and the moments use it.
+template <int LAT, int NC, typename H, int CP>
+__device__ __forceinline__ void ilv_pull_cell(const IlvBufs<H, NC, VS<LAT>::Q>& Bf, const Coord& c, unsigned cell,
+                                              unsigned bits, bool walls, float (&f)[NC][VS<LAT>::Q]) {
+  using V = VS<LAT>;
+  constexpr int Q = V::Q;
+  constexpr int NW = IlvWords<H, NC>::N;
+  using IB = IlvBufs<H, NC, Q>;
+  unsigned bw[Q][NC], rw[Q][NW];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const bool back = walls && ((bits >> a) & 1u);
+    const unsigned src = back ? cell : c.at(-V::cx(a), -V::cy(a), -V::cz(a));
+    const unsigned dir = back ? (unsigned)V::opp(a) : (unsigned)a;
+    ilv_load<0, float, NC>(Bf.rb, src * IB::bs, 0u, bw[a]);
+    ilv_load<CP, H, NC>(Bf.rr, src * IB::cs + dir * Bf.plane, 0u, rw[a]);
+  }
+  __builtin_amdgcn_sched_barrier(0);   // every load ahead of the decode
+  const float one = opaque_one();
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+#pragma unroll
+    for (int s = 0; s < NC; ++s)
+      f[s][a] = __builtin_bit_cast(float, bw[a][s]) * w_plus((float)V::w(a), ilv_get<H>(rw[a], s), one);
+}
+
 // pass 1 (interleaved offset storage): densities -> EOS -> psi, one cell per lane
 // with all its components; row segments as in k_psi.
 template <int LAT, int NC, int ST, int B = kBlock>
