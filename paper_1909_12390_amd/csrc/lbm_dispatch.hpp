@@ -81,8 +81,12 @@ struct OpsImpl {
                          make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
     } else {                         // kIlvWaves segments per workgroup, one per wavefront
       const int nb = (int)xcd_grid((segs + kIlvWaves - 1) / kIlvWaves);
-      hipLaunchKernelGGL((k_collide_ilv<LAT, NC, ST, COLL, FORC>), dim3(nb), dim3(64 * kIlvWaves), 0, st, P,
-                         make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
+      if (P.bb)
+        hipLaunchKernelGGL((k_collide_ilv<LAT, NC, ST, COLL, FORC, true>), dim3(nb), dim3(64 * kIlvWaves), 0, st,
+                           P, make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
+      else
+        hipLaunchKernelGGL((k_collide_ilv<LAT, NC, ST, COLL, FORC, false>), dim3(nb), dim3(64 * kIlvWaves), 0, st,
+                           P, make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
     }
   }
   static void moments(const KParams& P, const Bufs& in, const StepScratch& sc, double* rho, double* u, double* p,
