@@ -669,7 +669,15 @@ def main():
         progress("adjoint")
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_side, args.cpu_steps)
+        cb = cpu_baseline(args.cpu_side, args.cpu_steps)
+        if cb and cb.get("value"):
+            # GPU over the float64 oracle on the same mixture: at the same precision
+            # (the float64 GPU step) and for the headline storage
+            cb["gpu_over_oracle"] = {"headline": out["value"] / cb["value"]}
+            f64 = out.get("modes", {}).get("f64/two_pass")
+            if f64:
+                cb["gpu_over_oracle"]["f64"] = f64["mlups_x_comp"] / cb["value"]
+        out["cpu_baseline"] = cb
         progress("cpu baseline")
     print(json.dumps(out), flush=True)
 
