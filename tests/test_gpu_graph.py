@@ -63,15 +63,16 @@ def test_graph_replay_equals_plain_steps(lattice, shape, storage, schedule):
     b.close()
 
 
-def test_graph_replay_with_walls_and_mask_change():
-    print("case graph replay walls", flush=True)
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_graph_replay_with_walls_and_mask_change(storage):
+    print(f"case graph replay walls {storage}", flush=True)
     from oracle import lbm as olbm
     from oracle_backend import to_mixture
     shape = (45, 70)
     solid = np.random.default_rng([9, 1]).uniform(size=shape) < 0.12
     c0 = case("D2Q9", 3, shape, seed=5, u_amp=0.01)
     pw = 1.3 * float(olbm.pseudo_potential(c0["rho0"][:, 0, 0][:, None], c0["T"], to_mixture(c0["mix"]), -1.0)[0])
-    c, a, b = pair("D2Q9", shape, "f64", graph_steps=8, solid=solid, psi_wall=pw)
+    c, a, b = pair("D2Q9", shape, storage, graph_steps=8, solid=solid, psi_wall=pw)
     a.step(24)
     b.step(24)
     assert same(a, b)
