@@ -79,14 +79,18 @@ struct OpsImpl {
     if constexpr (ST == LBM_F64) {   // one workgroup (nc wavefronts) per segment
       hipLaunchKernelGGL((k_collide<LAT, NC, ST, COLL, FORC>), dim3(xcd_grid(segs)), dim3(kCells * NC), 0, st, P,
                          make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
-    } else {                         // kIlvWaves segments per workgroup, one per wavefront
-      const int nb = (int)xcd_grid((segs + kIlvWaves - 1) / kIlvWaves);
-      if (P.bb)
-        hipLaunchKernelGGL((k_collide_ilv<LAT, NC, ST, COLL, FORC, true>), dim3(nb), dim3(64 * kIlvWaves), 0, st,
-                           P, make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
-      else
-        hipLaunchKernelGGL((k_collide_ilv<LAT, NC, ST, COLL, FORC, false>), dim3(nb), dim3(64 * kIlvWaves), 0, st,
-                           P, make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi, plane0, np);
+    } else {                         // ilv_waves segments per workgroup, one per wavefront
+      if (P.bb) {
+        constexpr int w = ilv_waves(true);
+        hipLaunchKernelGGL((k_collide_ilv<LAT, NC, ST, COLL, FORC, true>), dim3(xcd_grid((segs + w - 1) / w)),
+                           dim3(64 * w), 0, st, P, make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi,
+                           plane0, np);
+      } else {
+        constexpr int w = ilv_waves(false);
+        hipLaunchKernelGGL((k_collide_ilv<LAT, NC, ST, COLL, FORC, false>), dim3(xcd_grid((segs + w - 1) / w)),
+                           dim3(64 * w), 0, st, P, make_pops<ST>(in), make_pops<ST>(out), (const double*)sc.psi,
+                           plane0, np);
+      }
     }
   }
   static void moments(const KParams& P, const Bufs& in, const StepScratch& sc, double* rho, double* u, double* p,

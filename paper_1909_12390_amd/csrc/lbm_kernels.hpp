@@ -1232,15 +1232,19 @@ __global__ __launch_bounds__(B) void k_psi_ilv(KParams P, Pops<ST> in, double* _
 // Loads psi at the cell and its Q - 1 neighbours and the pulls of every component,
 // sums the stencil of Eq. (coupledMCforce), the densities and momenta, forms the
 // velocity and the split, then collides and encodes each component in turn and
-// stores each direction's nc offsets with one vector store.  Workgroups of 4 row
-// segments (wavefronts), each independent.
-constexpr int kIlvWaves = 4;
-
+// stores each direction's nc offsets with one vector store.  Workgroups of
+// ilv_waves(WALLS) independent row segments (wavefronts).
+//
 // WALLS: the instantiation for boxes with solid cells (P.bb set), chosen at launch
 // (measured: both the plain and the walls collide run 2-3 % faster as separate
 // instantiations; the psi pass is faster as one kernel with a runtime branch).
+// Wavefronts per workgroup, measured at 128^3: the plain collide 149.7 us with 4,
+// 145-148 us with 2 and 1 (1 ahead by about 1 %); the walls collide 163 us with 2,
+// 166 us with 1.
+constexpr int ilv_waves(bool walls) { return walls ? 2 : 1; }
+
 template <int LAT, int NC, int ST, int COLL, int FORC, bool WALLS>
-__global__ __launch_bounds__(64 * kIlvWaves) void k_collide_ilv(KParams P, Pops<ST> in, Pops<ST> out,
+__global__ __launch_bounds__(64 * ilv_waves(WALLS)) void k_collide_ilv(KParams P, Pops<ST> in, Pops<ST> out,
                                                                const double* __restrict__ psi, int plane0,
                                                                int nplanes) {
   using V = VS<LAT>;
@@ -1250,7 +1254,8 @@ __global__ __launch_bounds__(64 * kIlvWaves) void k_collide_ilv(KParams P, Pops<
   constexpr int NW = IlvWords<H, NC>::N;
   using IB = IlvBufs<H, NC, Q>;
   const unsigned lane = threadIdx.x & 63u;
-  const unsigned seg = logical_block() * kIlvWaves + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const unsigned seg =
+      logical_block() * ilv_waves(WALLS) + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   RowCoord c;
   bool in_row = false;
   if (!row_segment<V::D>(P, seg, plane0, nplanes, lane, &c, &in_row)) return;   // uniform per wavefront
