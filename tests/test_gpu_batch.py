@@ -92,16 +92,21 @@ def test_tiles_grid_and_graph_are_bitwise_identical():
 
 
 @pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16", 1e-4)])
-def test_reduced_precision_batch_close_to_oracle(storage, tol):
-    print(f"case batch {storage}", flush=True)
+@pytest.mark.parametrize("collision,forcing", [("bgk", "edm"), ("mrt", "guo"), ("mrt", "edm")])
+def test_reduced_precision_batch_close_to_oracle(storage, tol, collision, forcing):
+    """Interleaved offset storage in the batch (kb_psi_ilv / kb_collide_ilv), every
+    collision and forcing, one step against the oracle (the budgets of
+    test_gpu_step's reduced-precision test)."""
+    print(f"case batch {storage} {collision}+{forcing}", flush=True)
     boxes = make_boxes(5, 3)
-    b = batch(boxes, collision="bgk", forcing="edm", storage=storage)
+    rates = inputs.default_mrt_rates("D2Q9", 0.8) if collision == "mrt" else None
+    b = batch(boxes, collision=collision, forcing=forcing, storage=storage, mrt_s=rates)
     b.step(1)
     f1 = [x.cpu().numpy() for x in b.fields(populations=True)[1]]
     b.check()
     for i, bx in enumerate(boxes):
         c = {"mix": bx["mix"], "T": bx["T"], "gamma": bx["gamma"], "rho0": bx["rho0"], "u0": None}
-        prm = oracle_params(c, "bgk", "edm", tau=bx["tau"], beta=bx["beta"])
+        prm = oracle_params(c, collision, forcing, tau=bx["tau"], beta=bx["beta"], mrt_s=rates)
         ref = oracle_run(c, "D2Q9", prm, 1)
         assert rel_err(f1[i], ref[1]) < tol
 
@@ -160,3 +165,24 @@ def test_d3q19_boxes_match_oracle(collision, forcing):
         prm = oracle_params(c, collision, forcing, tau=bx["tau"], beta=bx["beta"], mrt_s=rates)
         ref = oracle_run(c, "D3Q19", prm, 3)
         assert rel_err(f3[i], ref[3]) < 1e-12, i
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 5e-6), ("f16", 2e-4)])
+def test_d3q19_reduced_precision_boxes_close_to_oracle(storage, tol):
+    """D3Q19 boxes with 1..4 components in interleaved offset storage (the box's
+    component count selects the kb_*_ilv instantiation per tile), MRT + EDM, three
+    steps against the oracle (the 10-step budgets of test_gpu_step)."""
+    from paper_1909_12390_amd import lbm
+    print(f"case batch D3Q19 {storage}", flush=True)
+    boxes = make_boxes_3d(6, 5)
+    assert sorted({len(b["mix"]["a"]) for b in boxes})[-1] == 4
+    rates = inputs.default_mrt_rates("D3Q19", 0.8)
+    b = lbm.LbmBatch(boxes, "D3Q19", collision="mrt", forcing="edm", storage=storage, mrt_s=rates, tile=128)
+    b.step(3)
+    f3 = [x.cpu().numpy() for x in b.fields(populations=True)[1]]
+    b.check()
+    for i, bx in enumerate(boxes):
+        c = {"mix": bx["mix"], "T": bx["T"], "gamma": bx["gamma"], "rho0": bx["rho0"], "u0": None}
+        prm = oracle_params(c, "mrt", "edm", tau=bx["tau"], beta=bx["beta"], mrt_s=rates)
+        ref = oracle_run(c, "D3Q19", prm, 3)
+        assert rel_err(f3[i], ref[3]) < tol, i
