@@ -159,9 +159,12 @@ def test_set_get_populations_roundtrip():
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
 @pytest.mark.parametrize("storage,tol1,tol10", [("f32", 1e-6, 5e-6), ("f16", 1e-4, 2e-4)])
 @pytest.mark.parametrize("collision,forcing", [("bgk", "guo"), ("mrt", "edm")])
-def test_reduced_precision_step_close_to_oracle(lattice, storage, tol1, tol10, collision, forcing):
-    print(f"case {storage} {lattice} {collision}+{forcing}", flush=True)
-    c = case(lattice, 3, SHAPES[lattice], seed=11, u_amp=0.01)
+@pytest.mark.parametrize("nc", [1, 2, 3, 4])
+def test_reduced_precision_step_close_to_oracle(lattice, storage, tol1, tol10, collision, forcing, nc):
+    # nc sets the width of the interleaved accesses (float16: 2, 4, 4 + 2, 8 bytes;
+    # float32: 4, 8, 12, 16 bytes per direction and cell)
+    print(f"case {storage} {lattice} nc={nc} {collision}+{forcing}", flush=True)
+    c = case(lattice, nc, SHAPES[lattice], seed=11, u_amp=0.01)
     rates = mrt_rates(lattice, 0.8) if collision == "mrt" else None
     prm = oracle_params(c, collision, forcing, mrt_s=rates, beta=1.16 if forcing == "edm" else 1.945)
     ref = oracle_run(c, lattice, prm, 10)
