@@ -63,8 +63,11 @@ struct OpsImpl {
     if constexpr (ST == LBM_F64)
       hipLaunchKernelGGL((k_psi<LAT, NC, ST, B>), dim3(psi_blocks(P, np, D, B)), dim3(B), 0, st, P,
                          make_pops<ST>(in), psi, plane0, np);
+    else if (P.bb)
+      hipLaunchKernelGGL((k_psi_ilv<LAT, NC, ST, B, true>), dim3(psi_blocks(P, np, D, B)), dim3(B), 0, st, P,
+                         make_pops<ST>(in), psi, plane0, np);
     else
-      hipLaunchKernelGGL((k_psi_ilv<LAT, NC, ST, B>), dim3(psi_blocks(P, np, D, B)), dim3(B), 0, st, P,
+      hipLaunchKernelGGL((k_psi_ilv<LAT, NC, ST, B, false>), dim3(psi_blocks(P, np, D, B)), dim3(B), 0, st, P,
                          make_pops<ST>(in), psi, plane0, np);
   }
   static void psi(const KParams& P, const Bufs& in, const StepScratch& sc, int plane0, int np, hipStream_t st) {

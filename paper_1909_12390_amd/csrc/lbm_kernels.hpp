@@ -1067,15 +1067,21 @@ struct IlvBufs {
 // scalar loads (see row_segment: lanes past a short row's end hold x = 0, the
 // periodic right neighbour of its last cell).  issue() starts every load, decode()
 // shifts and decodes; every lane of the wavefront must be active in decode().
-template <int LAT, int NC, typename H>
+// BB (walls, halfway bounce-back as in pull_bb): where the source x - e_a of a
+// direction is solid (bit a of `bits`), the lane loads the offsets of its own slot
+// of the opposite direction instead and decodes them with its own base (the
+// unshifted value of its own row); the other bases still come from the row loads.
+// Lanes with `load` false issue no offset loads (their f is undefined).
+template <int LAT, int NC, typename H, bool BB = false>
 struct IlvRowPull {
   static constexpr int Q = VS<LAT>::Q;
   static constexpr int NW = IlvWords<H, NC>::N;
+  static constexpr int kOwnRow = 4;   // row index r = (dy + 1) + 3 (dz + 1) of (0, 0)
   unsigned bq[9][NC];
   float hl[9][NC], hr[9][NC];
   unsigned rw[Q][NW];
   __device__ __forceinline__ void issue(const IlvPops<H>& in, const IlvBufs<H, NC, Q>& B, const RowCoord& c,
-                                        unsigned nx) {
+                                        unsigned nx, unsigned bits = 0u, bool load = true) {
     using V = VS<LAT>;
     using IB = IlvBufs<H, NC, Q>;
     const unsigned xl = c.x0 == 0 ? nx - 1 : c.x0 - 1;
@@ -1094,14 +1100,30 @@ struct IlvRowPull {
         }
       }
     });
+    if constexpr (BB) {
+      if (load) {
+        const unsigned own = (c.row(0, 0) + c.x(0)) * IB::cs;
 #pragma unroll
-    for (int a = 0; a < Q; ++a)
-      ilv_load<kPopLoad, H, NC>(B.rr, c.x(-V::cx(a)) * IB::cs,
-                                (unsigned)a * B.plane + c.row(-V::cy(a), -V::cz(a)) * IB::cs, rw[a]);
+        for (int a = 0; a < Q; ++a) {
+          const unsigned off = ((bits >> a) & 1u)
+                                   ? own + (unsigned)V::opp(a) * B.plane
+                                   : (c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a))) * IB::cs + (unsigned)a * B.plane;
+          ilv_load<kPopLoad, H, NC>(B.rr, off, 0u, rw[a]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < Q; ++a)
+        ilv_load<kPopLoad, H, NC>(B.rr, c.x(-V::cx(a)) * IB::cs,
+                                  (unsigned)a * B.plane + c.row(-V::cy(a), -V::cz(a)) * IB::cs, rw[a]);
+    }
   }
-  __device__ __forceinline__ void decode(float (&f)[NC][Q]) const {
+  __device__ __forceinline__ void decode(float (&f)[NC][Q], unsigned bits = 0u) const {
     using V = VS<LAT>;
     const float one = opaque_one();
+    float ob[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) ob[s] = __builtin_bit_cast(float, bq[kOwnRow][s]);
     static_for<0, Q>([&](auto A) {
       constexpr int a = decltype(A)::value;
       constexpr int r = pull_row<LAT>(a);
@@ -1112,46 +1134,21 @@ struct IlvRowPull {
         if constexpr (V::cx(a) == 0) b = b0;
         else if constexpr (V::cx(a) > 0) b = lane_from_left(b0, hl[r][s]);   // source x - 1
         else b = lane_from_right(b0, hr[r][s]);                              // source x + 1
+        if constexpr (BB && a != 0) b = ((bits >> a) & 1u) ? ob[s] : b;   // bounced: own base
         f[s][a] = b * w_plus((float)V::w(a), ilv_get<H>(rw[a], s), one);
       }
     });
   }
 };
 
-template <int LAT, int NC, typename H>
+template <int LAT, int NC, typename H, bool BB = false>
 __device__ __forceinline__ void ilv_pull_row(const IlvPops<H>& in, const IlvBufs<H, NC, VS<LAT>::Q>& B,
-                                             const RowCoord& c, unsigned nx, float (&f)[NC][VS<LAT>::Q]) {
-  IlvRowPull<LAT, NC, H> p;
-  p.issue(in, B, c, nx);
+                                             const RowCoord& c, unsigned nx, float (&f)[NC][VS<LAT>::Q],
+                                             unsigned bits = 0u, bool load = true) {
+  IlvRowPull<LAT, NC, H, BB> p;
+  p.issue(in, B, c, nx, bits, load);
   __builtin_amdgcn_sched_barrier(0);   // every load ahead of the shifts and the decode
-  p.decode(f);
-}
-
-// Pull with walls (halfway bounce-back, see pull_bb): per lane, direction a comes
-// from the neighbour x - e_a, or, where that is solid, from the cell's own slot of
-// the opposite direction; the source's bases are loaded per direction.
-template <int LAT, int NC, typename H>
-__device__ __forceinline__ void ilv_pull_bb(const IlvBufs<H, NC, VS<LAT>::Q>& B, const RowCoord& c, unsigned bits,
-                                            float (&f)[NC][VS<LAT>::Q]) {
-  using V = VS<LAT>;
-  constexpr int Q = V::Q;
-  constexpr int NW = IlvWords<H, NC>::N;
-  using IB = IlvBufs<H, NC, Q>;
-  const unsigned own = c.row(0, 0) + c.x(0);
-  unsigned bw[Q][NC], rw[Q][NW];
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const bool back = (bits >> a) & 1u;
-    const unsigned src = back ? own : c.row(-V::cy(a), -V::cz(a)) + c.x(-V::cx(a));
-    const unsigned dir = back ? (unsigned)V::opp(a) : (unsigned)a;
-    ilv_load<0, float, NC>(B.rb, src * IB::bs, 0u, bw[a]);
-    ilv_load<kPopLoad, H, NC>(B.rr, src * IB::cs + dir * B.plane, 0u, rw[a]);
-  }
-#pragma unroll
-  for (int a = 0; a < Q; ++a)
-#pragma unroll
-    for (int s = 0; s < NC; ++s)
-      f[s][a] = __builtin_bit_cast(float, bw[a][s]) * ((float)V::w(a) + ilv_get<H>(rw[a], s));
+  p.decode(f, bits);
 }
 
 // Pull of all components at one cell (one cell per lane, any lane layout): per
@@ -1184,8 +1181,11 @@ __device__ __forceinline__ void ilv_pull_cell(const IlvBufs<H, NC, VS<LAT>::Q>& 
 }
 
 // pass 1 (interleaved offset storage): densities -> EOS -> psi, one cell per lane
-// with all its components; row segments as in k_psi.
-template <int LAT, int NC, int ST, int B = kBlock>
+// with all its components; row segments as in k_psi.  WALLS: the instantiation for
+// boxes with solid cells (P.bb set), chosen at launch, so that the walls pull's
+// registers (about 140 VGPRs, 3 wavefronts per SIMD) do not lower the occupancy of
+// the plain pass (4 per SIMD).
+template <int LAT, int NC, int ST, int B = kBlock, bool WALLS = false>
 __global__ __launch_bounds__(B) void k_psi_ilv(KParams P, Pops<ST> in, double* __restrict__ psi, int plane0,
                                               int nplanes) {
   using V = VS<LAT>;
@@ -1197,21 +1197,13 @@ __global__ __launch_bounds__(B) void k_psi_ilv(KParams P, Pops<ST> in, double* _
   bool in_row = false;
   if (!row_segment<V::D>(P, seg, plane0, nplanes, lane, &c, &in_row)) return;   // uniform per wavefront
   const unsigned cell = c.row(0, 0) + c.x(0);
-  const unsigned bits = P.bb ? P.bb[cell] : 0u;
+  const unsigned bits = WALLS ? P.bb[cell] : 0u;
   const IlvBufs<H, NC, Q> Bf(in, P.cells);
   float f[NC][Q];
-  if (P.bb) {
-    if (in_row && !(bits >> kSolidBit)) {
-      ilv_pull_bb<LAT, NC, H>(Bf, c, bits, f);
-    } else {
-#pragma unroll
-      for (int s = 0; s < NC; ++s)
-#pragma unroll
-        for (int a = 0; a < Q; ++a) f[s][a] = 0.0f;
-    }
-  } else {
+  if constexpr (WALLS)   // every lane takes part in the base shifts; solid lanes load no offsets
+    ilv_pull_row<LAT, NC, H, true>(in, Bf, c, (unsigned)P.nx, f, bits, in_row && !(bits >> kSolidBit));
+  else
     ilv_pull_row<LAT, NC, H>(in, Bf, c, (unsigned)P.nx, f);   // every lane pulls
-  }
   if (!in_row) return;
   if (bits >> kSolidBit) {   // solid: the wall's psi, no EOS
     psi[cell] = P.psi_wall;
@@ -1237,7 +1229,7 @@ __global__ __launch_bounds__(B) void k_psi_ilv(KParams P, Pops<ST> in, double* _
 //
 // WALLS: the instantiation for boxes with solid cells (P.bb set), chosen at launch
 // (measured: both the plain and the walls collide run 2-3 % faster as separate
-// instantiations; the psi pass is faster as one kernel with a runtime branch).
+// instantiations).
 // Wavefronts per workgroup, measured at 128^3: the plain collide 149.7 us with 4,
 // 145-148 us with 2 and 1 (1 ahead by about 1 %); the walls collide 163 us with 2,
 // 166 us with 1.
@@ -1287,11 +1279,10 @@ __global__ __launch_bounds__(64 * ilv_waves(WALLS)) void k_collide_ilv(KParams P
   const IB Bi(in, P.cells);
   float f[NC][Q];
   if constexpr (WALLS) {
-    // walls: solid cells do not pull and do not collide; their slots are never
+    // walls: solid cells load no offsets and do not collide; their slots are never
     // read and hold zeros, which their lanes store again (whole rows written)
-    if (valid) {
-      ilv_pull_bb<LAT, NC, H>(Bi, c, bits, f);
-    } else {
+    ilv_pull_row<LAT, NC, H, true>(in, Bi, c, (unsigned)P.nx, f, bits, valid);
+    if (!valid) {
 #pragma unroll
       for (int s = 0; s < NC; ++s)
 #pragma unroll

@@ -91,3 +91,16 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_stored_counters_match_the_current_kernel_sources():
+    # profiles/traffic.json holds the rocprofv3 FETCH_SIZE / WRITE_SIZE and pipe
+    # counters that bench.py reports; each entry names the step kernels' source hash
+    # it was taken with, and a stale entry is reported as null
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        rec = json.load(fh)
+    sha = bench.kernel_source_sha()
+    assert rec and all(v["source_sha"] == sha for v in rec.values()), \
+        {k: v["source_sha"] for k, v in rec.items()}
+    for key in rec:
+        assert bench.measured_profile(key) == rec[key]
