@@ -5,7 +5,7 @@
 * lbm_moments reports zero density, velocity and pressure on solid cells and
   psi_w there, the oracle's fields on fluid cells and its mass totals;
 * float32 / float16 offset storage stay within the reduced-precision budget of
-  the periodic step;
+  the periodic step, for 1 to 4 components;
 * BLOCKED and OVERLAP schedules are bitwise equal to TWO_PASS with walls;
 * the GPU's Poiseuille profile is the exact parabola at (tau - 1/2)^2 = 3/16;
 * replacing the mask keeps the canonical populations of cells that stay fluid;
@@ -110,10 +110,16 @@ def test_moments_with_walls(lattice):
 
 
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("nc", [1, 2, 3, 4])
 @pytest.mark.parametrize("storage,tol1,tol10", [("f32", 1e-6, 5e-6), ("f16", 1e-4, 2e-4)])
-def test_reduced_precision_walls(lattice, storage, tol1, tol10):
-    print(f"case walls {storage} {lattice}", flush=True)
-    c, solid, prm, ctx, f0 = setup(lattice, 3, 11, "mrt", "edm", storage=storage, beta=1.16)
+def test_reduced_precision_walls(lattice, nc, storage, tol1, tol10):
+    # every component count: the offset loads of the walls pull differ in width
+    # (float16: 2, 4, 4 + 2 and 8 bytes per cell; float32: 4 to 16)
+    print(f"case walls {storage} {lattice} nc={nc}", flush=True)
+    # seed 11 leaves the EOS domain next to the walls for the binary D2Q9 case
+    # within 10 oracle steps; seed 2 (the float64 test's) does not
+    seed = 2 if (lattice, nc) == ("D2Q9", 2) else 11
+    c, solid, prm, ctx, f0 = setup(lattice, nc, seed, "mrt", "edm", storage=storage, beta=1.16)
     ref = oracle_steps(c, prm, lattice, f0, 10)
     ctx.step(1)
     e1 = rel_err(ctx.get_populations().cpu().numpy(), ref[1])
