@@ -254,6 +254,29 @@ def batched_section(args, torch, lbm, inputs):
         b.close()
         del b
         torch.cuda.empty_cache()
+    # the one-launch step (psi of each tile and its neighbours in LDS), at its own
+    # tuned launch shape, beside the two launches
+    res["fused"] = {"step": "one launch per step, psi of each tile and its neighbours computed into LDS"}
+    for storage in ("f32", "f16"):
+        tune = autotune.tune_batch(boxes, "D2Q9", "bgk", "edm", storage, steps=20, fused=True)
+        b = lbm.LbmBatch(boxes, "D2Q9", collision="bgk", forcing="edm", storage=storage, tile=tune["tile"],
+                         grid=tune["grid"], graph_steps=graph_steps, fused=True)
+        b.step(2 * graph_steps)
+        b.check()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(b.stream)
+        b.step(args.batch_steps)
+        stop.record(b.stream)
+        stop.synchronize()
+        ms = start.elapsed_time(stop) / args.batch_steps
+        b.check()
+        res["fused"][storage] = {"ms_per_step": ms, "mlups_x_comp": comp_cells / (ms * 1e-3) / 1e6,
+                                 "tile": tune["tile"], "grid": tune["grid"],
+                                 "time_vs_two_launches": ms / res[storage]["ms_per_step"]}
+        b.close()
+        del b
+        torch.cuda.empty_cache()
     if args.batch_precision_steps > 0:
         fr = {}
         for storage in ("f64", "f32", "f16"):

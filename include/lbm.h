@@ -315,7 +315,17 @@ typedef struct {
   int grid;                  /* workgroups of the persistent launch (0 = all resident) */
   double mrt_s[LBM_MAX_Q];
   double accel[3];
+  int fused;                 /* 0: two launches per step (psi pass, collide pass).
+                                1: one launch per step: each workgroup computes psi
+                                for its tile's cells and their neighbours into LDS
+                                (rows padded with their periodic images), then
+                                collides from the pull it kept; populations equal the
+                                two-launch step's bit for bit.  D2Q9 with float32 / float16 offset storage
+                                and boxes with nx <= LBM_FUSED_MAX_NX only, else
+                                lbm_batch_layout / lbm_batch_init return LBM_ERR_ARG. */
 } lbm_batch_params;
+
+#define LBM_FUSED_MAX_NX 2048
 
 typedef struct lbm_batch lbm_batch;
 

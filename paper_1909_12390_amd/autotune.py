@@ -23,7 +23,7 @@ CANDIDATE_TILES = (64, 128, 256)
 CANDIDATE_GRIDS = (0, 4096, 16384)
 
 
-def _key(boxes, lattice, collision, forcing, storage):
+def _key(boxes, lattice, collision, forcing, storage, fused=False):
     import numpy as np
     import torch
     cells = int(sum(int(np.prod(b["shape"])) for b in boxes))
@@ -32,7 +32,9 @@ def _key(boxes, lattice, collision, forcing, storage):
         nc = len(b["mix"]["a"])
         hist[nc] = hist.get(nc, 0) + 1
     sig = ",".join(f"{k}:{hist[k]}" for k in sorted(hist))
-    return f"{torch.cuda.get_device_name(0)}|{lattice}|{collision}|{forcing}|{storage}|{len(boxes)}|{cells}|{sig}"
+    step = "|fused" if fused else ""
+    return (f"{torch.cuda.get_device_name(0)}|{lattice}|{collision}|{forcing}|{storage}{step}|{len(boxes)}|{cells}|"
+            f"{sig}")
 
 
 def _event_ms(torch, stream, run):
@@ -46,14 +48,15 @@ def _event_ms(torch, stream, run):
 
 
 def tune_batch(boxes, lattice="D2Q9", collision="bgk", forcing="edm", storage="f32", steps=20, warmup=5,
-               tiles=CANDIDATE_TILES, grids=CANDIDATE_GRIDS, cache_path=None, mrt_s=None):
+               tiles=CANDIDATE_TILES, grids=CANDIDATE_GRIDS, cache_path=None, mrt_s=None, fused=False):
     """Return {"tile", "grid", "ms_per_step", "trials": {"tile/grid": ms}} for this
-    batch and storage format."""
+    batch and storage format; fused=True tunes the one-launch step
+    (lbm_batch_params.fused) instead of the two launches."""
     import torch
 
     from . import lbm
 
-    key = _key(boxes, lattice, collision, forcing, storage)
+    key = _key(boxes, lattice, collision, forcing, storage, fused)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
@@ -67,7 +70,7 @@ def tune_batch(boxes, lattice="D2Q9", collision="bgk", forcing="edm", storage="f
     for tile in tiles:
         for grid in grids:
             b = lbm.LbmBatch(boxes, lattice, collision=collision, forcing=forcing, storage=storage, tile=tile,
-                             grid=grid, mrt_s=mrt_s)
+                             grid=grid, mrt_s=mrt_s, fused=fused)
             b.step(warmup)
             b.check()
             ms = _event_ms(torch, b.stream, lambda: b.step(steps)) / steps
@@ -78,7 +81,8 @@ def tune_batch(boxes, lattice="D2Q9", collision="bgk", forcing="edm", storage="f
             torch.cuda.empty_cache()
     best = min(trials, key=trials.get)
     tile, grid = (int(v) for v in best.split("/"))
-    res = {"tile": tile, "grid": grid, "ms_per_step": trials[best], "trials": trials, "storage": storage}
+    res = {"tile": tile, "grid": grid, "ms_per_step": trials[best], "trials": trials, "storage": storage,
+           "fused": bool(fused)}
     if cache_path:
         cache[key] = res
         os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)

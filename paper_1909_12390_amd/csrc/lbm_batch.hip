@@ -44,6 +44,9 @@ lbm_status batch_validate(const lbm_box* boxes, int nboxes, const lbm_batch_para
   const int t = prm->tile;
   if (!(t == 0 || t == 64 || t == 128 || t == 256)) return lbm_fail(LBM_ERR_ARG, "tile must be 0, 64, 128 or 256");
   if (prm->graph_steps < 0 || prm->grid < 0) return lbm_fail(LBM_ERR_ARG, "graph_steps and grid must be >= 0");
+  if (prm->fused != 0 && prm->fused != 1) return lbm_fail(LBM_ERR_ARG, "fused must be 0 or 1");
+  if (prm->fused && (prm->lattice != LBM_D2Q9 || prm->storage == LBM_F64))
+    return lbm_fail(LBM_ERR_ARG, "the fused step needs D2Q9 and float32 or float16 offset storage");
   const int Q = prm->lattice == LBM_D2Q9 ? 9 : 19;
   if (prm->collision == LBM_MRT)
     for (int k = 0; k < Q; ++k)
@@ -54,6 +57,8 @@ lbm_status batch_validate(const lbm_box* boxes, int nboxes, const lbm_batch_para
     if (m.nc < 1 || m.nc > LBM_MAX_NC) return lbm_fail(LBM_ERR_ARG, "box %d: nc must be in 1..4", i);
     if (B.nx < 1 || B.ny < 1 || B.nz < 1) return lbm_fail(LBM_ERR_ARG, "box %d: sides must be >= 1", i);
     if (prm->lattice == LBM_D2Q9 && B.nz != 1) return lbm_fail(LBM_ERR_ARG, "box %d: D2Q9 needs nz == 1", i);
+    if (prm->fused && B.nx > LBM_FUSED_MAX_NX)
+      return lbm_fail(LBM_ERR_ARG, "box %d: the fused step takes rows of at most %d cells", i, LBM_FUSED_MAX_NX);
     // a box's population planes are addressed with 32-bit byte offsets: one
     // component's planes (float64), all components' interleaved planes (offsets)
     const double sb = prm->storage == LBM_F64 ? 8.0 : (prm->storage == LBM_F32_OFS ? 4.0 : 2.0);
@@ -138,6 +143,8 @@ struct lbm_batch {
   BOps ops;
   int grid;           // persistent grid of the one-thread-per-cell kernels
   int grid_collide;   // persistent grid of kb_collide
+  int grid_step;      // persistent grid of the fused step (fused batches)
+  size_t step_lds;    // its LDS bytes per workgroup
   hipStream_t stream;
   BBufs pops[2];
   double* psi;
@@ -152,8 +159,12 @@ namespace {
 void enqueue_batch_step(lbm_batch* b) {
   const BBufs& in = b->pops[b->cur];
   const BBufs& out = b->pops[1 - b->cur];
-  b->ops.psi(b->K, b->grid, in, b->psi, b->stream);
-  b->ops.collide(b->K, b->grid_collide, in, out, b->psi, b->stream);
+  if (b->prm.fused) {
+    b->ops.step(b->K, b->grid_step, b->step_lds, in, out, b->stream);
+  } else {
+    b->ops.psi(b->K, b->grid, in, b->psi, b->stream);
+    b->ops.collide(b->K, b->grid_collide, in, out, b->psi, b->stream);
+  }
   b->cur = 1 - b->cur;
 }
 }  // namespace
@@ -287,6 +298,26 @@ extern "C" lbm_status lbm_batch_init(const lbm_box* boxes, int nboxes, const lbm
   for (int k = 0; k < 2; ++k) grids[k] = (int)xcd_grid((unsigned)std::max(1, std::min<int>(grids[k], (int)L.ntiles)));
   b->grid = grids[0];
   b->grid_collide = grids[1];
+  b->grid_step = 0;
+  b->step_lds = 0;
+  if (prm->fused) {
+    int nx_max = 1;
+    for (int i = 0; i < nboxes; ++i) nx_max = std::max(nx_max, boxes[i].nx);
+    b->step_lds = fused_lds_bytes(tile, nx_max);
+    int g = prm->grid;
+    if (g <= 0) {
+      int dev = 0, cus = 0, per_cu = 1;
+      st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+      if (st == LBM_OK) st = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "cus");
+      if (st != LBM_OK) {
+        delete b;
+        return st;
+      }
+      b->ops.step_occupancy(tile, b->step_lds, &per_cu);
+      g = cus * per_cu;
+    }
+    b->grid_step = (int)xcd_grid((unsigned)std::max(1, std::min<int>(g, (int)L.ntiles)));
+  }
 
   st = hip_check(hipMemcpyAsync((void*)b->K.boxes, hb.data(), hb.size() * sizeof(BoxK), hipMemcpyHostToDevice,
                                 b->stream), "upload boxes");

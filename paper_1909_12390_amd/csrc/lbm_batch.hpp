@@ -464,31 +464,18 @@ __global__ __launch_bounds__(256) void kb_psi_ilv(BatchK K, const BoxK* __restri
   }
 }
 
+// The collision of one cell from its pulled populations f (zeros for a solid cell)
+// and psi at the cell and its neighbours (pn[a] at x + e_a): the force, the split,
+// the collision, the encoding and the stores of the cell's slots.
 template <int LAT, int NC, typename H, int COLL, int FORC>
-__device__ __forceinline__ void kbi_collide_cell(const BatchK& K, const KParams& P, const BoxK& B, int bx,
-                                                 const BatchIlvPops<H>& in, const BatchIlvPops<H>& out,
-                                                 const Coord& c, unsigned cell, unsigned bits,
-                                                 const double* __restrict__ psi) {
+__device__ __forceinline__ void kbi_collide_pulled(const BatchK& K, const KParams& P, const BoxK& B, int bx,
+                                                   const BatchIlvPops<H>& out, unsigned cell, bool valid,
+                                                   float (&f)[NC][VS<LAT>::Q], const double (&pn)[VS<LAT>::Q]) {
   using V = VS<LAT>;
   using R = float;
   constexpr int Q = V::Q;
   constexpr int NW = IlvWords<H, NC>::N;
   using IB = IlvBufs<H, NC, Q>;
-  const bool valid = !(bits >> kSolidBit);
-  const double* ps = psi + B.psi_off;
-  double pn[Q];
-#pragma unroll
-  for (int a = 0; a < Q; ++a) pn[a] = ps[c.at(V::cx(a), V::cy(a), V::cz(a))];
-  const IB Bi = in.template bufs<NC, Q>(B);
-  float f[NC][Q];
-  if (valid) {
-    ilv_pull_cell<LAT, NC, H, kbi_load_policy<H>()>(Bi, c, cell, bits, B.walls != 0, f);
-  } else {   // solid cells: no pull, no collision; their lanes store zeros into never-read slots
-#pragma unroll
-    for (int s = 0; s < NC; ++s)
-#pragma unroll
-      for (int a = 0; a < Q; ++a) f[s][a] = 0.0f;
-  }
   // total force of Eq. (coupledMCforce) (float64), summed over opposite pairs
   double F[3] = {0.0, 0.0, 0.0};
   {
@@ -558,6 +545,31 @@ __device__ __forceinline__ void kbi_collide_cell(const BatchK& K, const KParams&
   ilv_store<kBaseStore, float, NC>(Bo.rb, cell * IB::bs, 0u, bw);
 }
 
+template <int LAT, int NC, typename H, int COLL, int FORC>
+__device__ __forceinline__ void kbi_collide_cell(const BatchK& K, const KParams& P, const BoxK& B, int bx,
+                                                 const BatchIlvPops<H>& in, const BatchIlvPops<H>& out,
+                                                 const Coord& c, unsigned cell, unsigned bits,
+                                                 const double* __restrict__ psi) {
+  using V = VS<LAT>;
+  constexpr int Q = V::Q;
+  const bool valid = !(bits >> kSolidBit);
+  const double* ps = psi + B.psi_off;
+  double pn[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) pn[a] = ps[c.at(V::cx(a), V::cy(a), V::cz(a))];
+  const auto Bi = in.template bufs<NC, Q>(B);
+  float f[NC][Q];
+  if (valid) {
+    ilv_pull_cell<LAT, NC, H, kbi_load_policy<H>()>(Bi, c, cell, bits, B.walls != 0, f);
+  } else {   // solid cells: no pull, no collision; their lanes store zeros into never-read slots
+#pragma unroll
+    for (int s = 0; s < NC; ++s)
+#pragma unroll
+      for (int a = 0; a < Q; ++a) f[s][a] = 0.0f;
+  }
+  kbi_collide_pulled<LAT, NC, H, COLL, FORC>(K, P, B, bx, out, cell, valid, f, pn);
+}
+
 // pass 2 over every tile (interleaved offsets): one cell per thread with all its
 // components (no LDS, no idle component groups for boxes with fewer components)
 template <int LAT, int NCMAX, int ST, int COLL, int FORC>
@@ -591,6 +603,130 @@ __global__ __launch_bounds__(256) void kb_collide_ilv(BatchK K, const BoxK* __re
       if (nc == 3) kbi_collide_cell<LAT, 3, H, COLL, FORC>(K, P, B, bx, in, out, c, cell, bits, psi);
     if constexpr (NCMAX >= 4)
       if (nc == 4) kbi_collide_cell<LAT, 4, H, COLL, FORC>(K, P, B, bx, in, out, c, cell, bits, psi);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused step (D2Q9, interleaved offsets): one launch per step instead of the psi
+// pass and the collide pass.  A tile's cells are consecutive in the box's
+// row-major order; the workgroup computes psi for them and their neighbours into
+// LDS (its own cells from the pull it keeps for their collision, the others from a
+// density-only pull) and collides after a barrier.  LDS holds padded rows of
+// nx + 2 slots, x = -1 .. nx, the two ends being the periodic images of x = nx - 1
+// and x = 0: with the padded index p(x, y) = y (nx + 2) + x + 1 of the unwrapped
+// row-major order, slot s holds psi at p = base + s, base = p(t0) - (nx + 3), and
+// every neighbour of a tile cell sits at the cell's own slot + c_y (nx + 2) + c_x
+// (no wrap on the read side; the rows are wrapped in y where psi is computed).
+// The slots span p(t0 + T - 1) - p(t0) + 2 (nx + 3) + 1 <= 3 T + 2 nx + 8.  Psi and
+// the collision are kbi_psi_cell's and kbi_collide_cell's arithmetic, so the
+// populations equal the two passes' bit for bit; the two-pass psi array is not
+// written.
+// ---------------------------------------------------------------------------
+
+// psi of `cell` (kb_psi_ilv's arithmetic); f receives the cell's pull, zeros for a
+// solid cell
+template <int LAT, int NC, typename H>
+__device__ __forceinline__ double kbi_psi_pull(const BatchK& K, const BoxK& B, int bx, const IlvBufs<H, NC, VS<LAT>::Q>& Bf,
+                                               unsigned cell, float (&f)[NC][VS<LAT>::Q]) {
+  constexpr int Q = VS<LAT>::Q;
+  const unsigned bits = B.walls ? K.bb[B.bb_off + cell] : 0u;
+  if (bits >> kSolidBit) {
+#pragma unroll
+    for (int s = 0; s < NC; ++s)
+#pragma unroll
+      for (int a = 0; a < Q; ++a) f[s][a] = 0.0f;
+    return B.psi_wall;
+  }
+  ilv_pull_cell<LAT, NC, H, kbi_load_policy<H>()>(Bf, box_coord(cell, B), cell, bits, B.walls != 0, f);
+  double rb[LBM_MAX_NC];
+#pragma unroll
+  for (int s = 0; s < LBM_MAX_NC; ++s) rb[s] = 0.0;
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) acc += (double)f[s][a];
+    rb[s] = acc;
+  }
+  return box_psi(K, B, bx, rb);
+}
+
+// bytes of LDS the fused step needs for tiles of `tile` cells and rows up to nx_max
+inline size_t fused_lds_bytes(int tile, int nx_max) { return (size_t)(3 * tile + 2 * nx_max + 8) * sizeof(double); }
+
+// one tile of the fused step; every thread of the workgroup calls it (two barriers)
+template <int LAT, int NC, typename H, int COLL, int FORC>
+__device__ __forceinline__ void kbi_fused_tile(const BatchK& K, const KParams& P, const BoxK& B, int bx,
+                                               const BatchIlvPops<H>& in, const BatchIlvPops<H>& out, unsigned t0,
+                                               double* sh) {
+  using V = VS<LAT>;
+  constexpr int Q = V::Q;
+  const int T = K.tile, tid = (int)threadIdx.x;
+  const int nx = B.nx, ny = B.ny, W = nx + 2;
+  const unsigned cells = B.cells;
+  const auto Bf = in.template bufs<NC, Q>(B);
+  const auto pad = [nx, W](unsigned i) { return (int)(i / (unsigned)nx) * W + (int)(i % (unsigned)nx) + 1; };
+  const int base = pad(t0) - (W + 1);
+  const int span = pad(t0 + (unsigned)T - 1u) + (W + 1) - base + 1;
+  // own cell (or, past the box's last cell, its periodic image), kept for the collision
+  const unsigned lin = t0 + (unsigned)tid;
+  const bool own = lin < cells;
+  const int my = pad(lin) - base;
+  float f[NC][Q];
+  sh[my] = kbi_psi_pull<LAT, NC, H>(K, B, bx, Bf, own ? lin : lin % cells, f);
+  // the other slots: neighbours outside the tile and the periodic images
+  for (int s = tid; s < span; s += T) {
+    const int p = base + s;
+    const int y = p >= 0 ? p / W : -((W - 1 - p) / W);   // floor division
+    const int xp = p - y * W - 1;                          // -1 .. nx
+    const long long l = (long long)y * nx + xp;
+    if (xp >= 0 && xp < nx && l >= (long long)t0 && l < (long long)t0 + T) continue;   // a tile thread's slot
+    const int x = xp < 0 ? nx - 1 : (xp >= nx ? 0 : xp);
+    const int yw = ((y % ny) + ny) % ny;
+    float g[NC][Q];
+    sh[s] = kbi_psi_pull<LAT, NC, H>(K, B, bx, Bf, (unsigned)(yw * nx + x), g);
+  }
+  __syncthreads();
+  if (own) {
+    double pn[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) pn[a] = sh[my + V::cy(a) * W + V::cx(a)];
+    const unsigned bits = B.walls ? K.bb[B.bb_off + lin] : 0u;
+    kbi_collide_pulled<LAT, NC, H, COLL, FORC>(K, P, B, bx, out, lin, !(bits >> kSolidBit), f, pn);
+  }
+  __syncthreads();   // the next tile overwrites sh
+}
+
+template <int LAT, int NCMAX, int ST, int COLL, int FORC>
+__global__ __launch_bounds__(256) void kb_step_ilv(BatchK K, const BoxK* __restrict__ boxes,
+                                                   const int* __restrict__ tile_box, BatchPops<ST> in,
+                                                   BatchPops<ST> out) {
+  static_assert(LAT == LBM_D2Q9 && ST != LBM_F64, "the fused step is built for D2Q9 offset storage");
+  using H = typename BatchPops<ST>::Elem;
+  extern __shared__ double sh_psi[];
+  KParams P;
+#pragma unroll
+  for (int k = 0; k < LBM_MAX_Q; ++k) P.mrt_c[k] = K.mrt_c[k];
+  P.mrt_rows = K.mrt_rows;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) P.accel[d] = K.accel[d];
+  const TileRange tr = tile_range(K.ntiles);
+  for (unsigned t = tr.t; t < tr.end; t += tr.stride) {   // uniform per workgroup
+    const int bx = __builtin_amdgcn_readfirstlane(tile_box[t]);
+    const BoxK& B = boxes[bx];
+    const unsigned t0 = (t - B.first_tile) * (unsigned)K.tile;
+    P.cells = (int)B.cells;
+    P.omega = B.omega;
+#pragma unroll
+    for (int s = 0; s < LBM_MAX_NC; ++s) P.gamma[s] = B.gamma[s];
+    const int nc = B.nc;
+    if (nc == 1) kbi_fused_tile<LAT, 1, H, COLL, FORC>(K, P, B, bx, in, out, t0, sh_psi);
+    if constexpr (NCMAX >= 2)
+      if (nc == 2) kbi_fused_tile<LAT, 2, H, COLL, FORC>(K, P, B, bx, in, out, t0, sh_psi);
+    if constexpr (NCMAX >= 3)
+      if (nc == 3) kbi_fused_tile<LAT, 3, H, COLL, FORC>(K, P, B, bx, in, out, t0, sh_psi);
+    if constexpr (NCMAX >= 4)
+      if (nc == 4) kbi_fused_tile<LAT, 4, H, COLL, FORC>(K, P, B, bx, in, out, t0, sh_psi);
   }
 }
 

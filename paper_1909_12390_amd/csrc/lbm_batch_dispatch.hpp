@@ -43,6 +43,9 @@ inline BatchPops<LBM_F16_OFS> bpops<LBM_F16_OFS>(const BBufs& b) {
 struct BOps {
   void (*psi)(const BatchK&, int, const BBufs&, double*, hipStream_t);
   void (*collide)(const BatchK&, int, const BBufs&, const BBufs&, const double*, hipStream_t);
+  // fused step (kb_step_ilv, D2Q9 offset storage; null otherwise): grid, LDS bytes
+  void (*step)(const BatchK&, int, size_t, const BBufs&, const BBufs&, hipStream_t);
+  void (*step_occupancy)(int tile, size_t lds, int* per_cu);
   void (*exp)(const BatchK&, int, const BBufs&, const unsigned long long*, double*, double*, hipStream_t);
   void (*init)(const BatchK&, int, const BBufs&, const unsigned long long*, const double*, hipStream_t);
   void (*occupancy)(int tile, int* per_cu);   // resident workgroups per CU: [cell kernels, collide]
@@ -97,7 +100,23 @@ struct BOpsImpl {
     per_cu[0] = ea == hipSuccess ? std::max(1, a) : 1;
     per_cu[1] = eb == hipSuccess ? std::max(1, b) : 1;
   }
-  static BOps ops() { return BOps{&psi, &collide, &exp, &init, &occupancy, NCMAX}; }
+  static constexpr bool kFused = kIlv && LAT == LBM_D2Q9;
+  static void step(const BatchK& K, int grid, size_t lds, const BBufs& in, const BBufs& out, hipStream_t st) {
+    if constexpr (kFused)
+      hipLaunchKernelGGL((kb_step_ilv<LAT, NCMAX, ST, COLL, FORC>), dim3(grid), dim3(K.tile), lds, st, K, K.boxes,
+                         K.tile_box, bpops<ST>(in), bpops<ST>(out));
+  }
+  static void step_occupancy(int tile, size_t lds, int* per_cu) {
+    int a = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if constexpr (kFused)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kb_step_ilv<LAT, NCMAX, ST, COLL, FORC>, tile, lds);
+    *per_cu = e == hipSuccess ? std::max(1, a) : 1;
+  }
+  static BOps ops() {
+    return BOps{&psi, &collide, kFused ? &step : nullptr, kFused ? &step_occupancy : nullptr, &exp, &init, &occupancy,
+                NCMAX};
+  }
 };
 
 template <int LAT, int NCMAX, int ST>

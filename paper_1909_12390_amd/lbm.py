@@ -78,7 +78,7 @@ class LbmBox(ctypes.Structure):
 class LbmBatchParams(ctypes.Structure):
     _fields_ = [("lattice", c_int), ("collision", c_int), ("forcing", c_int), ("storage", c_int),
                 ("tile", c_int), ("graph_steps", c_int), ("grid", c_int), ("mrt_s", c_double * MAX_Q),
-                ("accel", c_double * 3)]
+                ("accel", c_double * 3), ("fused", c_int)]
 
 
 _lib = None
@@ -541,10 +541,12 @@ class LbmBatch:
     "gamma", "rho0" (nc, *shape)}, optionally "solid" (*shape, bool) and "psi_wall"
     for walls (the model of lbm_set_solid).  With graph_steps > 0 the batch runs on
     its own (default-priority) stream so the steps can be captured in a HIP graph.
+    fused=True runs one launch per step (D2Q9 with "f32" / "f16" storage only; see
+    lbm_batch_params.fused).
     """
 
     def __init__(self, boxes, lattice="D2Q9", collision="bgk", forcing="edm", storage="f64", tile=0,
-                 graph_steps=0, grid=0, mrt_s=None, accel=None, G=-1.0, device="cuda"):
+                 graph_steps=0, grid=0, mrt_s=None, accel=None, G=-1.0, device="cuda", fused=False):
         import torch
         self.torch = torch
         self.lattice = lattice
@@ -589,6 +591,7 @@ class LbmBatch:
         prm.tile = int(tile)
         prm.graph_steps = int(graph_steps)
         prm.grid = int(grid)
+        prm.fused = 1 if fused else 0
         if mrt_s is not None:
             for k, v in enumerate(mrt_s):
                 prm.mrt_s[k] = float(v)

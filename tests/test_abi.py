@@ -82,7 +82,7 @@ def _mix4():
 
 
 def _batch_layout(nboxes=2, tile=0, grid=0, graph_steps=0, nc=2, lattice="D2Q9", shape=(8, 16), gamma=None,
-                  solid=None, psi_wall=0.0, storage=2):
+                  solid=None, psi_wall=0.0, storage=2, fused=0):
     n = nboxes
     arr = (lbm.LbmBox * max(n, 1))()
     for i in range(n):
@@ -99,10 +99,25 @@ def _batch_layout(nboxes=2, tile=0, grid=0, graph_steps=0, nc=2, lattice="D2Q9",
     prm.lattice = lbm.LATTICES[lattice]
     prm.collision, prm.forcing, prm.storage = 0, 1, storage
     prm.tile, prm.grid, prm.graph_steps = tile, grid, graph_steps
+    prm.fused = fused
     ws, fe, pe = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
     code = lbm.lib().lbm_batch_layout(arr, n, ctypes.byref(prm), ctypes.byref(ws), ctypes.byref(fe),
                                       ctypes.byref(pe))
     return code, ws.value, fe.value, pe.value
+
+
+def test_fused_batch_validation():
+    with open(HEADER) as fh:
+        nx_max = int(re.search(r"#define LBM_FUSED_MAX_NX (\d+)", fh.read()).group(1))
+    f64, f32, f16 = (lbm.STORAGES[k] for k in ("f64", "f32", "f16"))
+    assert _batch_layout(fused=1, storage=f16)[0] == lbm.LBM_OK
+    assert _batch_layout(fused=1, storage=f32)[0] == lbm.LBM_OK
+    assert _batch_layout(fused=1, storage=f64)[0] == lbm.LBM_ERR_ARG
+    assert _batch_layout(fused=1, lattice="D3Q19")[0] == lbm.LBM_ERR_ARG
+    assert _batch_layout(fused=2)[0] == lbm.LBM_ERR_ARG
+    assert _batch_layout(fused=1, shape=(2, nx_max))[0] == lbm.LBM_OK
+    assert _batch_layout(fused=1, shape=(2, nx_max + 1))[0] == lbm.LBM_ERR_ARG
+    assert _batch_layout(fused=0, shape=(2, nx_max + 1))[0] == lbm.LBM_OK
 
 
 def test_batch_layout_counts_and_validation():

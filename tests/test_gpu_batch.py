@@ -72,6 +72,50 @@ def test_each_box_matches_oracle(collision, forcing):
         assert e1 < 1e-12 and e8 < 1e-12, (i, e1, e8)
 
 
+def _fused_boxes():
+    """Ragged D2Q9 boxes for the fused step: 1 to 4 components, sides from 1 to 70
+    cells (several boxes are smaller than one tile plus its psi halo, so the halo
+    wraps around them more than once; one box is a single row), three porous."""
+    from cases import case
+    from oracle import lbm as olbm
+    specs = [(1, (2, 3), 1, False), (2, (3, 70), 2, False), (3, (17, 12), 3, True), (4, (24, 33), 4, False),
+             (2, (33, 41), 5, True), (3, (1, 67), 6, False), (4, (12, 12), 7, True), (1, (70, 9), 8, False)]
+    boxes = []
+    for nc, shape, seed, por in specs:
+        c = case("D2Q9", nc, shape, seed=seed)
+        bx = {"mix": c["mix"], "shape": shape, "T": c["T"], "tau": 0.8 + 0.05 * (seed % 3), "beta": 1.16,
+              "gamma": c["gamma"], "rho0": c["rho0"]}
+        if por:
+            m = to_mixture(c["mix"])
+            corner = c["rho0"][:, 0, 0]
+            bx["solid"] = np.random.default_rng([9, seed]).uniform(size=shape) < 0.15
+            bx["psi_wall"] = 1.3 * float(olbm.pseudo_potential(corner[:, None], c["T"], m, -1.0)[0])
+        boxes.append(bx)
+    return boxes
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("collision,forcing", [("bgk", "edm"), ("bgk", "guo"), ("mrt", "edm"), ("mrt", "guo")])
+def test_fused_step_equals_two_launches(storage, collision, forcing):
+    """The fused step (psi of each tile and its halo in LDS, one launch) leaves every
+    box's populations bit for bit where the psi pass + collide pass leave them, for
+    every tile size, a small persistent grid and graph replay."""
+    print(f"case batch fused {storage} {collision}+{forcing}", flush=True)
+    boxes = _fused_boxes()
+    rates = inputs.default_mrt_rates("D2Q9", 0.8) if collision == "mrt" else None
+    for kw in (dict(tile=64), dict(tile=256), dict(tile=128, grid=8), dict(tile=256, graph_steps=4)):
+        out = []
+        for fused in (False, True):
+            b = batch(boxes, collision=collision, forcing=forcing, storage=storage, mrt_s=rates, fused=fused, **kw)
+            b.step(3)
+            b.step(4)
+            out.append([x.cpu().numpy() for x in b.fields(populations=True)[1]])
+            b.check()
+            b.close()
+        for i, (a, c) in enumerate(zip(*out)):
+            assert np.array_equal(a, c), (kw, i, float(np.max(np.abs(a - c))))
+
+
 def test_tiles_grid_and_graph_are_bitwise_identical():
     print("case batch tiles/grid/graph", flush=True)
     boxes = make_boxes(9, 2)
