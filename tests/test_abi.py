@@ -195,3 +195,33 @@ def test_batch_box_planes_past_4gib_refused():
     assert _batch_layout(nboxes=1, nc=4, shape=shape, storage=lbm.STORAGES["f64"])[0] == lbm.LBM_OK
     assert _batch_layout(nboxes=1, nc=4, shape=shape, storage=lbm.STORAGES["f16"])[0] == lbm.LBM_OK
     assert _batch_layout(nboxes=1, nc=4, shape=shape, storage=lbm.STORAGES["f32"])[0] == lbm.LBM_ERR_ARG
+
+
+def test_python_structs_match_the_c_header(tmp_path):
+    """Every ctypes mirror of an lbm.h struct has the C struct's size and field
+    offsets (compiled with the host C compiler against the header)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = {"lbm_mixture": lbm.LbmMixture, "lbm_params": lbm.LbmParams, "lbm_flash_result": lbm.LbmFlashResult,
+             "lbm_box": lbm.LbmBox, "lbm_batch_params": lbm.LbmBatchParams}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lbm.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
