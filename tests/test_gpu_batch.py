@@ -99,15 +99,18 @@ def _fused_boxes():
 def test_fused_step_equals_two_launches(storage, collision, forcing):
     """The fused step (psi of each tile and its halo in LDS, one launch) leaves every
     box's populations bit for bit where the psi pass + collide pass leave them, for
-    every tile size, a small persistent grid and graph replay."""
+    every tile size, a small persistent grid and graph replay, also across a change
+    of one box's volatility coefficients between steps."""
     print(f"case batch fused {storage} {collision}+{forcing}", flush=True)
     boxes = _fused_boxes()
     rates = inputs.default_mrt_rates("D2Q9", 0.8) if collision == "mrt" else None
+    gam3 = np.clip(np.asarray(boxes[3]["gamma"]) * 0.97, 1e-3, 1.0)
     for kw in (dict(tile=64), dict(tile=256), dict(tile=128, grid=8), dict(tile=256, graph_steps=4)):
         out = []
         for fused in (False, True):
             b = batch(boxes, collision=collision, forcing=forcing, storage=storage, mrt_s=rates, fused=fused, **kw)
             b.step(3)
+            b.set_gamma(3, gam3)
             b.step(4)
             out.append([x.cpu().numpy() for x in b.fields(populations=True)[1]])
             b.check()
