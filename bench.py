@@ -111,7 +111,7 @@ def fugacities(lbm, mix, T, n_l, n_v):
     return fl, fv, float(np.sum((fl / fv - 1.0) ** 2)), 0.5 * float(f["p"][0] + f["p"][1])
 
 
-def copy_bandwidth(torch, lbm, nbytes=2 << 30, reps=5, grids=(1024, 2048, 4096, 8192)):
+def copy_bandwidth(torch, lbm, nbytes=2 << 30, reps=5, grids=(2048, 4096, 8192, 16384, 32768)):
     """Measured HBM ceiling: the library's streaming copy (16-byte non-temporal loads
     and stores, every byte read once and written once) of nbytes, timed with HIP
     events over `reps` copies for each workgroup count; GB/s = 2 nbytes / time.
